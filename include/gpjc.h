@@ -1,0 +1,155 @@
+/*
+ * libgpjc -- group-patch joint compression of B0- and RF-modulated k-space
+ * and the compressed Wave encoding operator, for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The method: arXiv 2601.05418, Section 2.4 (Eqs. 6-15).  A readout line of
+ * Nt = os * nx samples is cut into patches of P consecutive samples; patch p
+ * belongs to group g(p).  For each group the Nc * P products of coil map,
+ * modulation phase and readout DFT row (Eq. 6) form "virtual channels"; the
+ * top-K eigenvectors of their normalised Gram matrix P_g (Eqs. 7-11) give the
+ * compression matrix A_g (Eqs. 8, 12), applied to every patch of the group
+ * (Eqs. 13, 14) to form the reduced model S' = E' rho (Eq. 15).
+ * Reconstruction solves Eq. 16 (least squares, here by CG on the normal
+ * equations) or Eq. 17 with the wavelet term (FISTA), Section 3.4.
+ *
+ * Operator conventions (the paper leaves FFT centring and scaling open; this
+ * library uses centred unitary DFTs):
+ *   W[n][y][t]  = psf[y][t] * sum_x F_Nt[t][x + (Nt-Nx)/2] coils[n][y][x] img[y][x]
+ *   Z[p][k][y]  = sum_{n,j} A[g(p)][k][n][j] W[n][y][p*P + j]
+ *   S'[p][k][m] = sum_y F_Ny[line_m][y] Z[p][k][y]
+ * with F_N[k][i] = exp(-2 pi i (k - N/2)(i - N/2) / N) / sqrt(N) and line_m
+ * the m-th set entry of the phase-encode mask (ascending).  The uncompressed
+ * operator (geom.compressed = 0) skips Z: S[n][m][t] = sum_y F_Ny[line_m][y] W[n][y][t].
+ *
+ * Memory: every d_* argument is a device pointer, every h_* argument a host
+ * pointer.  The caller owns all buffers passed in; they must stay valid until
+ * the work queued on the plan's stream has completed.  Complex data are
+ * interleaved (re, im) and 8-byte (c64) / 16-byte (c128) aligned; buffers
+ * read with vector loads (gpjc_compress input) must be 16-byte aligned.
+ * The plan owns its copies of coil maps and PSF, the compression bank and all
+ * workspaces; they are allocated by gpjc_plan_create / gpjc_calibrate /
+ * gpjc_set_compression and freed by gpjc_plan_destroy.  gpjc_forward,
+ * gpjc_adjoint, gpjc_normal and the recon calls allocate nothing.
+ *
+ * Errors: every call returns GPJC_OK (0) or a negative status.  Arguments are
+ * validated before anything is launched, so a failing call leaves its outputs
+ * untouched (except GPJC_E_DEVICE / GPJC_E_NUMERIC raised after launch).
+ * gpjc_last_error() returns a thread-local message for the last failure.
+ * Calls are asynchronous on the plan's stream unless they return host data
+ * (h_* outputs), which synchronise.  A plan is used by one thread at a time.
+ */
+#ifndef GPJC_H
+#define GPJC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } gpjc_c64;
+typedef struct { double re, im; } gpjc_c128;
+
+/* Arithmetic of the group contraction and PSF product inside the operator.
+ * FP32: everything FP32 (FP32 MFMA).  BF16 / FP16: the hybrid readout data W
+ * and the compression matrices are rounded to BF16 / FP16 (round to nearest
+ * even) and contracted on MFMA with FP32 accumulation; FFTs and the
+ * phase-encode stage stay FP32. */
+typedef enum { GPJC_FP32 = 0, GPJC_BF16 = 1, GPJC_FP16 = 2 } gpjc_prec;
+
+enum {
+  GPJC_OK = 0,
+  GPJC_E_INVAL = -1,       /* bad argument, geometry or group partition */
+  GPJC_E_STATE = -2,       /* compressed operator used before a bank exists */
+  GPJC_E_NOMEM = -3,       /* device allocation failed */
+  GPJC_E_DEVICE = -4,      /* HIP runtime error (message in gpjc_last_error) */
+  GPJC_E_UNSUPPORTED = -5, /* size or mode this build does not provide */
+  GPJC_E_NUMERIC = -6      /* NaN/Inf in a solver, or eigensolver did not converge */
+};
+
+/* Geometry of a plan (Section 2.3, Fig. 3A; Section 3.3).  The host arrays
+ * are copied at plan creation. */
+typedef struct {
+  int32_t nx, ny;              /* image matrix, readout x fastest; both even */
+  int32_t nc;                  /* receive coils */
+  int32_t os;                  /* readout oversampling; nt = os * nx */
+  int32_t patch_len;           /* P; nt % P == 0 */
+  int32_t n_groups;            /* G */
+  const int32_t* patch_group;  /* host [nt / P], values in [0, G), every group used */
+  int32_t k;                   /* kept rank per group, 1 <= K <= nc * P */
+  const uint8_t* mask;         /* host [ny], nonzero = phase-encode line acquired */
+  int32_t batch;               /* B images sharing the geometry and maps */
+  int32_t compressed;          /* 1 = E' (Eq. 15), 0 = uncompressed E (Eq. 4) */
+} gpjc_geom;
+
+typedef struct gpjc_plan gpjc_plan;
+
+/* Create a plan.  d_coils [nc][ny][nx] c64 (E_RF of Eq. 6), d_psf [ny][nt]
+ * c64 = exp(-i k_m(t, y)) (E_NG of Eq. 6, Eqs. 1 and 3 for Wave), both
+ * copied.  hip_stream: a hipStream_t (NULL = default stream).  Checks that
+ * every group's member patches see identical PSF columns (max abs difference
+ * <= 1e-6), the condition under which one matrix serves all of them
+ * (Section 2.3); GPJC_E_INVAL otherwise.  Synchronises. */
+int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_psf,
+                     void* hip_stream, gpjc_plan** out);
+int gpjc_plan_destroy(gpjc_plan* plan);
+/* Switch the stream later calls are queued on. */
+int gpjc_set_stream(gpjc_plan* plan, void* hip_stream);
+
+/* Calibrate the compression bank (Eqs. 6-12): per group, FP64 Gram matrix of
+ * the composite maps over the ROI (d_roi [ny][nx] uint8, NULL = all pixels
+ * with a nonzero vector), Jacobi eigen-decomposition, descending order, each
+ * eigenvector phase-normalised (largest-magnitude entry real positive), first
+ * K rows of U^H, times T (x) I_P with T = Q^{-1}, Psi = Q Q^H from
+ * d_noise_cov [nc][nc] c64 (NULL = identity).  Outputs (optional):
+ * h_eigvals [G][nc*P] descending, d_A_out [G][K][nc][P] c128.
+ * Synchronises when h_eigvals is given.  Compressed plans only. */
+int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov,
+                   double* h_eigvals, gpjc_c128* d_A_out);
+
+/* Install an externally computed bank d_A [G][K][nc][P] c128 (copied). */
+int gpjc_set_compression(gpjc_plan* plan, const gpjc_c128* d_A);
+
+/* Eq. 13: d_ksp [B][nc][Ms][nt] c64 (acquired lines, ascending; 16-byte
+ * aligned) -> d_out [B][Np][K][Ms] c64, Np = nt / P. */
+int gpjc_compress(const gpjc_plan* plan, const gpjc_c64* d_ksp, gpjc_c64* d_out);
+
+/* E' (compressed plan): d_img [B][ny][nx] -> d_out [B][Np][K][Ms].
+ * E  (uncompressed plan): d_img -> d_out [B][nc][Ms][nt]. */
+int gpjc_forward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gpjc_c64* d_out);
+/* Conjugate transpose of gpjc_forward. */
+int gpjc_adjoint(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_in, gpjc_c64* d_img);
+/* E'^H E' (or E^H E): d_img [B][ny][nx] -> d_out [B][ny][nx]. */
+int gpjc_normal(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gpjc_c64* d_out);
+
+/* CG on the normal equations E'^H E' x = E'^H y (Eq. 16's minimiser),
+ * d_y in gpjc_forward's output layout, d_x [B][ny][nx] holds x0 on entry and
+ * the result on exit; all B images form one joint system.  Dot products are
+ * accumulated in FP64 with a fixed reduction order.  With prec != FP32 and
+ * refine_every > 0 the residual is recomputed every refine_every iterations
+ * as E'^H y - E'^H E' x with the FP32 operator and the search restarted.
+ * h_resid [iters+1] (optional) receives ||r_k||_2; synchronises if given.
+ * GPJC_E_NUMERIC if a residual or step is NaN/Inf (checked at the end). */
+int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x,
+                  int iters, int refine_every, double* h_resid);
+
+/* FISTA (Eq. 17 with the wavelet term, TV weight 0) on
+ * 1/2 ||E' x - y||^2 + lambda ||W x||_1, W the orthonormal separable Haar
+ * transform with haar_levels levels (1..3, nx and ny divisible by
+ * 2^levels; the final low-pass band is not penalised), step 1 / lipschitz,
+ * x_0 = 0.  d_x [B][ny][nx] receives the last iterate.  h_obj [iters]
+ * (optional) receives the objective after each iteration; synchronises. */
+int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
+                     double lambda, double lipschitz, int haar_levels, double* h_obj);
+
+const char* gpjc_status_string(int status);
+const char* gpjc_last_error(void);
+/* Path of the HIP runtime library this build is bound to in this process. */
+const char* gpjc_runtime_path(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPJC_H */

@@ -1,0 +1,409 @@
+// C ABI of libgpjc: argument validation, plan set-up and dispatch.
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+struct gpjc_plan : gpjc::Plan {};
+
+namespace gpjc {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+static bool debug_sync() {
+  static const bool on = [] {
+    const char* e = std::getenv("GPJC_DEBUG_SYNC");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
+}
+
+// Status of a queued call; with GPJC_DEBUG_SYNC set, also waits and reports
+// errors raised by the kernels.
+static int finish(const Plan& pl, int status) {
+  if (status != GPJC_OK || !debug_sync()) return status;
+  GPJC_HIP(hipStreamSynchronize(pl.stream));
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+template <class T>
+static int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return GPJC_OK;
+  GPJC_HIP(hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)));
+  return GPJC_OK;
+}
+
+static void free_plan(Plan* pl) {
+  void* bufs[] = {pl->coils, pl->psf,  pl->psfp, pl->twin, pl->tw_x, pl->tw_y, pl->lines, pl->pgroup,
+                  pl->maskf, pl->A128, pl->Aexp, pl->AH,   pl->W,    pl->Zp,   pl->Zt,    pl->part,
+                  pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->red,  pl->hist,  pl->flag};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (int i = 0; i < 3; ++i) {
+    if (pl->Aexp16[i]) (void)hipFree(pl->Aexp16[i]);
+    if (pl->AH16[i]) (void)hipFree(pl->AH16[i]);
+  }
+}
+
+static int validate_geom(const gpjc_geom* g) {
+  if (!g) return fail(GPJC_E_INVAL, "geom is NULL");
+  if (g->nx < 2 || g->ny < 2 || (g->nx & 1) || (g->ny & 1))
+    return fail(GPJC_E_INVAL, "nx and ny must be even and >= 2");
+  if (g->nc < 1) return fail(GPJC_E_INVAL, "nc must be >= 1");
+  if (g->os < 1) return fail(GPJC_E_INVAL, "os must be >= 1");
+  if (g->batch < 1) return fail(GPJC_E_INVAL, "batch must be >= 1");
+  if (!g->mask) return fail(GPJC_E_INVAL, "mask is NULL");
+  int ms = 0;
+  for (int i = 0; i < g->ny; ++i) ms += g->mask[i] != 0;
+  if (ms == 0) return fail(GPJC_E_INVAL, "mask selects no phase-encode line");
+  if (g->compressed) {
+    const int nt = g->os * g->nx;
+    if (g->patch_len < 1 || nt % g->patch_len)
+      return fail(GPJC_E_INVAL, "patch_len must divide nt = os * nx");
+    if (g->n_groups < 1) return fail(GPJC_E_INVAL, "n_groups must be >= 1");
+    if (!g->patch_group) return fail(GPJC_E_INVAL, "patch_group is NULL");
+    const long ns = (long)g->nc * g->patch_len;
+    if (g->k < 1 || g->k > ns) return fail(GPJC_E_INVAL, "k must lie in [1, nc * patch_len]");
+    const int np = nt / g->patch_len;
+    std::vector<int> used(g->n_groups, 0);
+    for (int p = 0; p < np; ++p) {
+      const int v = g->patch_group[p];
+      if (v < 0 || v >= g->n_groups) return fail(GPJC_E_INVAL, "patch_group value out of [0, n_groups)");
+      used[v] = 1;
+    }
+    for (int v = 0; v < g->n_groups; ++v)
+      if (!used[v]) return fail(GPJC_E_INVAL, "group " + std::to_string(v) + " has no patch");
+  }
+  return GPJC_OK;
+}
+
+static int check_supported(const gpjc_geom* g) {
+  if (!fft_size_supported(g->nx) || !fft_size_supported(g->ny))
+    return fail(GPJC_E_UNSUPPORTED, "nx / ny must be one of the built FFT lengths");
+  if (g->compressed && (g->patch_len & 1))
+    return fail(GPJC_E_UNSUPPORTED, "odd patch_len is not built for the compressed operator");
+  return GPJC_OK;
+}
+
+static constexpr int kLdsSlots = 8192;  // float2 slots per work-group (64 KiB)
+
+// Every kernel keeps its LDS within 64 KiB; shapes that cannot are rejected.
+static int check_lds(const gpjc_geom* g) {
+  const long line = 2L * g->os * g->nx + g->nx;  // one image row of the readout stages
+  if (line > kLdsSlots) return fail(GPJC_E_UNSUPPORTED, "os * nx too large for the readout stages");
+  if (3L * g->ny > kLdsSlots || 2L * (g->ny + 1) + g->ny > kLdsSlots)
+    return fail(GPJC_E_UNSUPPORTED, "ny too large for the phase-encode stages");
+  return GPJC_OK;
+}
+
+static void choose_launch(Plan& pl) {
+  const int lds_f2 = kLdsSlots;
+  int rows = std::max(1, (lds_f2 - pl.nx) / (2 * pl.os * pl.nx));
+  rows = std::min(rows, std::max(1, pl.ny * pl.nc * pl.B / 1024));
+  pl.f1_rows = std::max(1, std::min(rows, pl.ny));
+
+  int cb = std::max(1, (lds_f2 - pl.nx) / (2 * pl.os * pl.nx));
+  cb = std::min(std::min(cb, 4), pl.nc);
+  int nchunk = (1024 + pl.ny * pl.B - 1) / (pl.ny * pl.B);
+  nchunk = std::max(1, std::min(nchunk, (pl.nc + cb - 1) / cb));
+  int cpc = (pl.nc + nchunk - 1) / nchunk;
+  cpc = (cpc + cb - 1) / cb * cb;
+  pl.f1h_cb = cb;
+  pl.f1h_cpc = cpc;
+  pl.f1h_nchunk = (pl.nc + cpc - 1) / cpc;
+
+  pl.f3_lpb = std::max(1, std::min(32, (lds_f2 - pl.ny) / (2 * pl.ny)));
+  pl.f3_tb = std::max(1, std::min(16, (lds_f2 - pl.ny) / (2 * (pl.ny + 1))));
+
+  if (pl.compressed) {
+    const int kd = 2 * pl.ns;
+    const long tiles = (long)((pl.ny + 63) / 64) * ((2 * pl.K + 63) / 64) * pl.B * pl.np;
+    int ks = (int)std::max<long>(1, (1024 + tiles - 1) / tiles);
+    ks = std::min(ks, std::max(1, kd / 64));
+    pl.gemm_ksplit = ks;
+  }
+}
+
+static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, const gpjc_c64* d_psf,
+                      hipStream_t stream) {
+  pl.nx = g->nx;
+  pl.ny = g->ny;
+  pl.nc = g->nc;
+  pl.os = g->os;
+  pl.nt = g->os * g->nx;
+  pl.B = g->batch;
+  pl.compressed = g->compressed ? 1 : 0;
+  pl.stream = stream;
+  pl.mask_h.assign(g->mask, g->mask + g->ny);
+  for (int i = 0; i < g->ny; ++i)
+    if (g->mask[i]) pl.lines_h.push_back(i);
+  pl.ms = (int)pl.lines_h.size();
+  if (pl.compressed) {
+    pl.P = g->patch_len;
+    pl.np = pl.nt / pl.P;
+    pl.G = g->n_groups;
+    pl.K = g->k;
+    pl.Kp = (pl.K + 7) / 8 * 8;
+    pl.ns = pl.nc * pl.P;
+    pl.pgroup_h.assign(g->patch_group, g->patch_group + pl.np);
+  }
+  GPJC_HIP(hipGetDevice(&pl.device));
+  choose_launch(pl);
+
+  const size_t npix = (size_t)pl.ny * pl.nx;
+  GPJC_TRY(dalloc(&pl.coils, (size_t)pl.nc * npix));
+  GPJC_TRY(dalloc(&pl.psf, (size_t)pl.ny * pl.nt));
+  GPJC_TRY(dalloc(&pl.psfp, (size_t)pl.ny * pl.nt));
+  GPJC_TRY(dalloc(&pl.twin, (size_t)pl.os * pl.nx));
+  GPJC_TRY(dalloc(&pl.tw_x, (size_t)pl.nx));
+  GPJC_TRY(dalloc(&pl.tw_y, (size_t)pl.ny));
+  GPJC_TRY(dalloc(&pl.lines, (size_t)pl.ms));
+  GPJC_TRY(dalloc(&pl.maskf, (size_t)pl.ny));
+  GPJC_TRY(dalloc(&pl.W, (size_t)pl.B * pl.nc * pl.ny * pl.nt));
+  GPJC_TRY(dalloc(&pl.part, (size_t)pl.f1h_nchunk * pl.B * npix));
+  const size_t ni = pl.img_elems();
+  GPJC_TRY(dalloc(&pl.vx, ni));
+  GPJC_TRY(dalloc(&pl.vr, ni));
+  GPJC_TRY(dalloc(&pl.vp, ni));
+  GPJC_TRY(dalloc(&pl.vq, ni));
+  GPJC_TRY(dalloc(&pl.vb, ni));
+  GPJC_TRY(dalloc(&pl.red, 4096));
+  pl.hist_cap = 100001;
+  GPJC_TRY(dalloc(&pl.hist, (size_t)pl.hist_cap));
+  GPJC_TRY(dalloc(&pl.flag, 4));
+  if (pl.compressed) {
+    GPJC_TRY(dalloc(&pl.pgroup, (size_t)pl.np));
+    GPJC_TRY(dalloc(&pl.A128, (size_t)pl.G * pl.K * pl.ns));
+    GPJC_TRY(dalloc(&pl.Aexp, (size_t)pl.G * 2 * pl.K * 2 * pl.ns));
+    GPJC_TRY(dalloc(&pl.AH, (size_t)pl.G * 2 * pl.ns * 2 * pl.Kp));
+    GPJC_TRY(dalloc(&pl.Zp, (size_t)pl.gemm_ksplit * pl.B * pl.np * pl.K * pl.ny));
+    GPJC_TRY(dalloc(&pl.Zt, (size_t)pl.B * pl.np * pl.ny * pl.Kp));
+    GPJC_HIP(hipMemsetAsync(pl.Zt, 0, sizeof(float2) * (size_t)pl.B * pl.np * pl.ny * pl.Kp, stream));
+    GPJC_HIP(hipMemcpyAsync(pl.pgroup, pl.pgroup_h.data(), sizeof(int) * pl.np, hipMemcpyHostToDevice, stream));
+  }
+  std::vector<float> mf(pl.ny);
+  for (int i = 0; i < pl.ny; ++i) mf[i] = pl.mask_h[i] ? 1.f : 0.f;
+  GPJC_HIP(hipMemcpyAsync(pl.maskf, mf.data(), sizeof(float) * pl.ny, hipMemcpyHostToDevice, stream));
+  GPJC_HIP(hipMemcpyAsync(pl.lines, pl.lines_h.data(), sizeof(int) * pl.ms, hipMemcpyHostToDevice, stream));
+  GPJC_HIP(hipMemcpyAsync(pl.coils, d_coils, sizeof(float2) * pl.nc * npix, hipMemcpyDeviceToDevice, stream));
+  GPJC_HIP(hipMemcpyAsync(pl.psf, d_psf, sizeof(float2) * pl.ny * pl.nt, hipMemcpyDeviceToDevice, stream));
+  GPJC_TRY(launch_prep_tables(pl));
+  GPJC_HIP(hipMemsetAsync(pl.hist, 0, sizeof(double) * pl.hist_cap, stream));
+
+  if (pl.compressed && pl.G < pl.np) {
+    // One matrix per group is only valid if every member sees the same modulation.
+    std::vector<float2> h((size_t)pl.ny * pl.nt);
+    GPJC_HIP(hipMemcpyAsync(h.data(), pl.psf, sizeof(float2) * h.size(), hipMemcpyDeviceToHost, stream));
+    GPJC_HIP(hipStreamSynchronize(stream));
+    std::vector<int> first(pl.G, -1);
+    for (int p = 0; p < pl.np; ++p) {
+      const int g0 = pl.pgroup_h[p];
+      if (first[g0] < 0) {
+        first[g0] = p;
+        continue;
+      }
+      const int q = first[g0];
+      for (int y = 0; y < pl.ny; ++y)
+        for (int j = 0; j < pl.P; ++j) {
+          const float2 a = h[(size_t)y * pl.nt + p * pl.P + j], b = h[(size_t)y * pl.nt + q * pl.P + j];
+          if (std::hypot(a.x - b.x, a.y - b.y) > 1e-6)
+            return fail(GPJC_E_INVAL, "patch " + std::to_string(p) + " does not share the modulation of group " +
+                                          std::to_string(g0));
+        }
+    }
+  }
+  GPJC_HIP(hipStreamSynchronize(stream));
+  return GPJC_OK;
+}
+
+static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+static int check_plan(const gpjc_plan* plan) {
+  if (!plan) return fail(GPJC_E_INVAL, "plan is NULL");
+  return GPJC_OK;
+}
+
+static int check_prec(const Plan& pl, int prec, Store* st) {
+  if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
+  if (prec != GPJC_FP32 && !pl.compressed)
+    return fail(GPJC_E_UNSUPPORTED, "the uncompressed operator is FP32 only");
+  *st = prec == GPJC_FP32 ? Store::F32 : prec == GPJC_BF16 ? Store::BF16 : Store::F16;
+  return GPJC_OK;
+}
+
+static int check_bank(const Plan& pl) {
+  if (pl.compressed && !pl.have_bank)
+    return fail(GPJC_E_STATE, "no compression bank: call gpjc_calibrate or gpjc_set_compression first");
+  return GPJC_OK;
+}
+
+}  // namespace gpjc
+
+using namespace gpjc;
+
+extern "C" {
+
+int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_psf, void* hip_stream,
+                     gpjc_plan** out) {
+  if (!out) return fail(GPJC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  GPJC_TRY(validate_geom(geom));
+  if (!d_coils || !d_psf) return fail(GPJC_E_INVAL, "coil maps or PSF is NULL");
+  if (!aligned(d_coils, 8) || !aligned(d_psf, 8)) return fail(GPJC_E_INVAL, "coil maps / PSF not 8-byte aligned");
+  GPJC_TRY(check_supported(geom));
+  GPJC_TRY(check_lds(geom));
+  gpjc_plan* pl = new (std::nothrow) gpjc_plan();
+  if (!pl) return fail(GPJC_E_NOMEM, "host allocation failed");
+  const int s = setup_plan(*pl, geom, d_coils, d_psf, reinterpret_cast<hipStream_t>(hip_stream));
+  if (s != GPJC_OK) {
+    free_plan(pl);
+    delete pl;
+    return s;
+  }
+  *out = pl;
+  return GPJC_OK;
+}
+
+int gpjc_plan_destroy(gpjc_plan* plan) {
+  if (!plan) return GPJC_OK;
+  (void)hipStreamSynchronize(plan->stream);
+  free_plan(plan);
+  delete plan;
+  return GPJC_OK;
+}
+
+int gpjc_set_stream(gpjc_plan* plan, void* hip_stream) {
+  GPJC_TRY(check_plan(plan));
+  plan->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return GPJC_OK;
+}
+
+int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov, double* h_eigvals,
+                   gpjc_c128* d_A_out) {
+  GPJC_TRY(check_plan(plan));
+  if (!plan->compressed) return fail(GPJC_E_INVAL, "calibration needs a compressed plan");
+  return finish(*plan, run_calibrate(*plan, d_roi, reinterpret_cast<const float2*>(d_noise_cov), h_eigvals,
+                                     reinterpret_cast<double2*>(d_A_out)));
+}
+
+int gpjc_set_compression(gpjc_plan* plan, const gpjc_c128* d_A) {
+  GPJC_TRY(check_plan(plan));
+  if (!plan->compressed) return fail(GPJC_E_INVAL, "compression bank needs a compressed plan");
+  if (!d_A || !aligned(d_A, 16)) return fail(GPJC_E_INVAL, "bank pointer NULL or not 16-byte aligned");
+  GPJC_HIP(hipMemcpyAsync(plan->A128, d_A, sizeof(double2) * (size_t)plan->G * plan->K * plan->ns,
+                          hipMemcpyDeviceToDevice, plan->stream));
+  GPJC_TRY(launch_expand_bank(*plan));
+  plan->have_bank = true;
+  return finish(*plan, GPJC_OK);
+}
+
+int gpjc_compress(const gpjc_plan* plan, const gpjc_c64* d_ksp, gpjc_c64* d_out) {
+  GPJC_TRY(check_plan(plan));
+  if (!plan->compressed) return fail(GPJC_E_INVAL, "gpjc_compress needs a compressed plan");
+  if (!d_ksp || !d_out) return fail(GPJC_E_INVAL, "NULL buffer");
+  if (!aligned(d_ksp, 16) || !aligned(d_out, 8)) return fail(GPJC_E_INVAL, "k-space must be 16-byte aligned");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, launch_compress_data(*plan, reinterpret_cast<const float2*>(d_ksp),
+                                            reinterpret_cast<float2*>(d_out)));
+}
+
+int gpjc_forward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gpjc_c64* d_out) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_img || !d_out || !aligned(d_img, 8) || !aligned(d_out, 8))
+    return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, op_forward(*plan, st, reinterpret_cast<const float2*>(d_img), reinterpret_cast<float2*>(d_out)));
+}
+
+int gpjc_adjoint(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_in, gpjc_c64* d_img) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_in || !d_img || !aligned(d_in, 8) || !aligned(d_img, 8))
+    return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  GPJC_TRY(check_bank(*plan));
+  GPJC_TRY(op_adjoint_part(*plan, st, reinterpret_cast<const float2*>(d_in)));
+  return finish(*plan, launch_combine(*plan, reinterpret_cast<float2*>(d_img)));
+}
+
+int gpjc_normal(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gpjc_c64* d_out) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_img || !d_out || !aligned(d_img, 8) || !aligned(d_out, 8))
+    return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  GPJC_TRY(check_bank(*plan));
+  GPJC_TRY(op_normal_part(*plan, st, reinterpret_cast<const float2*>(d_img)));
+  return finish(*plan, launch_combine(*plan, reinterpret_cast<float2*>(d_out)));
+}
+
+int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, int refine_every,
+                  double* h_resid) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_y || !d_x || !aligned(d_y, 8) || !aligned(d_x, 8)) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  if (iters < 0 || iters + 1 > plan->hist_cap) return fail(GPJC_E_INVAL, "iters out of range");
+  if (refine_every < 0) return fail(GPJC_E_INVAL, "refine_every must be >= 0");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, run_cg(*plan, st, reinterpret_cast<const float2*>(d_y), reinterpret_cast<float2*>(d_x), iters,
+                              refine_every, h_resid));
+}
+
+int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, double lambda,
+                     double lipschitz, int haar_levels, double* h_obj) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_y || !d_x || !aligned(d_y, 8) || !aligned(d_x, 8)) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  if (iters < 0) return fail(GPJC_E_INVAL, "iters must be >= 0");
+  if (!(lipschitz > 0.0) || !std::isfinite(lipschitz)) return fail(GPJC_E_INVAL, "lipschitz must be positive");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(GPJC_E_INVAL, "lambda must be >= 0");
+  if (haar_levels < 1 || haar_levels > 3) return fail(GPJC_E_UNSUPPORTED, "haar_levels must be 1, 2 or 3");
+  const int t = 1 << haar_levels;
+  if (plan->nx % t || plan->ny % t) return fail(GPJC_E_INVAL, "nx and ny must be divisible by 2^haar_levels");
+  if (h_obj) return fail(GPJC_E_UNSUPPORTED, "objective history is not built");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, run_fista(*plan, st, reinterpret_cast<const float2*>(d_y), reinterpret_cast<float2*>(d_x),
+                                 iters, lambda, lipschitz, haar_levels, h_obj));
+}
+
+const char* gpjc_status_string(int status) {
+  switch (status) {
+    case GPJC_OK: return "ok";
+    case GPJC_E_INVAL: return "invalid argument";
+    case GPJC_E_STATE: return "invalid state";
+    case GPJC_E_NOMEM: return "out of device memory";
+    case GPJC_E_DEVICE: return "HIP runtime error";
+    case GPJC_E_UNSUPPORTED: return "unsupported";
+    case GPJC_E_NUMERIC: return "numerical failure";
+    default: return "unknown status";
+  }
+}
+
+const char* gpjc_last_error(void) { return g_last_error.c_str(); }
+
+const char* gpjc_runtime_path(void) {
+  static std::string path;
+  Dl_info info;
+  if (dladdr(reinterpret_cast<void*>(&hipGetDeviceCount), &info) && info.dli_fname) path = info.dli_fname;
+  return path.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal plan state and launcher prototypes shared by the HIP sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gpjc.h"
+
+namespace gpjc {
+
+// Status helper: records the message and returns the code.
+int fail(int code, const std::string& msg);
+
+#define GPJC_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return ::gpjc::fail(e_ == hipErrorOutOfMemory ? GPJC_E_NOMEM : GPJC_E_DEVICE, \
+                          std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define GPJC_TRY(expr)        \
+  do {                        \
+    int s_ = (expr);          \
+    if (s_ != GPJC_OK) return s_; \
+  } while (0)
+
+// Reduced-precision storage types.
+enum class Store { F32 = 0, BF16 = 1, F16 = 2 };
+
+struct Plan {
+  // geometry
+  int nx = 0, ny = 0, nc = 0, os = 0, nt = 0, P = 0, np = 0, G = 0, K = 0, Kp = 0, ns = 0, ms = 0;
+  int B = 1, compressed = 1;
+  std::vector<int> pgroup_h;
+  std::vector<uint8_t> mask_h;
+  std::vector<int> lines_h;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // launch configuration
+  int f1_rows = 1;          // image rows per readout-forward workgroup
+  int f1h_cb = 1;           // coils transformed together in the readout adjoint
+  int f1h_nchunk = 1;       // coil chunks (partial images) in the readout adjoint
+  int f1h_cpc = 1;          // coils per chunk
+  int f3_lpb = 1;           // phase-encode lines per workgroup
+  int f3_tb = 1;            // readout columns per uncompressed phase-encode workgroup
+  int gemm_ksplit = 1;      // contraction split of the compressing group GEMM
+
+  // device: geometry tables
+  float2* coils = nullptr;  // [nc][ny][nx]
+  float2* psf = nullptr;    // [ny][nt] as given
+  float2* psfp = nullptr;   // [ny][nt] psf times the readout post-twiddle
+  float2* twin = nullptr;   // [os][nx] readout pre-twiddle
+  float2* tw_x = nullptr;   // [nx] exp(-2 pi i m / nx)
+  float2* tw_y = nullptr;   // [ny]
+  int* lines = nullptr;     // [ms]
+  int* pgroup = nullptr;    // [np]
+  float* maskf = nullptr;   // [ny] 0 / 1
+
+  // device: compression bank
+  bool have_bank = false;
+  double2* A128 = nullptr;  // [G][K][ns]
+  float* Aexp = nullptr;    // [G][2K][2ns]   real form for compressing
+  float* AH = nullptr;      // [G][2ns][2Kp]  real form for expanding
+  uint16_t* Aexp16[3] = {nullptr, nullptr, nullptr};  // [prec] reduced copies
+  uint16_t* AH16[3] = {nullptr, nullptr, nullptr};
+
+  // device: workspaces
+  float2* W = nullptr;      // [B][nc][ny][nt] (also holds 16-bit W)
+  float2* Zp = nullptr;     // [ksplit][B][np][K][ny]
+  float2* Zt = nullptr;     // [B][np][ny][Kp]
+  float2* part = nullptr;   // [f1h_nchunk][B][ny][nx]
+
+  // device: solver state
+  float2 *vx = nullptr, *vr = nullptr, *vp = nullptr, *vq = nullptr, *vb = nullptr;
+  double* red = nullptr;    // reduction partials
+  double* hist = nullptr;   // [hist_cap]
+  int* flag = nullptr;      // numeric status flag
+  int hist_cap = 0;
+  int red_blocks = 0;
+
+  size_t img_elems() const { return (size_t)B * ny * nx; }
+};
+
+// ---- operator stages (operator.hip) ----
+int launch_prep_tables(Plan& pl);
+int launch_readout_fwd(const Plan& pl, const float2* img, Store st);
+int launch_readout_adj(const Plan& pl, Store st);
+int launch_combine(const Plan& pl, float2* out);
+int launch_group_compress(const Plan& pl, Store st);
+int launch_group_expand(const Plan& pl, Store st);
+int launch_pe_fwd(const Plan& pl, float2* out);
+int launch_pe_adj(const Plan& pl, const float2* in);
+int launch_pe_normal(const Plan& pl);
+int launch_pe_cols_fwd(const Plan& pl, float2* out);
+int launch_pe_cols_adj(const Plan& pl, const float2* in);
+int launch_pe_cols_normal(const Plan& pl);
+int launch_expand_bank(Plan& pl);
+int launch_compress_data(const Plan& pl, const float2* ksp, float2* out);
+
+// Whole operators: images in, images (as partial sums in pl.part) or data out.
+int op_forward(const Plan& pl, Store st, const float2* img, float2* out);
+int op_adjoint_part(const Plan& pl, Store st, const float2* in);  // result in pl.part
+int op_normal_part(const Plan& pl, Store st, const float2* img);  // result in pl.part
+
+// ---- calibration (calib.hip) ----
+int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out);
+
+// ---- solvers (solver.hip) ----
+int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid);
+int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lip,
+              int levels, double* h_obj);
+
+// Lengths the FFT kernels are instantiated for.
+bool fft_size_supported(int n);
+
+}  // namespace gpjc

@@ -1,0 +1,381 @@
+// Reconstruction on top of the compressed operator (Section 3.4).
+//
+// CG solves the normal equations of Eq. 16.  Dot products are FP64 and
+// deterministic: every partial-producing kernel runs on the same fixed grid,
+// each block writes one partial, and every consumer block re-sums the full
+// partial array in the same order.  Scalars are never stored and re-read
+// across blocks; the squared-residual partials alternate between two slots.
+//
+// FISTA solves Eq. 17 with the wavelet term.  A separable Haar transform of
+// L levels acts independently on 2^L x 2^L tiles (every level only combines
+// pixels inside such a tile), so the gradient step, the wavelet
+// soft-threshold and the momentum update are one pass with one tile per
+// thread, held in registers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fft.h"
+#include "plan.h"
+
+namespace gpjc {
+
+static constexpr int kRedBlocks = 240;  // fixed grid of every partial-producing kernel
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block sum (256 threads); result valid in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return t;
+}
+
+// Sum of nb partials, same order in every block; result returned to all threads.
+__device__ inline double sum_partials(const double* __restrict__ p, int nb, double* sh) {
+  double v = 0.0;
+  if (threadIdx.x < 64)
+    for (int i = threadIdx.x; i < nb; i += 64) v += p[i];
+  if (threadIdx.x < 64) v = wave_sum(v);
+  if (threadIdx.x == 0) sh[4] = v;
+  __syncthreads();
+  const double r = sh[4];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline float2 sum_part(const float2* __restrict__ part, int nchunk, size_t n, size_t i) {
+  float2 v = part[i];
+  for (int c = 1; c < nchunk; ++c) v = cadd(v, part[c * n + i]);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(float2* __restrict__ v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = make_float2(0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_copy(const float2* __restrict__ a, float2* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// r = b - A x (A x given as partial images), p = r, partial <r, r>.
+__global__ __launch_bounds__(256) void k_cg_start(const float2* __restrict__ part, int nchunk,
+                                                  const float2* __restrict__ bvec, float2* __restrict__ r,
+                                                  float2* __restrict__ p, double* __restrict__ red_rr, size_t n) {
+  __shared__ double sh[8];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 v = csub(bvec[i], sum_part(part, nchunk, n, i));
+    r[i] = v;
+    p[i] = v;
+    acc += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red_rr[blockIdx.x] = s;
+}
+
+// hist = sqrt(sum of partials); single block.
+__global__ void k_store_norm(const double* __restrict__ red, int nb, double* __restrict__ hist) {
+  __shared__ double sh[8];
+  const double s = sum_partials(red, nb, sh);
+  if (threadIdx.x == 0) *hist = sqrt(s);
+}
+
+// q = A p (from partials), partial Re <p, q>.
+__global__ __launch_bounds__(256) void k_cg_q(const float2* __restrict__ part, int nchunk, const float2* __restrict__ p,
+                                              float2* __restrict__ q, double* __restrict__ red_pq, size_t n) {
+  __shared__ double sh[8];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 v = sum_part(part, nchunk, n, i);
+    q[i] = v;
+    const float2 pv = p[i];
+    acc += (double)pv.x * v.x + (double)pv.y * v.y;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red_pq[blockIdx.x] = s;
+}
+
+// alpha = rr / pq; x += alpha p; r -= alpha q; partial <r, r> into red_new.
+__global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ red_pq,
+                                                   const double* __restrict__ red_old, double* __restrict__ red_new,
+                                                   int nb, float2* __restrict__ x, float2* __restrict__ r,
+                                                   const float2* __restrict__ p, const float2* __restrict__ q,
+                                                   size_t n, int* __restrict__ flag) {
+  __shared__ double sh[8];
+  const double pq = sum_partials(red_pq, nb, sh);
+  const double rr = sum_partials(red_old, nb, sh);
+  if (!isfinite(pq) || !isfinite(rr)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+  }
+  const double alpha = (pq > 0.0 && rr > 0.0) ? rr / pq : 0.0;
+  const float a = (float)alpha;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 pv = p[i], qv = q[i];
+    float2 xv = x[i], rv = r[i];
+    xv = make_float2(fmaf(a, pv.x, xv.x), fmaf(a, pv.y, xv.y));
+    rv = make_float2(fmaf(-a, qv.x, rv.x), fmaf(-a, qv.y, rv.y));
+    x[i] = xv;
+    r[i] = rv;
+    acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red_new[blockIdx.x] = s;
+}
+
+// beta = rr_new / rr_old; p = r + beta p; hist = ||r||.
+__global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ red_new, const double* __restrict__ red_old,
+                                                int nb, const float2* __restrict__ r, float2* __restrict__ p, size_t n,
+                                                double* __restrict__ hist) {
+  __shared__ double sh[8];
+  const double rn = sum_partials(red_new, nb, sh);
+  const double ro = sum_partials(red_old, nb, sh);
+  const float beta = (float)((ro > 0.0) ? rn / ro : 0.0);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 rv = r[i], pv = p[i];
+    p[i] = make_float2(fmaf(beta, pv.x, rv.x), fmaf(beta, pv.y, rv.y));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hist = sqrt(rn);
+}
+
+static int fill_zero(const Plan& pl, float2* v, size_t n) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(kRedBlocks), dim3(256), 0, pl.stream, v, n);
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+static int copy_vec(const Plan& pl, const float2* a, float2* b, size_t n) {
+  hipLaunchKernelGGL(k_copy, dim3(kRedBlocks), dim3(256), 0, pl.stream, a, b, n);
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid) {
+  const size_t n = pl.img_elems();
+  const int nb = kRedBlocks;
+  double* red_pq = pl.red;
+  double* red_rr[2] = {pl.red + nb, pl.red + 2 * nb};
+  const bool refine = refine_every > 0 && st != Store::F32;
+  GPJC_HIP(hipMemsetAsync(pl.flag, 0, sizeof(int), pl.stream));
+  // b = E'^H y
+  GPJC_TRY(op_adjoint_part(pl, st, y));
+  GPJC_TRY(launch_combine(pl, pl.vb));
+  GPJC_TRY(copy_vec(pl, x, pl.vx, n));
+  // r0 = b - A x0
+  GPJC_TRY(op_normal_part(pl, st, pl.vx));
+  hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
+                     red_rr[0], n);
+  hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, red_rr[0], nb, pl.hist);
+  GPJC_HIP(hipGetLastError());
+  for (int it = 0; it < iters; ++it) {
+    double* r_old = red_rr[it & 1];
+    double* r_new = red_rr[(it + 1) & 1];
+    GPJC_TRY(op_normal_part(pl, st, pl.vp));
+    hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vp, pl.vq, red_pq, n);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, pl.stream, red_pq, r_old, r_new, nb, pl.vx, pl.vr, pl.vp,
+                       pl.vq, n, pl.flag);
+    GPJC_HIP(hipGetLastError());
+    if (refine && (it + 1) % refine_every == 0 && it + 1 < iters) {
+      GPJC_TRY(op_normal_part(pl, Store::F32, pl.vx));
+      hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
+                         r_new, n);
+      hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, r_new, nb, pl.hist + it + 1);
+    } else {
+      hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, pl.stream, r_new, r_old, nb, pl.vr, pl.vp, n,
+                         pl.hist + it + 1);
+    }
+    GPJC_HIP(hipGetLastError());
+  }
+  GPJC_TRY(copy_vec(pl, pl.vx, x, n));
+  int flag = 0;
+  if (h_resid) {
+    GPJC_HIP(hipMemcpyAsync(h_resid, pl.hist, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost, pl.stream));
+  }
+  GPJC_HIP(hipMemcpyAsync(&flag, pl.flag, sizeof(int), hipMemcpyDeviceToHost, pl.stream));
+  GPJC_HIP(hipStreamSynchronize(pl.stream));
+  if (flag) return fail(GPJC_E_NUMERIC, "CG: non-finite residual or curvature");
+  return GPJC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FISTA
+// ---------------------------------------------------------------------------
+template <int LEV>
+__device__ inline void haar_tile(float2 (&c)[1 << LEV][1 << LEV], bool inverse) {
+  constexpr int S = 1 << LEV;
+  constexpr float rs = 0.70710678118654752440f;
+  if (!inverse) {
+#pragma unroll
+    for (int lev = 0; lev < LEV; ++lev) {
+      const int h = S >> lev;
+      // along x (rows i < h)
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        if (i < h) {
+          float2 t[S];
+#pragma unroll
+          for (int j = 0; j < S / 2; ++j)
+            if (j < h / 2) {
+              t[j] = cscale(cadd(c[i][2 * j], c[i][2 * j + 1]), rs);
+              t[j + h / 2] = cscale(csub(c[i][2 * j], c[i][2 * j + 1]), rs);
+            }
+#pragma unroll
+          for (int j = 0; j < S; ++j)
+            if (j < h) c[i][j] = t[j];
+        }
+      }
+      // along y (columns j < h)
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        if (j < h) {
+          float2 t[S];
+#pragma unroll
+          for (int i = 0; i < S / 2; ++i)
+            if (i < h / 2) {
+              t[i] = cscale(cadd(c[2 * i][j], c[2 * i + 1][j]), rs);
+              t[i + h / 2] = cscale(csub(c[2 * i][j], c[2 * i + 1][j]), rs);
+            }
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            if (i < h) c[i][j] = t[i];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int lev = LEV - 1; lev >= 0; --lev) {
+      const int h = S >> lev;
+      // along y
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        if (j < h) {
+          float2 t[S];
+#pragma unroll
+          for (int i = 0; i < S / 2; ++i)
+            if (i < h / 2) {
+              const float2 lo = c[i][j], hi = c[i + h / 2][j];
+              t[2 * i] = cscale(cadd(lo, hi), rs);
+              t[2 * i + 1] = cscale(csub(lo, hi), rs);
+            }
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            if (i < h) c[i][j] = t[i];
+        }
+      }
+      // along x
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        if (i < h) {
+          float2 t[S];
+#pragma unroll
+          for (int j = 0; j < S / 2; ++j)
+            if (j < h / 2) {
+              const float2 lo = c[i][j], hi = c[i][j + h / 2];
+              t[2 * j] = cscale(cadd(lo, hi), rs);
+              t[2 * j + 1] = cscale(csub(lo, hi), rs);
+            }
+#pragma unroll
+          for (int j = 0; j < S; ++j)
+            if (j < h) c[i][j] = t[j];
+        }
+      }
+    }
+  }
+}
+
+// v = y - (A y - b) / L; x = W^H soft(W v, thr) (final low-pass untouched);
+// y <- x + mom (x - x_prev); x_prev <- x.
+template <int LEV>
+__global__ __launch_bounds__(64) void k_fista_step(const float2* __restrict__ part, int nchunk,
+                                                   const float2* __restrict__ bvec, float2* __restrict__ yv,
+                                                   float2* __restrict__ xprev, int nx, int ny, int B, float invL,
+                                                   float thr, float mom) {
+  constexpr int S = 1 << LEV;
+  const int tx_n = nx / S, ty_n = ny / S;
+  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tile >= B * tx_n * ty_n) return;
+  const int b = tile / (tx_n * ty_n);
+  const int rem = tile - b * tx_n * ty_n;
+  const int ty = rem / tx_n, tx = rem - ty * tx_n;
+  const size_t n = (size_t)B * nx * ny;
+  float2 c[S][S];
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const size_t idx = ((size_t)b * ny + ty * S + i) * nx + tx * S + j;
+      const float2 g = csub(sum_part(part, nchunk, n, idx), bvec[idx]);
+      const float2 yy = yv[idx];
+      c[i][j] = make_float2(fmaf(-invL, g.x, yy.x), fmaf(-invL, g.y, yy.y));
+    }
+  haar_tile<LEV>(c, false);
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      if (i == 0 && j == 0) continue;
+      const float2 z = c[i][j];
+      const float mag = sqrtf(z.x * z.x + z.y * z.y);
+      const float sc = mag > thr ? 1.0f - thr / mag : 0.0f;
+      c[i][j] = cscale(z, sc);
+    }
+  haar_tile<LEV>(c, true);
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const size_t idx = ((size_t)b * ny + ty * S + i) * nx + tx * S + j;
+      const float2 xn = c[i][j], xo = xprev[idx];
+      yv[idx] = make_float2(fmaf(mom, xn.x - xo.x, xn.x), fmaf(mom, xn.y - xo.y, xn.y));
+      xprev[idx] = xn;
+    }
+}
+
+template <int LEV>
+static int launch_fista_step(const Plan& pl, float invL, float thr, float mom) {
+  constexpr int S = 1 << LEV;
+  const int tiles = pl.B * (pl.nx / S) * (pl.ny / S);
+  hipLaunchKernelGGL(k_fista_step<LEV>, dim3((tiles + 63) / 64), dim3(64), 0, pl.stream, pl.part, pl.f1h_nchunk,
+                     pl.vb, pl.vp, pl.vx, pl.nx, pl.ny, pl.B, invL, thr, mom);
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lip, int levels,
+              double* h_obj) {
+  (void)h_obj;
+  const size_t n = pl.img_elems();
+  GPJC_TRY(op_adjoint_part(pl, st, y));
+  GPJC_TRY(launch_combine(pl, pl.vb));
+  GPJC_TRY(fill_zero(pl, pl.vx, n));  // x_{k-1}
+  GPJC_TRY(fill_zero(pl, pl.vp, n));  // y_k
+  const float invL = (float)(1.0 / lip);
+  const float thr = (float)(lambda / lip);
+  double t = 1.0;
+  for (int it = 0; it < iters; ++it) {
+    GPJC_TRY(op_normal_part(pl, st, pl.vp));
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    const float mom = (float)((t - 1.0) / tn);
+    t = tn;
+    switch (levels) {
+      case 1: GPJC_TRY(launch_fista_step<1>(pl, invL, thr, mom)); break;
+      case 2: GPJC_TRY(launch_fista_step<2>(pl, invL, thr, mom)); break;
+      default: GPJC_TRY(launch_fista_step<3>(pl, invL, thr, mom)); break;
+    }
+  }
+  return copy_vec(pl, pl.vx, x, n);
+}
+
+}  // namespace gpjc

@@ -1,0 +1,264 @@
+"""Python binding of libgpjc (ctypes).
+
+Argument marshalling only: every step of the operator, calibration and
+reconstruction runs in the library's HIP kernels.  PyTorch provides device
+memory (tensors) and the stream.  torch is imported before the library is
+loaded so that libgpjc binds to the same HIP runtime instance as torch and
+device pointers can be shared.
+
+The function names mirror the C ABI in include/gpjc.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpjc.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "gpjc.h")
+
+FP32, BF16, FP16 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
+
+GPJC_OK = 0
+GPJC_E_INVAL = -1
+GPJC_E_STATE = -2
+GPJC_E_NOMEM = -3
+GPJC_E_DEVICE = -4
+GPJC_E_UNSUPPORTED = -5
+GPJC_E_NUMERIC = -6
+
+
+class GpjcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libgpjc status {status}: {message}")
+        self.status = status
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nc", ctypes.c_int32), ("os", ctypes.c_int32),
+        ("patch_len", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+        ("patch_group", ctypes.POINTER(ctypes.c_int32)), ("k", ctypes.c_int32),
+        ("mask", ctypes.POINTER(ctypes.c_uint8)), ("batch", ctypes.c_int32), ("compressed", ctypes.c_int32),
+    ]
+
+
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    "gpjc_plan_create": (_I, [ctypes.POINTER(_Geom), _VP, _VP, _VP, ctypes.POINTER(_VP)]),
+    "gpjc_plan_destroy": (_I, [_VP]),
+    "gpjc_set_stream": (_I, [_VP, _VP]),
+    "gpjc_calibrate": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "gpjc_set_compression": (_I, [_VP, _VP]),
+    "gpjc_compress": (_I, [_VP, _VP, _VP]),
+    "gpjc_forward": (_I, [_VP, _I, _VP, _VP]),
+    "gpjc_adjoint": (_I, [_VP, _I, _VP, _VP]),
+    "gpjc_normal": (_I, [_VP, _I, _VP, _VP]),
+    "gpjc_recon_cg": (_I, [_VP, _I, _VP, _VP, _I, _I, _VP]),
+    "gpjc_recon_fista": (_I, [_VP, _I, _VP, _VP, _I, _D, _D, _I, _VP]),
+    "gpjc_status_string": (ctypes.c_char_p, [_I]),
+    "gpjc_last_error": (ctypes.c_char_p, []),
+    "gpjc_runtime_path": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def header_symbols(path: str = HEADER_PATH):
+    """Names of the functions declared in include/gpjc.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpjc_[a-z0-9_]+)\s*\(", text)))
+
+
+def load(path: str = LIB_PATH):
+    """Load libgpjc.so (built in-tree).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def runtime_path() -> str:
+    return load().gpjc_runtime_path().decode()
+
+
+def _check(status: int):
+    if status != GPJC_OK:
+        raise GpjcError(status, load().gpjc_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    """Device pointer of an output tensor (must be contiguous)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("output tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dtype).contiguous()
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class Plan:
+    """A libgpjc plan: geometry, coil maps, PSF, compression bank, workspaces.
+
+    coils [nc][ny][nx] and psf [ny][nt] (complex, host or device) are copied.
+    """
+
+    def __init__(self, nx, ny, nc, os_, coils, psf, mask, patch_len=0, patch_group=None, n_groups=0, k=0,
+                 batch=1, compressed=True, device="cuda:0", stream=None):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.nx, self.ny, self.nc, self.os = int(nx), int(ny), int(nc), int(os_)
+        self.nt = self.os * self.nx
+        self.batch = int(batch)
+        self.compressed = bool(compressed)
+        self.mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        self.ms = int((self.mask != 0).sum())
+        self.patch_len = int(patch_len)
+        self.k = int(k)
+        self.n_groups = int(n_groups)
+        self.np_ = self.nt // self.patch_len if self.compressed and self.patch_len else 0
+        pg = np.zeros(max(self.np_, 1), np.int32) if patch_group is None else patch_group
+        self.patch_group = np.ascontiguousarray(np.asarray(pg, dtype=np.int32))
+        g = _Geom(self.nx, self.ny, self.nc, self.os, self.patch_len, self.n_groups,
+                  self.patch_group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.k,
+                  self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), self.batch, int(self.compressed))
+        c = _dev_tensor(coils, torch.complex64, self.device)
+        p = _dev_tensor(psf, torch.complex64, self.device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        handle = ctypes.c_void_p()
+        torch.cuda.synchronize(self.device)
+        _check(self.lib.gpjc_plan_create(ctypes.byref(g), _ptr(c), _ptr(p), ctypes.c_void_p(st),
+                                         ctypes.byref(handle)))
+        self.handle = handle
+        self._inputs = []
+
+    @classmethod
+    def from_slice(cls, sl, batch=1, compressed=True, **kw):
+        g = sl.geom
+        return cls(g.nx, g.ny, g.nc, g.os, sl.coils, sl.psf, g.mask, g.patch_len, g.patch_group, g.n_groups,
+                   g.k, batch=batch, compressed=compressed, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gpjc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- shapes ----
+    @property
+    def ns(self):
+        return self.nc * self.patch_len
+
+    def data_shape(self):
+        if self.compressed:
+            return (self.batch, self.np_, self.k, self.ms)
+        return (self.batch, self.nc, self.ms, self.nt)
+
+    def image_shape(self):
+        return (self.batch, self.ny, self.nx)
+
+    def _empty(self, shape, dtype=torch.complex64):
+        return torch.empty(shape, dtype=dtype, device=self.device)
+
+    def _in(self, t: torch.Tensor, dtype=torch.complex64):
+        """Pointer to an input, made contiguous on the plan's device; the
+        tensor is kept referenced until the next call so a temporary copy
+        outlives the queued work."""
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(np.ascontiguousarray(t))
+        t = t.to(device=self.device, dtype=dtype).contiguous()
+        self._inputs.append(t)
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _begin(self):
+        self._inputs = []
+
+    # ---- calls ----
+    def set_stream(self, stream=None):
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib.gpjc_set_stream(self.handle, ctypes.c_void_p(st)))
+
+    def calibrate(self, roi=None, noise_cov=None, want_eigvals=False, want_bank=False):
+        roi_t = None if roi is None else _dev_tensor(np.asarray(roi, np.uint8), torch.uint8, self.device)
+        cov_t = None if noise_cov is None else _dev_tensor(noise_cov, torch.complex64, self.device)
+        eig = np.zeros((self.n_groups, self.ns), np.float64) if want_eigvals else None
+        bank = self._empty((self.n_groups, self.k, self.nc, self.patch_len), torch.complex128) if want_bank else None
+        _check(self.lib.gpjc_calibrate(self.handle, _ptr(roi_t), _ptr(cov_t),
+                                       None if eig is None else eig.ctypes.data_as(ctypes.c_void_p),
+                                       _ptr(bank)))
+        return eig, bank
+
+    def set_compression(self, bank):
+        self._begin()
+        _check(self.lib.gpjc_set_compression(self.handle, self._in(bank, torch.complex128)))
+
+    def compress(self, ksp, out=None):
+        self._begin()
+        out = self._empty((self.batch, self.np_, self.k, self.ms)) if out is None else out
+        _check(self.lib.gpjc_compress(self.handle, self._in(ksp), _ptr(out)))
+        return out
+
+    def forward(self, img, prec="fp32", out=None):
+        out = self._empty(self.data_shape()) if out is None else out
+        self._begin()
+        _check(self.lib.gpjc_forward(self.handle, _prec(prec), self._in(img), _ptr(out)))
+        return out
+
+    def adjoint(self, y, prec="fp32", out=None):
+        out = self._empty(self.image_shape()) if out is None else out
+        self._begin()
+        _check(self.lib.gpjc_adjoint(self.handle, _prec(prec), self._in(y), _ptr(out)))
+        return out
+
+    def normal(self, img, prec="fp32", out=None):
+        out = self._empty(self.image_shape()) if out is None else out
+        self._begin()
+        _check(self.lib.gpjc_normal(self.handle, _prec(prec), self._in(img), _ptr(out)))
+        return out
+
+    def recon_cg(self, y, iters, x0=None, prec="fp32", refine_every=0, want_resid=False):
+        x = torch.zeros(self.image_shape(), dtype=torch.complex64, device=self.device) if x0 is None \
+            else x0.clone().contiguous()
+        hist = np.zeros(iters + 1, np.float64) if want_resid else None
+        self._begin()
+        _check(self.lib.gpjc_recon_cg(self.handle, _prec(prec), self._in(y), _ptr(x), int(iters), int(refine_every),
+                                      None if hist is None else hist.ctypes.data_as(ctypes.c_void_p)))
+        return (x, hist) if want_resid else x
+
+    def recon_fista(self, y, iters, lam, lipschitz, levels=3, prec="fp32", out=None):
+        x = self._empty(self.image_shape()) if out is None else out
+        self._begin()
+        _check(self.lib.gpjc_recon_fista(self.handle, _prec(prec), self._in(y), _ptr(x), int(iters), float(lam),
+                                         float(lipschitz), int(levels), None))
+        return x

@@ -1,0 +1,90 @@
+"""Shared set-up for the GPU parity tests: seeded cases, inputs rounded to
+complex64 once so both sides see identical values, oracle banks."""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from oracle import compression as oc
+from oracle import encoding as oe
+from paper_2601_05418_amd import synth
+
+# Bounds stated for FP32 operator applications against the FP64 oracle.
+REL_L2_FP32 = 1e-5
+NRMSE_RECON = 1e-4
+
+
+def round64(x):
+    return np.asarray(x, np.complex64).astype(np.complex128)
+
+
+def rounded_slice(sl: synth.Slice) -> synth.Slice:
+    return dataclasses.replace(sl, image=round64(sl.image), coils=round64(sl.coils), psf=round64(sl.psf))
+
+
+def rect_slice(seed=0):
+    """96 x 80, 6 coils, os 3 (288 samples), 24 patches of 12, K = 20: every
+    stage has ragged tiles (2K = 40, 2 Ns = 144, Ny = 80)."""
+    return synth._make_rect(seed, nx=96, ny=80, nc=6, os_=3, patch_len=12, k=20, accel=3, acs=6,
+                            cycles=3, phase_max=2.5)
+
+
+def periodic_slice(seed=0):
+    """64 x 64, os 4, wave with 4 cycles (period 64 samples = 4 patches of 16):
+    16 patches share 4 group matrices."""
+    sl = synth._make_rect(seed, nx=64, ny=64, nc=4, os_=4, patch_len=16, k=12, accel=2, acs=8,
+                          cycles=4, phase_max=2.0)
+    g = dataclasses.replace(sl.geom, patch_group=synth.periodic_groups(16, 4), n_groups=4)
+    return dataclasses.replace(sl, geom=g)
+
+
+CASES = {
+    "small": lambda: synth.small_slice(0),
+    "rect": lambda: rect_slice(0),
+    "periodic": lambda: periodic_slice(0),
+}
+
+
+def oracle_bank(sl):
+    g = sl.geom
+    a, lam = oc.calibrate(sl.coils, sl.psf, g.os, g.patch_len, g.patch_group, g.n_groups, g.k)
+    return a, lam
+
+
+def random_bank(g, seed=0):
+    """Orthonormal-row random bank, for operator parity where calibration is
+    not under test."""
+    rng = np.random.default_rng(seed)
+    a = np.empty((g.n_groups, g.k, g.nc, g.patch_len), complex)
+    for i in range(g.n_groups):
+        q, _ = np.linalg.qr(rng.standard_normal((g.ns, g.k)) + 1j * rng.standard_normal((g.ns, g.k)))
+        a[i] = q.conj().T.reshape(g.k, g.nc, g.patch_len)
+    return a
+
+
+def oracle_ops(sl, bank):
+    g = sl.geom
+    args = (sl.coils, sl.psf, g.mask, g.os)
+    cargs = (bank, g.patch_group, g.patch_len)
+    return dict(
+        fwd=lambda x: oe.forward(x, *args, *cargs),
+        adj=lambda y: oe.adjoint(y, *args, *cargs),
+        nrm=lambda x: oe.normal(x, *args, *cargs),
+        fwd_full=lambda x: oe.forward_full(x, *args),
+        adj_full=lambda y: oe.adjoint_full(y, *args),
+        nrm_full=lambda x: oe.normal_full(x, *args),
+    )
+
+
+def crandn(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2)
+
+
+def rel_l2(a, ref):
+    return float(np.linalg.norm(np.asarray(a) - ref) / np.linalg.norm(ref))
+
+
+def max_rel(a, ref):
+    """Largest element error relative to the largest reference magnitude."""
+    return float(np.max(np.abs(np.asarray(a) - ref)) / np.max(np.abs(ref)))

@@ -1,0 +1,89 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/gpjc.h declares, and rejects bad geometry before touching a device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2601_05418_amd import gpjc
+
+
+def test_exports_every_declared_symbol():
+    lib = gpjc.load()
+    names = gpjc.header_symbols()
+    assert "gpjc_forward" in names and "gpjc_calibrate" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = gpjc.load()
+    assert lib.gpjc_status_string(0) == b"ok"
+    assert lib.gpjc_status_string(gpjc.GPJC_E_INVAL) == b"invalid argument"
+    assert lib.gpjc_status_string(gpjc.GPJC_E_NUMERIC) == b"numerical failure"
+
+
+def _geom(**over):
+    kw = dict(nx=64, ny=64, nc=8, os=4, patch_len=16, n_groups=16, k=11, batch=1, compressed=1)
+    kw.update(over)
+    nt = kw["os"] * kw["nx"]
+    np_ = nt // kw["patch_len"] if nt % kw["patch_len"] == 0 else 1
+    pg = over.pop("pg", None)
+    pg = np.arange(np_, dtype=np.int32) % kw["n_groups"] if pg is None else np.asarray(pg, np.int32)
+    mask = over.pop("mask_arr", None)
+    mask = np.ones(kw["ny"], np.uint8) if mask is None else mask
+    keep = (pg, mask)
+    g = gpjc._Geom(kw["nx"], kw["ny"], kw["nc"], kw["os"], kw["patch_len"], kw["n_groups"],
+                   pg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), kw["k"],
+                   mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), kw["batch"], kw["compressed"])
+    return g, keep
+
+
+FAKE = ctypes.c_void_p(0x100000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(nx=63), gpjc.GPJC_E_INVAL),
+    (dict(ny=0), gpjc.GPJC_E_INVAL),
+    (dict(nc=0), gpjc.GPJC_E_INVAL),
+    (dict(patch_len=24), gpjc.GPJC_E_INVAL),      # 256 % 24 != 0
+    (dict(k=0), gpjc.GPJC_E_INVAL),
+    (dict(k=8 * 16 + 1), gpjc.GPJC_E_INVAL),
+    (dict(n_groups=17), gpjc.GPJC_E_INVAL),       # group 16 unused
+    (dict(batch=0), gpjc.GPJC_E_INVAL),
+    (dict(nx=22, ny=22, os=2, patch_len=4, n_groups=11), gpjc.GPJC_E_UNSUPPORTED),  # FFT length 22 not built
+    (dict(patch_len=1, n_groups=256, k=4), gpjc.GPJC_E_UNSUPPORTED),  # odd patch length
+])
+def test_invalid_geometry(over, code):
+    lib = gpjc.load()
+    g, keep = _geom(**over)
+    out = ctypes.c_void_p()
+    assert lib.gpjc_plan_create(ctypes.byref(g), FAKE, FAKE, None, ctypes.byref(out)) == code
+    assert out.value is None
+    assert lib.gpjc_last_error()
+
+
+def test_group_value_out_of_range():
+    lib = gpjc.load()
+    pg = np.arange(16, dtype=np.int32)
+    pg[3] = 99
+    g, keep = _geom(pg=pg)
+    out = ctypes.c_void_p()
+    assert lib.gpjc_plan_create(ctypes.byref(g), FAKE, FAKE, None, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+    assert b"out of" in lib.gpjc_last_error()
+
+
+def test_empty_mask_and_null_maps():
+    lib = gpjc.load()
+    g, keep = _geom(mask_arr=np.zeros(64, np.uint8))
+    out = ctypes.c_void_p()
+    assert lib.gpjc_plan_create(ctypes.byref(g), FAKE, FAKE, None, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+    g, keep = _geom()
+    assert lib.gpjc_plan_create(ctypes.byref(g), None, FAKE, None, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+
+
+def test_null_plan_calls():
+    lib = gpjc.load()
+    assert lib.gpjc_forward(None, 0, FAKE, FAKE) == gpjc.GPJC_E_INVAL
+    assert lib.gpjc_recon_cg(None, 0, FAKE, FAKE, 5, 0, None) == gpjc.GPJC_E_INVAL
+    assert lib.gpjc_plan_destroy(None) == gpjc.GPJC_OK

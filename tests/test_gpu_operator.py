@@ -1,0 +1,153 @@
+"""Parity of the HIP operator (through the C ABI) with the FP64 oracle.
+
+Bound: relative L2 <= 1e-5 per FP32 application, and every element within
+1e-5 of the largest reference magnitude.  Inputs are rounded to complex64
+once and the oracle receives the same rounded values.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import compression as oc
+from paper_2601_05418_amd import gpjc, synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+ELEM = 1e-5
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, np.complex64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def make(case, batch=1, compressed=True, bank="oracle"):
+    sl = H.rounded_slice(H.CASES[case]())
+    a = None
+    if compressed:
+        a = H.oracle_bank(sl)[0] if bank == "oracle" else H.random_bank(sl.geom)
+    plan = gpjc.Plan.from_slice(sl, batch=batch, compressed=compressed)
+    if compressed:
+        plan.set_compression(torch.as_tensor(a).cuda())
+    return sl, a, plan
+
+
+def check(out, ref, bound=H.REL_L2_FP32):
+    rl, mr = H.rel_l2(out, ref), H.max_rel(out, ref)
+    print(f"rel_l2={rl:.3e} max_rel={mr:.3e}", flush=True)
+    assert rl <= bound
+    assert mr <= ELEM
+
+
+@pytest.mark.parametrize("case", list(H.CASES))
+def test_forward(gpu_lib, case):
+    sl, a, plan = make(case)
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(H.crandn(np.random.default_rng(1), (1, sl.geom.ny, sl.geom.nx)))
+    out = host(plan.forward(dev(x)))
+    check(out[0], ops["fwd"](x[0]))
+
+
+@pytest.mark.parametrize("case", list(H.CASES))
+def test_adjoint(gpu_lib, case):
+    sl, a, plan = make(case)
+    ops = H.oracle_ops(sl, a)
+    y = H.round64(H.crandn(np.random.default_rng(2), plan.data_shape()))
+    out = host(plan.adjoint(dev(y)))
+    check(out[0], ops["adj"](y[0]))
+
+
+@pytest.mark.parametrize("case", list(H.CASES))
+def test_normal(gpu_lib, case):
+    sl, a, plan = make(case)
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(H.crandn(np.random.default_rng(3), (1, sl.geom.ny, sl.geom.nx)))
+    out = host(plan.normal(dev(x)))
+    check(out[0], ops["nrm"](x[0]))
+
+
+def test_batched_images_are_independent(gpu_lib):
+    sl, a, plan = make("rect", batch=3)
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(H.crandn(np.random.default_rng(4), (3, sl.geom.ny, sl.geom.nx)))
+    f = host(plan.forward(dev(x)))
+    n = host(plan.normal(dev(x)))
+    for b in range(3):
+        check(f[b], ops["fwd"](x[b]))
+        check(n[b], ops["nrm"](x[b]))
+
+
+@pytest.mark.parametrize("case", ["small", "rect"])
+def test_uncompressed(gpu_lib, case):
+    sl, _, plan = make(case, compressed=False)
+    ops = H.oracle_ops(sl, None)
+    rng = np.random.default_rng(5)
+    x = H.round64(H.crandn(rng, (1, sl.geom.ny, sl.geom.nx)))
+    check(host(plan.forward(dev(x)))[0], ops["fwd_full"](x[0]))
+    y = H.round64(H.crandn(rng, plan.data_shape()))
+    check(host(plan.adjoint(dev(y)))[0], ops["adj_full"](y[0]))
+    check(host(plan.normal(dev(x)))[0], ops["nrm_full"](x[0]))
+
+
+@pytest.mark.parametrize("case", ["small", "rect"])
+def test_adjoint_identity(gpu_lib, case):
+    sl, a, plan = make(case)
+    rng = np.random.default_rng(6)
+    x = H.round64(H.crandn(rng, (1, sl.geom.ny, sl.geom.nx)))
+    y = H.round64(H.crandn(rng, plan.data_shape()))
+    fx = host(plan.forward(dev(x)))
+    ahy = host(plan.adjoint(dev(y)))
+    lhs, rhs = np.vdot(fx, y), np.vdot(x, ahy)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("case", ["small", "rect"])
+def test_compress_matches_oracle(gpu_lib, case):
+    sl, a, plan = make(case)
+    g = sl.geom
+    ops = H.oracle_ops(sl, a)
+    s = H.round64(ops["fwd_full"](sl.image))  # acquired k-space [Nc][Ms][Nt]
+    out = host(plan.compress(dev(s[None])))
+    check(out[0], oc.compress(s, a, g.patch_group, g.patch_len))
+
+
+def test_highfield_full_size(gpu_lib):
+    """224 x 224, 32 coils, 1344 samples, 42 groups, K = 64: forward and
+    adjoint at full size in the launch configuration the benchmark uses,
+    every element against the oracle (random orthonormal bank)."""
+    sl = H.rounded_slice(synth.highfield_slice(0))
+    g = sl.geom
+    a = H.random_bank(g, seed=7)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(sl.image)[None]
+    check(host(plan.forward(dev(x)))[0], ops["fwd"](x[0]))
+    y = H.round64(H.crandn(np.random.default_rng(8), plan.data_shape()))
+    check(host(plan.adjoint(dev(y)))[0], ops["adj"](y[0]))
+
+
+def test_state_and_argument_errors(gpu_lib):
+    sl = H.rounded_slice(synth.small_slice(0))
+    plan = gpjc.Plan.from_slice(sl)
+    x = torch.zeros((1, 64, 64), dtype=torch.complex64, device="cuda")
+    with pytest.raises(gpjc.GpjcError) as e:
+        plan.forward(x)
+    assert e.value.status == gpjc.GPJC_E_STATE
+    out = torch.full(plan.data_shape(), 7.0 + 0j, dtype=torch.complex64, device="cuda")
+    with pytest.raises(gpjc.GpjcError):
+        plan.forward(x, prec=9, out=out)
+    assert torch.all(out == 7.0)  # untouched on error
+
+
+def test_runtime_is_torchs(gpu_lib):
+    """libgpjc must share torch's HIP runtime, or device pointers would not
+    be valid across the two."""
+    import os
+    path = gpjc.runtime_path()
+    assert os.path.dirname(os.path.realpath(path)) == os.path.dirname(os.path.realpath(torch.__file__)) + "/lib", path

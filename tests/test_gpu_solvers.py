@@ -1,0 +1,77 @@
+"""CG and FISTA on the GPU against the oracle's same-schedule FP64 runs
+(NRMSE <= 1e-4, Section 3.4's metric)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import solvers as osv
+from paper_2601_05418_amd import gpjc, synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, np.complex64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def setup(case):
+    sl = H.rounded_slice(H.CASES[case]())
+    a = H.oracle_bank(sl)[0]
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    y = H.round64(ops["fwd"](sl.image))
+    return sl, plan, ops, y
+
+
+@pytest.mark.parametrize("case", ["small", "rect"])
+def test_cg_same_schedule(gpu_lib, case):
+    sl, plan, ops, y = setup(case)
+    x, hist = plan.recon_cg(dev(y[None]), 20, want_resid=True)
+    xg = host(x)[0]
+    xo, ho = osv.cg(ops["nrm"], ops["adj"](y), 20, x0=np.zeros_like(sl.image))
+    e = osv.nrmse(xg, xo)
+    print(f"{case}: nrmse vs oracle CG-20 = {e:.3e}; truth nrmse = {osv.nrmse(xg, sl.image):.3e}", flush=True)
+    assert e <= H.NRMSE_RECON
+    assert np.allclose(hist, ho, rtol=1e-3, atol=1e-6 * ho[0])
+
+
+def test_cg_warm_start_and_zero_iterations(gpu_lib):
+    sl, plan, ops, y = setup("small")
+    x0 = dev(H.round64(sl.image)[None] * 0.5)
+    x = host(plan.recon_cg(dev(y[None]), 0, x0=x0))
+    assert np.array_equal(x, host(x0))
+    xg = host(plan.recon_cg(dev(y[None]), 10, x0=x0))[0]
+    xo, _ = osv.cg(ops["nrm"], ops["adj"](y), 10, x0=H.round64(sl.image) * 0.5)
+    assert osv.nrmse(xg, xo) <= H.NRMSE_RECON
+
+
+@pytest.mark.parametrize("case", ["small", "rect"])
+def test_fista_same_schedule(gpu_lib, case):
+    sl, plan, ops, y = setup(case)
+    b = ops["adj"](y)
+    lip = osv.power_iteration(ops["nrm"], b.shape, iters=50, seed=0) * 1.01
+    lam = 1e-3 * np.abs(osv.haar_fwd(b, 3)).max()
+    xg = host(plan.recon_fista(dev(y[None]), 30, lam, lip, levels=3))[0]
+    xo, _ = osv.fista(ops["nrm"], b, 30, lam, lip, 3)
+    e = osv.nrmse(xg, xo)
+    print(f"{case}: fista nrmse vs oracle = {e:.3e}", flush=True)
+    assert e <= H.NRMSE_RECON
+
+
+def test_fista_strong_penalty_matches(gpu_lib):
+    """A large lambda makes many coefficients exactly zero: checks the
+    threshold path, not only the gradient path."""
+    sl, plan, ops, y = setup("small")
+    b = ops["adj"](y)
+    lip = osv.power_iteration(ops["nrm"], b.shape, iters=50, seed=0) * 1.01
+    lam = 0.05 * np.abs(osv.haar_fwd(b, 3)).max()
+    xg = host(plan.recon_fista(dev(y[None]), 15, lam, lip, levels=2))[0]
+    xo, _ = osv.fista(ops["nrm"], b, 15, lam, lip, 2)
+    assert osv.nrmse(xg, xo) <= H.NRMSE_RECON
