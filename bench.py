@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the compressed Wave operator and reconstruction on one GPU.
+
+Workload: the 2D high-field slice -- 224 x 224 image, 32 coils with B1
+phase, readout oversampling 6 (1344 samples), Wave 7 cycles / +-6 rad, 42
+patches of 32 samples each its own group (1024 virtual channels), K = 64
+(16x joint compression), R = 4 with 16 calibration lines, noise at SNR 30.
+
+One step = one FISTA reconstruction of the slice (50 iterations, 3-level
+Haar, lambda = 1e-3 max|W E'^H S'|, step 1/L with L from 50 power
+iterations x 1.01): E'^H S' once, then 50 applications of E'^H E' and the
+fused gradient / wavelet-prox / momentum update.  value = E'^H E'
+applications per second over the timed steps (50 per step).  Calibration
+(Gram + eigen-decomposition) and compression of the acquired k-space are
+timed once, outside the steps.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "compressed E^H E applications/s and s/slice recon vs plain FP32, at <=1e-4 NRMSE"
+ITERS = 50
+LEVELS = 3
+
+PEAKS = {"hbm": 8.0e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def stage_work(g, stage, prec, ksplit_read=1):
+    """Algorithmic work of one launch of a stage: (bound, amount, unit)."""
+    B, nx, ny, nc, nt = 1, g.nx, g.ny, g.nc, g.nt
+    wbytes = 8 if prec == "fp32" else 4
+    if stage in ("group_compress", "group_expand"):
+        return "mfma", 8.0 * B * g.k * nc * nt * ny, "flop"
+    if stage in ("readout_fwd", "readout_adj"):
+        return "hbm", 8.0 * (B * nx * ny + nc * nx * ny + ny * nt) + wbytes * B * nc * ny * nt, "byte"
+    if stage == "pe_normal":
+        return "hbm", 16.0 * B * g.n_patches * g.k * ny, "byte"
+    if stage == "solver":
+        return "hbm", 10 * 8.0 * B * nx * ny, "byte"
+    return "hbm", 8.0 * B * nx * ny, "byte"
+
+
+def cpu_baseline(sl, budget_s):
+    """The oracle's E'^H E' on the host cores: as many applications as fit in
+    the time budget (at least one)."""
+    import numpy as np
+
+    from oracle import encoding as oe
+    g = sl.geom
+    rng = np.random.default_rng(0)
+    bank = np.empty((g.n_groups, g.k, g.nc, g.patch_len), complex)
+    for i in range(g.n_groups):
+        q, _ = np.linalg.qr(rng.standard_normal((g.ns, g.k)) + 1j * rng.standard_normal((g.ns, g.k)))
+        bank[i] = q.conj().T.reshape(g.k, g.nc, g.patch_len)
+    x = sl.image
+    n = 0
+    t0 = time.perf_counter()
+    c0 = os.times()
+    while True:
+        x = oe.normal(x, sl.coils, sl.psf, g.mask, g.os, bank, g.patch_group, g.patch_len)
+        x = x / np.linalg.norm(x)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    wall = time.perf_counter() - t0
+    c1 = os.times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    try:
+        import threadpoolctl
+        blas = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        blas = None
+    return {
+        "value": n / wall,
+        "unit": "E'^H E' applications/s",
+        "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": f"{n} FP64 NumPy applications of E'^H E' on the same 224x224 / 32-coil / 42-group slice "
+                  f"(random orthonormal bank), {wall:.1f} s wall; host affinity {len(os.sched_getaffinity(0))} "
+                  f"cores, BLAS threads {blas}, np.fft single-threaded",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--periodic", action="store_true", help="map the 42 patches onto the 6 of one wave period")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
+              "MI355X; the multi-GPU sharding is a design in the documentation only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2601_05418_amd import gpjc, synth
+
+    dev = torch.device("cuda:0")
+    sl = synth.highfield_slice(0, periodic=args.periodic)
+    g = sl.geom
+    log(f"workload: {g.nx}x{g.ny}, nc={g.nc}, nt={g.nt}, P={g.patch_len}, G={g.n_groups}, K={g.k}, Ms={g.ms}")
+
+    # acquired k-space: uncompressed operator on the GPU, then noise at SNR 30
+    full = gpjc.Plan.from_slice(sl, compressed=False)
+    img = torch.as_tensor(np.ascontiguousarray(sl.image[None], np.complex64)).to(dev)
+    s_h = full.forward(img).cpu().numpy().astype(np.complex128)
+    full.close()
+    noisy = s_h + synth.scaled_noise(s_h, sl.noise[None], sl.snr)
+    ksp = torch.as_tensor(np.ascontiguousarray(noisy, np.complex64)).to(dev)
+
+    plan = gpjc.Plan.from_slice(sl)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan.calibrate()
+    torch.cuda.synchronize()
+    t_cal = time.perf_counter() - t
+    log(f"calibrate: {t_cal:.3f} s")
+    y = plan.compress(ksp)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        plan.compress(ksp, out=y)
+    torch.cuda.synchronize()
+    t_comp = (time.perf_counter() - t) / 10
+
+    b = plan.adjoint(y, prec=args.prec)
+    lam = 1e-3 * plan.wavelet_absmax(b, LEVELS)
+    rng = np.random.default_rng(1)
+    x0 = torch.as_tensor(np.ascontiguousarray(synth.unit_noise((1, g.ny, g.nx), rng), np.complex64)).to(dev)
+    lip = plan.power_iteration(x0, 50, prec=args.prec) * 1.01
+    log(f"lambda {lam:.4e}, L {lip:.4e}")
+
+    x = torch.empty((1, g.ny, g.nx), dtype=torch.complex64, device=dev)
+    for i in range(args.warmup):
+        plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec=args.prec, out=x)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup}")
+    plan.stage_timing(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec=args.prec, out=x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    stages = plan.stage_times()
+    plan.stage_timing(False)
+    ms_per_step = 1e3 * dt / args.steps
+    value = ITERS * args.steps / dt
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms per slice, {value:.1f} E'^H E' per s")
+
+    # operator alone
+    out = torch.empty_like(x)
+    for _ in range(5):
+        plan.normal(x, prec=args.prec, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    nop = 100
+    for _ in range(nop):
+        plan.normal(x, prec=args.prec, out=out)
+    torch.cuda.synchronize()
+    op_rate = nop / (time.perf_counter() - t)
+
+    per_stage = {k: {"ms_per_launch": (v[0] / v[1] if v[1] else 0.0), "launches": v[1], "ms_total": v[0]}
+                 for k, v in stages.items() if v[1]}
+    dom = max(per_stage, key=lambda k: per_stage[k]["ms_total"])
+    bound, work, kind = stage_work(g, dom, args.prec)
+    avg_s = per_stage[dom]["ms_per_launch"] / 1e3
+    if bound == "mfma":
+        peak = PEAKS[args.prec]
+        roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+    else:
+        peak = PEAKS["hbm"]
+        roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": peak / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["work_per_launch"] = work
+    roof["work_unit"] = kind
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "E'^H E' applications/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[args.prec],
+        "data": "synthetic",
+        "config": {
+            "workload": f"2D high-field slice {g.nx}x{g.ny}, {g.nc} coils, os {g.os} ({g.nt} samples), "
+                        f"{g.n_patches} patches of {g.patch_len}, {g.n_groups} groups, K={g.k}, R=4+16 ACS, "
+                        f"SNR 30; step = FISTA-{ITERS} with {LEVELS}-level Haar",
+            "nx": g.nx, "ny": g.ny, "nc": g.nc, "os": g.os, "patch_len": g.patch_len,
+            "groups": g.n_groups, "k": g.k, "ms": g.ms, "fista_iters": ITERS, "precision": args.prec,
+        },
+        "s_per_slice": ms_per_step / 1e3,
+        "op_apps_per_s": op_rate,
+        "calibrate_s": t_cal,
+        "compress_s": t_comp,
+        "stages": per_stage,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(sl, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,38 @@ int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64
 int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
                      double lambda, double lipschitz, int haar_levels, double* h_obj);
 
+/* Largest eigenvalue of E'^H E' (the Lipschitz constant of FISTA's
+ * gradient) by power iteration from the caller's start d_x0 [B][ny][nx]
+ * (normalised first): v <- A v / ||A v||, lambda_k = <v_{k-1}, A v_{k-1}>.
+ * Returns the last lambda in *h_lambda; synchronises. */
+int gpjc_power_iteration(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x0, int iters, double* h_lambda);
+
+/* max over all coefficients of |W x| for d_img [B][ny][nx], W the
+ * orthonormal Haar transform of haar_levels levels (FISTA's lambda is
+ * chosen relative to this for x = E'^H y).  Synchronises. */
+int gpjc_wavelet_absmax(gpjc_plan* plan, const gpjc_c64* d_img, int haar_levels, double* h_out);
+
+/* Per-stage kernel timing with HIP events on the plan's stream.  While
+ * enabled, every stage launch is bracketed by an event pair (up to 16384
+ * launches); gpjc_stage_times synchronises and returns, per stage id, the
+ * summed milliseconds and the number of timed launches.  Enabling resets the
+ * record. */
+enum {
+  GPJC_STAGE_READOUT_FWD = 0,   /* F1 */
+  GPJC_STAGE_GROUP_COMPRESS,    /* F2 (and Eq. 13 on k-space) */
+  GPJC_STAGE_PE_NORMAL,         /* fused phase-encode normal stage */
+  GPJC_STAGE_PE_FWD,            /* phase-encode forward */
+  GPJC_STAGE_PE_ADJ,            /* phase-encode adjoint */
+  GPJC_STAGE_GROUP_EXPAND,      /* F2^H */
+  GPJC_STAGE_READOUT_ADJ,       /* F1^H */
+  GPJC_STAGE_PE_COLS,           /* uncompressed phase-encode stages */
+  GPJC_STAGE_COMBINE,           /* partial-image sums */
+  GPJC_STAGE_SOLVER,            /* CG / FISTA vector kernels */
+  GPJC_STAGE_COUNT
+};
+int gpjc_stage_timing(gpjc_plan* plan, int enable);
+int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches);
+
 const char* gpjc_status_string(int status);
 const char* gpjc_last_error(void);
 /* Path of the HIP runtime library this build is bound to in this process. */

@@ -57,6 +57,8 @@ static void free_plan(Plan* pl) {
     if (pl->Aexp16[i]) (void)hipFree(pl->Aexp16[i]);
     if (pl->AH16[i]) (void)hipFree(pl->AH16[i]);
   }
+  for (hipEvent_t e : pl->timing.ev) (void)hipEventDestroy(e);
+  pl->timing.ev.clear();
 }
 
 static int validate_geom(const gpjc_geom* g) {
@@ -382,6 +384,60 @@ int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_
   GPJC_TRY(check_bank(*plan));
   return finish(*plan, run_fista(*plan, st, reinterpret_cast<const float2*>(d_y), reinterpret_cast<float2*>(d_x),
                                  iters, lambda, lipschitz, haar_levels, h_obj));
+}
+
+int gpjc_power_iteration(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x0, int iters, double* h_lambda) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_x0 || !aligned(d_x0, 8) || !h_lambda) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  if (iters < 1) return fail(GPJC_E_INVAL, "iters must be >= 1");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, run_power_iteration(*plan, st, reinterpret_cast<const float2*>(d_x0), iters, h_lambda));
+}
+
+int gpjc_wavelet_absmax(gpjc_plan* plan, const gpjc_c64* d_img, int haar_levels, double* h_out) {
+  GPJC_TRY(check_plan(plan));
+  if (!d_img || !aligned(d_img, 8) || !h_out) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  if (haar_levels < 1 || haar_levels > 3) return fail(GPJC_E_UNSUPPORTED, "haar_levels must be 1, 2 or 3");
+  const int t = 1 << haar_levels;
+  if (plan->nx % t || plan->ny % t) return fail(GPJC_E_INVAL, "nx and ny must be divisible by 2^haar_levels");
+  return finish(*plan, run_wavelet_absmax(*plan, reinterpret_cast<const float2*>(d_img), haar_levels, h_out));
+}
+
+int gpjc_stage_timing(gpjc_plan* plan, int enable) {
+  GPJC_TRY(check_plan(plan));
+  Timing& t = plan->timing;
+  if (enable) {
+    if (t.ev.empty()) {
+      const int cap = 16384;
+      t.ev.resize(2 * cap);
+      for (auto& e : t.ev) GPJC_HIP(hipEventCreate(&e));
+      t.stage.assign(cap, 0);
+    }
+    t.used = 0;
+  }
+  t.on = enable != 0;
+  return GPJC_OK;
+}
+
+int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches) {
+  GPJC_TRY(check_plan(plan));
+  if (!h_ms || !h_launches) return fail(GPJC_E_INVAL, "NULL output");
+  for (int i = 0; i < GPJC_STAGE_COUNT; ++i) {
+    h_ms[i] = 0.0;
+    h_launches[i] = 0;
+  }
+  Timing& t = plan->timing;
+  if (t.used == 0) return GPJC_OK;
+  GPJC_HIP(hipEventSynchronize(t.ev[2 * (t.used - 1) + 1]));
+  for (int k = 0; k < t.used; ++k) {
+    float ms = 0.f;
+    GPJC_HIP(hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]));
+    h_ms[t.stage[k]] += ms;
+    h_launches[t.stage[k]] += 1;
+  }
+  return GPJC_OK;
 }
 
 const char* gpjc_status_string(int status) {

@@ -626,6 +626,7 @@ struct ReadoutFwd {
   template <int NX>
   struct L {
     static int run(const Plan& pl, const float2* img) {
+      StageScope sc(pl, GPJC_STAGE_READOUT_FWD);
       const int rows = pl.f1_rows;
       const size_t lds = (size_t)(NX + 2 * rows * pl.os * NX) * sizeof(float2);
       dim3 grid((pl.ny + rows - 1) / rows, pl.nc, pl.B);
@@ -642,6 +643,7 @@ struct ReadoutAdj {
   template <int NX>
   struct L {
     static int run(const Plan& pl) {
+      StageScope sc(pl, GPJC_STAGE_READOUT_ADJ);
       const size_t lds = (size_t)(NX + 2 * pl.f1h_cb * pl.os * NX) * sizeof(float2);
       dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
       hipLaunchKernelGGL((k_readout_adj<NX, ST>), grid, dim3(256), lds, pl.stream, (const void*)pl.W, pl.coils,
@@ -655,6 +657,7 @@ struct ReadoutAdj {
 template <int NY>
 struct PeFwd {
   static int run(const Plan& pl, float2* out) {
+    StageScope sc(pl, GPJC_STAGE_PE_FWD);
     const int nlines = pl.B * pl.np * pl.K;
     const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * NY) * sizeof(float2);
     const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
@@ -668,6 +671,7 @@ struct PeFwd {
 template <int NY>
 struct PeAdj {
   static int run(const Plan& pl, const float2* in) {
+    StageScope sc(pl, GPJC_STAGE_PE_ADJ);
     const int nlines = pl.B * pl.np * pl.K;
     const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * NY) * sizeof(float2);
     hipLaunchKernelGGL(k_pe_adj<NY>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream, in,
@@ -680,6 +684,7 @@ struct PeAdj {
 template <int NY>
 struct PeNormal {
   static int run(const Plan& pl) {
+    StageScope sc(pl, GPJC_STAGE_PE_NORMAL);
     const int nlines = pl.B * pl.np * pl.K;
     const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * NY) * sizeof(float2);
     const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
@@ -695,6 +700,7 @@ struct PeCols {
   template <int NY>
   struct L {
     static int run(const Plan& pl, int mode, const float2* in_s, float2* out_s) {
+      StageScope sc(pl, GPJC_STAGE_PE_COLS);
       const int tb = pl.f3_tb;
       const size_t lds = (size_t)(NY + 2 * tb * (NY + 1)) * sizeof(float2);
       dim3 grid((pl.nt + tb - 1) / tb, pl.B * pl.nc);
@@ -723,6 +729,7 @@ int launch_readout_adj(const Plan& pl, Store st) {
 }
 
 int launch_combine(const Plan& pl, float2* out) {
+  StageScope sc(pl, GPJC_STAGE_COMBINE);
   const size_t n = pl.img_elems();
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
   hipLaunchKernelGGL(k_combine, dim3(blocks), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, n, out);
@@ -745,6 +752,7 @@ int launch_pe_cols_normal(const Plan& pl) {
 }
 
 static int gemm_compress(const Plan& pl, const float* in, int ncol, float2* out, int ksplit) {
+  StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS);
   GemmCompressArgs a;
   a.A = pl.Aexp;
   a.in = in;
@@ -778,6 +786,7 @@ int launch_compress_data(const Plan& pl, const float2* ksp, float2* out) {
 }
 
 int launch_group_expand(const Plan& pl, Store st) {
+  StageScope sc(pl, GPJC_STAGE_GROUP_EXPAND);
   GemmExpandArgs a;
   a.Zt = reinterpret_cast<const float*>(pl.Zt);
   a.AH = pl.AH;

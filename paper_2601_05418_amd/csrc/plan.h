@@ -30,6 +30,14 @@ int fail(int code, const std::string& msg);
 // Reduced-precision storage types.
 enum class Store { F32 = 0, BF16 = 1, F16 = 2 };
 
+// HIP-event timing of stage launches (enabled on request).
+struct Timing {
+  bool on = false;
+  int used = 0;
+  std::vector<hipEvent_t> ev;  // 2 per launch
+  std::vector<int> stage;
+};
+
 struct Plan {
   // geometry
   int nx = 0, ny = 0, nc = 0, os = 0, nt = 0, P = 0, np = 0, G = 0, K = 0, Kp = 0, ns = 0, ms = 0;
@@ -82,7 +90,26 @@ struct Plan {
   int hist_cap = 0;
   int red_blocks = 0;
 
+  mutable Timing timing;
+
   size_t img_elems() const { return (size_t)B * ny * nx; }
+};
+
+// Brackets one launch with an event pair while timing is on.
+struct StageScope {
+  const Plan& pl;
+  int slot = -1;
+  StageScope(const Plan& p, int st) : pl(p) {
+    Timing& t = p.timing;
+    if (t.on && t.used < (int)t.stage.size()) {
+      slot = t.used++;
+      t.stage[slot] = st;
+      (void)hipEventRecord(t.ev[2 * slot], p.stream);
+    }
+  }
+  ~StageScope() {
+    if (slot >= 0) (void)hipEventRecord(pl.timing.ev[2 * slot + 1], pl.stream);
+  }
 };
 
 // ---- operator stages (operator.hip) ----
@@ -113,6 +140,9 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
 int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid);
 int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lip,
               int levels, double* h_obj);
+
+int run_power_iteration(Plan& pl, Store st, const float2* x0, int iters, double* h_lambda);
+int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
 
 // Lengths the FFT kernels are instantiated for.
 bool fft_size_supported(int n);

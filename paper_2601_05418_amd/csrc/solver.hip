@@ -13,7 +13,9 @@
 // thread, held in registers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "fft.h"
 #include "plan.h"
@@ -183,16 +185,22 @@ int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine
     double* r_old = red_rr[it & 1];
     double* r_new = red_rr[(it + 1) & 1];
     GPJC_TRY(op_normal_part(pl, st, pl.vp));
-    hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vp, pl.vq, red_pq, n);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, pl.stream, red_pq, r_old, r_new, nb, pl.vx, pl.vr, pl.vp,
-                       pl.vq, n, pl.flag);
+    {
+      StageScope sc(pl, GPJC_STAGE_SOLVER);
+      hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vp, pl.vq, red_pq,
+                         n);
+      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, pl.stream, red_pq, r_old, r_new, nb, pl.vx, pl.vr,
+                         pl.vp, pl.vq, n, pl.flag);
+    }
     GPJC_HIP(hipGetLastError());
     if (refine && (it + 1) % refine_every == 0 && it + 1 < iters) {
       GPJC_TRY(op_normal_part(pl, Store::F32, pl.vx));
+      StageScope sc(pl, GPJC_STAGE_SOLVER);
       hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
                          r_new, n);
       hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, r_new, nb, pl.hist + it + 1);
     } else {
+      StageScope sc(pl, GPJC_STAGE_SOLVER);
       hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, pl.stream, r_new, r_old, nb, pl.vr, pl.vp, n,
                          pl.hist + it + 1);
     }
@@ -345,6 +353,7 @@ __global__ __launch_bounds__(64) void k_fista_step(const float2* __restrict__ pa
 
 template <int LEV>
 static int launch_fista_step(const Plan& pl, float invL, float thr, float mom) {
+  StageScope sc(pl, GPJC_STAGE_SOLVER);
   constexpr int S = 1 << LEV;
   const int tiles = pl.B * (pl.nx / S) * (pl.ny / S);
   hipLaunchKernelGGL(k_fista_step<LEV>, dim3((tiles + 63) / 64), dim3(64), 0, pl.stream, pl.part, pl.f1h_nchunk,
@@ -376,6 +385,127 @@ int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double 
     }
   }
   return copy_vec(pl, pl.vx, x, n);
+}
+
+// ---------------------------------------------------------------------------
+// Power iteration for the largest eigenvalue of the normal operator.
+// ---------------------------------------------------------------------------
+// partial sums of |v|^2
+__global__ __launch_bounds__(256) void k_norm2(const float2* __restrict__ v, double* __restrict__ red, size_t n) {
+  __shared__ double sh[8];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 a = v[i];
+    acc += (double)a.x * a.x + (double)a.y * a.y;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+// v_out = v_in / sqrt(sum partials)
+__global__ __launch_bounds__(256) void k_scale_unit(const float2* __restrict__ vin, float2* __restrict__ vout,
+                                                    const double* __restrict__ red, int nb, size_t n) {
+  __shared__ double sh[8];
+  const double s = sum_partials(red, nb, sh);
+  const float inv = (float)(s > 0.0 ? 1.0 / sqrt(s) : 0.0);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    vout[i] = cscale(vin[i], inv);
+}
+
+// q = A v (partials); partial Re <v, q> and |q|^2
+__global__ __launch_bounds__(256) void k_power_q(const float2* __restrict__ part, int nchunk,
+                                                 const float2* __restrict__ v, float2* __restrict__ q,
+                                                 double* __restrict__ red_vq, double* __restrict__ red_qq, size_t n) {
+  __shared__ double sh[8];
+  double a1 = 0.0, a2 = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 w = sum_part(part, nchunk, n, i);
+    q[i] = w;
+    const float2 a = v[i];
+    a1 += (double)a.x * w.x + (double)a.y * w.y;
+    a2 += (double)w.x * w.x + (double)w.y * w.y;
+  }
+  const double s1 = block_sum(a1, sh);
+  if (threadIdx.x == 0) red_vq[blockIdx.x] = s1;
+  const double s2 = block_sum(a2, sh);
+  if (threadIdx.x == 0) red_qq[blockIdx.x] = s2;
+}
+
+__global__ void k_store_sum(const double* __restrict__ red, int nb, double* __restrict__ out) {
+  __shared__ double sh[8];
+  const double s = sum_partials(red, nb, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+int run_power_iteration(Plan& pl, Store st, const float2* x0, int iters, double* h_lambda) {
+  const size_t n = pl.img_elems();
+  const int nb = kRedBlocks;
+  double* red_a = pl.red;
+  double* red_b = pl.red + nb;
+  hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, pl.stream, x0, red_a, n);
+  hipLaunchKernelGGL(k_scale_unit, dim3(nb), dim3(256), 0, pl.stream, x0, pl.vp, red_a, nb, n);
+  GPJC_HIP(hipGetLastError());
+  GPJC_HIP(hipMemsetAsync(pl.hist, 0, sizeof(double), pl.stream));
+  for (int it = 0; it < iters; ++it) {
+    GPJC_TRY(op_normal_part(pl, st, pl.vp));
+    hipLaunchKernelGGL(k_power_q, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vp, pl.vq, red_a,
+                       red_b, n);
+    hipLaunchKernelGGL(k_scale_unit, dim3(nb), dim3(256), 0, pl.stream, pl.vq, pl.vp, red_b, nb, n);
+    if (it == iters - 1) hipLaunchKernelGGL(k_store_sum, dim3(1), dim3(256), 0, pl.stream, red_a, nb, pl.hist);
+    GPJC_HIP(hipGetLastError());
+  }
+  GPJC_HIP(hipMemcpyAsync(h_lambda, pl.hist, sizeof(double), hipMemcpyDeviceToHost, pl.stream));
+  GPJC_HIP(hipStreamSynchronize(pl.stream));
+  return GPJC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// max |W x| over all Haar coefficients (per-tile transform, block maxima).
+// ---------------------------------------------------------------------------
+template <int LEV>
+__global__ __launch_bounds__(64) void k_wavelet_absmax(const float2* __restrict__ img, int nx, int ny, int B,
+                                                       double* __restrict__ red) {
+  constexpr int S = 1 << LEV;
+  const int tx_n = nx / S, ty_n = ny / S;
+  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+  float m = 0.f;
+  if (tile < B * tx_n * ty_n) {
+    const int b = tile / (tx_n * ty_n);
+    const int rem = tile - b * tx_n * ty_n;
+    const int ty = rem / tx_n, tx = rem - ty * tx_n;
+    float2 c[S][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) c[i][j] = img[((size_t)b * ny + ty * S + i) * nx + tx * S + j];
+    haar_tile<LEV>(c, false);
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) m = fmaxf(m, sqrtf(c[i][j].x * c[i][j].x + c[i][j].y * c[i][j].y));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off, 64));
+  if (threadIdx.x == 0) red[blockIdx.x] = m;
+}
+
+int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out) {
+  const int S = 1 << levels;
+  const int tiles = pl.B * (pl.nx / S) * (pl.ny / S);
+  const int blocks = (tiles + 63) / 64;
+  if (blocks > 4096) return fail(GPJC_E_UNSUPPORTED, "image too large for the wavelet maximum");
+  switch (levels) {
+    case 1: hipLaunchKernelGGL(k_wavelet_absmax<1>, dim3(blocks), dim3(64), 0, pl.stream, img, pl.nx, pl.ny, pl.B, pl.red); break;
+    case 2: hipLaunchKernelGGL(k_wavelet_absmax<2>, dim3(blocks), dim3(64), 0, pl.stream, img, pl.nx, pl.ny, pl.B, pl.red); break;
+    default: hipLaunchKernelGGL(k_wavelet_absmax<3>, dim3(blocks), dim3(64), 0, pl.stream, img, pl.nx, pl.ny, pl.B, pl.red); break;
+  }
+  GPJC_HIP(hipGetLastError());
+  std::vector<double> h(blocks);
+  GPJC_HIP(hipMemcpyAsync(h.data(), pl.red, sizeof(double) * blocks, hipMemcpyDeviceToHost, pl.stream));
+  GPJC_HIP(hipStreamSynchronize(pl.stream));
+  double m = 0.0;
+  for (double v : h) m = std::max(m, v);
+  *h_out = m;
+  return GPJC_OK;
 }
 
 }  // namespace gpjc

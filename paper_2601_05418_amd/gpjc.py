@@ -25,6 +25,9 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "gpjc.h")
 FP32, BF16, FP16 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 
+STAGES = ("readout_fwd", "group_compress", "pe_normal", "pe_fwd", "pe_adj", "group_expand", "readout_adj",
+          "pe_cols", "combine", "solver")
+
 GPJC_OK = 0
 GPJC_E_INVAL = -1
 GPJC_E_STATE = -2
@@ -64,6 +67,10 @@ _SIGS = {
     "gpjc_normal": (_I, [_VP, _I, _VP, _VP]),
     "gpjc_recon_cg": (_I, [_VP, _I, _VP, _VP, _I, _I, _VP]),
     "gpjc_recon_fista": (_I, [_VP, _I, _VP, _VP, _I, _D, _D, _I, _VP]),
+    "gpjc_power_iteration": (_I, [_VP, _I, _VP, _I, _VP]),
+    "gpjc_wavelet_absmax": (_I, [_VP, _VP, _I, _VP]),
+    "gpjc_stage_timing": (_I, [_VP, _I]),
+    "gpjc_stage_times": (_I, [_VP, _VP, _VP]),
     "gpjc_status_string": (ctypes.c_char_p, [_I]),
     "gpjc_last_error": (ctypes.c_char_p, []),
     "gpjc_runtime_path": (ctypes.c_char_p, []),
@@ -262,3 +269,24 @@ class Plan:
         _check(self.lib.gpjc_recon_fista(self.handle, _prec(prec), self._in(y), _ptr(x), int(iters), float(lam),
                                          float(lipschitz), int(levels), None))
         return x
+
+    def power_iteration(self, x0, iters=50, prec="fp32"):
+        self._begin()
+        lam = ctypes.c_double()
+        _check(self.lib.gpjc_power_iteration(self.handle, _prec(prec), self._in(x0), int(iters), ctypes.byref(lam)))
+        return lam.value
+
+    def wavelet_absmax(self, img, levels=3):
+        self._begin()
+        out = ctypes.c_double()
+        _check(self.lib.gpjc_wavelet_absmax(self.handle, self._in(img), int(levels), ctypes.byref(out)))
+        return out.value
+
+    def stage_timing(self, enable=True):
+        _check(self.lib.gpjc_stage_timing(self.handle, int(bool(enable))))
+
+    def stage_times(self):
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int * len(STAGES))()
+        _check(self.lib.gpjc_stage_times(self.handle, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}

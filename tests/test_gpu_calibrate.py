@@ -1,0 +1,132 @@
+"""GPU calibration (FP64 Gram + block Jacobi + selection) against the oracle.
+
+Eigenvalues are compared relative to the largest; the bank is compared on
+projectors Pi_g = A_g^H A_g (unique when lambda_K > lambda_{K+1}) and also
+row by row (the phase normalisation makes rows unique when the kept
+eigenvalues are simple)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import compression as oc
+from oracle import encoding as oe
+from paper_2601_05418_amd import gpjc, synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def calibrate_both(sl, roi=None, cov=None, groups=None):
+    g = sl.geom
+    plan = gpjc.Plan.from_slice(sl)
+    cov64 = None if cov is None else np.asarray(cov, np.complex64).astype(np.complex128)
+    eig, bank = plan.calibrate(roi=roi, noise_cov=None if cov is None else cov64.astype(np.complex64),
+                               want_eigvals=True, want_bank=True)
+    bank = bank.cpu().numpy()
+    if groups is None:
+        a_ref, lam_ref = oc.calibrate(sl.coils, sl.psf, g.os, g.patch_len, g.patch_group, g.n_groups, g.k,
+                                      roi=roi, noise_cov=cov64)
+        return plan, eig, bank, a_ref, lam_ref, list(range(g.n_groups))
+    maps = sl.coils if cov64 is None else np.einsum("ab,byx->ayx", oc.whitening(cov64), sl.coils)
+    firsts = oc.first_members(g.patch_group, g.n_groups)
+    a_ref, lam_ref = [], []
+    for gi in groups:
+        e = oc.virtual_channels(maps, sl.psf, g.os, g.patch_len, firsts[gi] * g.patch_len)
+        a, lam = oc.compression_matrix(oc.gram(e, roi), g.k, g.patch_len)
+        a_ref.append(a.reshape(g.k, g.nc, g.patch_len))
+        lam_ref.append(lam)
+    return plan, eig[groups], bank[groups], np.stack(a_ref), np.stack(lam_ref), groups
+
+
+def check_bank(eig, bank, a_ref, lam_ref, k, rows=True, cov=None):
+    scale = lam_ref[:, :1]
+    err_l = np.max(np.abs(eig - lam_ref) / scale)
+    pi, pr = oc.projectors(bank), oc.projectors(a_ref)
+    err_p = np.max(np.abs(pi - pr))
+    gaps = (lam_ref[:, k - 1] - lam_ref[:, k]) / lam_ref[:, 0] if k < lam_ref.shape[1] else np.ones(len(lam_ref))
+    b = bank.reshape(bank.shape[0], k, -1)
+    # rows are orthonormal; with whitening T, orthonormal in the noise metric: A (Psi x I) A^H = I
+    metric = np.eye(b.shape[2]) if cov is None else np.kron(cov, np.eye(b.shape[2] // cov.shape[0]))
+    err_u = np.max(np.abs(np.einsum("gki,ij,glj->gkl", b, metric, b.conj()) - np.eye(k)))
+    print(f"eig err {err_l:.2e}, projector err {err_p:.2e}, unitarity {err_u:.2e}, min gap {gaps.min():.2e}",
+          flush=True)
+    assert err_l <= 1e-10
+    assert err_u <= 1e-11
+    assert err_p <= 1e-9 / max(gaps.min(), 1e-3)
+    if rows:
+        assert np.max(np.abs(bank - a_ref)) <= 1e-7 / max(gaps.min(), 1e-3)
+
+
+@pytest.mark.parametrize("case", ["small", "rect", "periodic"])
+def test_calibrate_matches_oracle(gpu_lib, case):
+    sl = H.rounded_slice(H.CASES[case]())
+    plan, eig, bank, a_ref, lam_ref, _ = calibrate_both(sl)
+    check_bank(eig, bank, a_ref, lam_ref, sl.geom.k)
+
+
+def test_calibrate_roi_and_whitening(gpu_lib):
+    sl = H.rounded_slice(H.rect_slice(1))
+    g = sl.geom
+    rng = np.random.default_rng(9)
+    roi = (rng.uniform(size=(g.ny, g.nx)) > 0.4).astype(np.uint8)
+    m = H.crandn(rng, (g.nc, g.nc))
+    cov = m @ m.conj().T + g.nc * np.eye(g.nc)
+    plan, eig, bank, a_ref, lam_ref, _ = calibrate_both(sl, roi=roi, cov=cov)
+    check_bank(eig, bank, a_ref, lam_ref, g.k, cov=np.asarray(cov, np.complex64).astype(np.complex128))
+
+
+def test_calibrate_trace_and_full_rank_lossless(gpu_lib):
+    """tr P_g = number of ROI pixels; K = Ns makes the compressed normal
+    operator equal the uncompressed one."""
+    sl = H.rounded_slice(synth.tiny_slice(nx=16, ny=16, os_=2, nc=2, patch_len=4, k=8))
+    g = sl.geom
+    plan = gpjc.Plan.from_slice(sl)
+    eig, _ = plan.calibrate(want_eigvals=True)
+    assert np.allclose(eig.sum(axis=1), g.nx * g.ny, rtol=1e-12)
+    full = gpjc.Plan.from_slice(sl, compressed=False)
+    x = torch.as_tensor(np.ascontiguousarray(H.round64(sl.image)[None], np.complex64)).cuda()
+    a = plan.normal(x).cpu().numpy()
+    b = full.normal(x).cpu().numpy()
+    assert H.rel_l2(a, b) <= 1e-5
+
+
+def test_calibrated_operator_parity(gpu_lib):
+    """The bank the GPU calibrates drives the operator exactly like the
+    oracle's bank (compared through the basis-free normal operator)."""
+    sl = H.rounded_slice(synth.small_slice(0))
+    g = sl.geom
+    plan = gpjc.Plan.from_slice(sl)
+    plan.calibrate()
+    a_ref, _ = H.oracle_bank(sl)
+    x = H.round64(H.crandn(np.random.default_rng(3), (g.ny, g.nx)))
+    out = plan.normal(torch.as_tensor(np.ascontiguousarray(x[None], np.complex64)).cuda()).cpu().numpy()[0]
+    ref = oe.normal(x, sl.coils, sl.psf, g.mask, g.os, a_ref, g.patch_group, g.patch_len)
+    assert H.rel_l2(out, ref) <= 1e-5
+
+
+def test_noise_covariance_not_positive_definite(gpu_lib):
+    sl = H.rounded_slice(synth.small_slice(0))
+    plan = gpjc.Plan.from_slice(sl)
+    cov = np.eye(sl.geom.nc, dtype=np.complex64)
+    cov[2, 2] = -1.0
+    with pytest.raises(gpjc.GpjcError) as e:
+        plan.calibrate(noise_cov=cov)
+    assert e.value.status == gpjc.GPJC_E_NUMERIC
+
+
+def test_calibrate_highfield_sampled_groups(gpu_lib):
+    """224 x 224, 32 coils, Ns = 1024, 42 groups at full size; the oracle
+    recomputes two of the groups."""
+    sl = H.rounded_slice(synth.highfield_slice(0))
+    plan, eig, bank, a_ref, lam_ref, groups = calibrate_both(sl, groups=[0, 41])
+    check_bank(eig, bank, a_ref, lam_ref, sl.geom.k, rows=False)
+
+
+def test_calibrate_ns512_decayed_couplings(gpu_lib):
+    """Ns = 512 (32 Jacobi blocks): couplings decay far enough during the
+    sweeps that |c|^2 underflows; every rotation must stay unitary."""
+    sl = H.rounded_slice(synth._make_rect(0, nx=64, ny=64, nc=16, os_=4, patch_len=32, k=8, accel=4, acs=8,
+                                          cycles=5, phase_max=3.0))
+    plan, eig, bank, a_ref, lam_ref, groups = calibrate_both(sl, groups=[0, 3, 7])
+    assert np.allclose(eig.sum(axis=1), 64 * 64, rtol=1e-11)
+    check_bank(eig, bank, a_ref, lam_ref, sl.geom.k)

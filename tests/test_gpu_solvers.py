@@ -75,3 +75,37 @@ def test_fista_strong_penalty_matches(gpu_lib):
     xg = host(plan.recon_fista(dev(y[None]), 15, lam, lip, levels=2))[0]
     xo, _ = osv.fista(ops["nrm"], b, 15, lam, lip, 2)
     assert osv.nrmse(xg, xo) <= H.NRMSE_RECON
+
+
+def test_power_iteration_matches_oracle(gpu_lib):
+    sl, plan, ops, y = setup("small")
+    rng = np.random.default_rng(4)
+    x0 = H.round64(H.crandn(rng, (sl.geom.ny, sl.geom.nx)))
+    lam = plan.power_iteration(dev(x0[None]), 30)
+    # oracle power iteration from the same start
+    v = x0 / np.linalg.norm(x0)
+    ref = 0.0
+    for _ in range(30):
+        w = ops["nrm"](v)
+        ref = np.vdot(v, w).real
+        v = w / np.linalg.norm(w)
+    assert abs(lam - ref) <= 1e-5 * ref
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_wavelet_absmax(gpu_lib, levels):
+    sl, plan, ops, y = setup("rect")
+    x = H.round64(H.crandn(np.random.default_rng(5), (sl.geom.ny, sl.geom.nx)))
+    got = plan.wavelet_absmax(dev(x[None]), levels)
+    ref = np.abs(osv.haar_fwd(x, levels)).max()
+    assert abs(got - ref) <= 1e-6 * ref
+
+
+def test_stage_timing_counts(gpu_lib):
+    sl, plan, ops, y = setup("small")
+    plan.stage_timing(True)
+    plan.recon_fista(dev(y[None]), 4, 1e-3, 2.0, levels=3)
+    t = plan.stage_times()
+    plan.stage_timing(False)
+    assert t["readout_fwd"][1] == 4 and t["group_compress"][1] == 4 and t["readout_adj"][1] == 5
+    assert t["solver"][1] == 4 and all(v[0] >= 0 for v in t.values())
