@@ -33,6 +33,18 @@ LEVELS = 3
 
 PEAKS = {"hbm": 8.0e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
 
+# Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
+# plain copy) for the FP32 operator on this workload, with the hash of the
+# sources each kernel is built from when the counters were taken.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "highfield_op_hbm_traffic.md")
+STAGE_SOURCES = {
+    "readout_fwd": ("operator.hip", "fft.h", "devutil.h"),
+    "readout_adj": ("operator.hip", "fft.h", "devutil.h"),
+    "pe_normal": ("operator.hip", "fft.h", "devutil.h"),
+    "group_compress": ("gemm.hip", "devutil.h"),
+    "group_expand": ("gemm.hip", "devutil.h"),
+}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -51,6 +63,29 @@ def stage_work(g, stage, prec, ksplit_read=1):
     if stage == "solver":
         return "hbm", 10 * 8.0 * B * nx * ny, "byte"
     return "hbm", 8.0 * B * nx * ny, "byte"
+
+
+def source_hash(files):
+    import hashlib
+    m = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2601_05418_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def measured_traffic(stage):
+    """Bytes per launch from the committed counter summary, or None when the
+    kernel's sources changed since the counters were taken."""
+    if stage not in STAGE_SOURCES or not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = source_hash(STAGE_SOURCES[stage])
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic-bytes" and f[1] == stage and f[3] == "src":
+                return float(f[2]) if f[4] == want else None
+    return None
 
 
 def cpu_baseline(sl, budget_s):
@@ -103,6 +138,10 @@ def main():
     ap.add_argument("--periodic", action="store_true", help="map the 42 patches onto the 6 of one wave period")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (reference for byte counters)")
+    ap.add_argument("--op-only", type=int, default=0, metavar="N",
+                    help="only calibrate and run N applications of E'^H E' (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
@@ -115,6 +154,15 @@ def main():
     from paper_2601_05418_amd import gpjc, synth
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 4, "copies": 5}), flush=True)
+        return
     sl = synth.highfield_slice(0, periodic=args.periodic)
     g = sl.geom
     log(f"workload: {g.nx}x{g.ny}, nc={g.nc}, nt={g.nt}, P={g.patch_len}, G={g.n_groups}, K={g.k}, Ms={g.ms}")
@@ -141,6 +189,15 @@ def main():
         plan.compress(ksp, out=y)
     torch.cuda.synchronize()
     t_comp = (time.perf_counter() - t) / 10
+
+    if args.op_only:
+        xin = torch.as_tensor(np.ascontiguousarray(sl.image[None], np.complex64)).to(dev)
+        out = torch.empty_like(xin)
+        for _ in range(args.op_only):
+            plan.normal(xin, prec=args.prec, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"op_only_applications": args.op_only}), flush=True)
+        return
 
     b = plan.adjoint(y, prec=args.prec)
     lam = 1e-3 * plan.wavelet_absmax(b, LEVELS)
@@ -191,7 +248,9 @@ def main():
         peak = PEAKS["hbm"]
         roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": peak / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    # counters were taken on the FP32 operator of the 42-group workload
+    roof["traffic"] = measured_traffic(dom) if (args.prec == "fp32" and not args.periodic) else None
+    roof["traffic_unit"] = "bytes per launch"
     roof["kernel"] = dom
     roof["work_per_launch"] = work
     roof["work_unit"] = kind

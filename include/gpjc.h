@@ -175,6 +175,15 @@ enum {
 int gpjc_stage_timing(gpjc_plan* plan, int enable);
 int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches);
 
+/* Work-group tile shape of the two group contractions and the contraction
+ * split of the compressing one (1..8).  The defaults come from the plan's
+ * shapes; an autotuner may time the variants with gpjc_stage_timing and
+ * install the fastest.  Changes only speed, never results beyond FP32
+ * summation order. */
+int gpjc_set_gemm_config(gpjc_plan* plan, int compress_variant, int expand_variant, int ksplit);
+int gpjc_get_gemm_config(const gpjc_plan* plan, int* compress_variant, int* expand_variant, int* ksplit,
+                         int* n_compress_variants, int* n_expand_variants);
+
 const char* gpjc_status_string(int status);
 const char* gpjc_last_error(void);
 /* Path of the HIP runtime library this build is bound to in this process. */

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "fft.h"
 #include "plan.h"
 
 struct gpjc_plan : gpjc::Plan {};
@@ -49,7 +50,7 @@ static int dalloc(T** p, size_t count) {
 
 static void free_plan(Plan* pl) {
   void* bufs[] = {pl->coils, pl->psf,  pl->psfp, pl->twin, pl->tw_x, pl->tw_y, pl->lines, pl->pgroup,
-                  pl->maskf, pl->A128, pl->Aexp, pl->AH,   pl->W,    pl->Zp,   pl->Zt,    pl->part,
+                  pl->maskf, pl->zeros, pl->A128, pl->Aexp, pl->AH,   pl->W,    pl->Zp,   pl->Zt,    pl->part,
                   pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->red,  pl->hist,  pl->flag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -105,22 +106,27 @@ static constexpr int kLdsSlots = 8192;  // float2 slots per work-group (64 KiB)
 
 // Every kernel keeps its LDS within 64 KiB; shapes that cannot are rejected.
 static int check_lds(const gpjc_geom* g) {
-  const long line = 2L * g->os * g->nx + g->nx;  // one image row of the readout stages
+  const long line = 2L * g->os * fline(g->nx) + g->nx;  // one image row of the readout stages
   if (line > kLdsSlots) return fail(GPJC_E_UNSUPPORTED, "os * nx too large for the readout stages");
-  if (3L * g->ny > kLdsSlots || 2L * (g->ny + 1) + g->ny > kLdsSlots)
-    return fail(GPJC_E_UNSUPPORTED, "ny too large for the phase-encode stages");
+  if ((long)g->os * g->nx > 16 * 256) return fail(GPJC_E_UNSUPPORTED, "readout longer than 4096 samples");
+  if (2L * fline(g->ny) + g->ny > kLdsSlots) return fail(GPJC_E_UNSUPPORTED, "ny too large for the phase-encode stages");
   return GPJC_OK;
 }
 
 static void choose_launch(Plan& pl) {
   const int lds_f2 = kLdsSlots;
-  int rows = std::max(1, (lds_f2 - pl.nx) / (2 * pl.os * pl.nx));
-  rows = std::min(rows, std::max(1, pl.ny * pl.nc * pl.B / 1024));
+  const int lsx = fline(pl.nx), lsy = fline(pl.ny);
+  // readout forward: one image row per work-group once there are enough rows
+  int rows = std::max(1, (lds_f2 - pl.nx) / (2 * pl.os * lsx));
+  rows = std::min(rows, std::max(1, pl.ny * pl.nc * pl.B / 4096));
   pl.f1_rows = std::max(1, std::min(rows, pl.ny));
 
-  int cb = std::max(1, (lds_f2 - pl.nx) / (2 * pl.os * pl.nx));
-  cb = std::min(std::min(cb, 4), pl.nc);
-  int nchunk = (1024 + pl.ny * pl.B - 1) / (pl.ny * pl.B);
+  // readout adjoint: coils transformed together (up to 2, LDS permitting),
+  // and enough coil chunks for about 2048 work-groups (each chunk leaves one
+  // partial image)
+  int cb = std::max(1, (lds_f2 - pl.nx) / (2 * pl.os * lsx));
+  cb = std::min(std::min(cb, 2), pl.nc);
+  int nchunk = (2048 + pl.ny * pl.B - 1) / (pl.ny * pl.B);
   nchunk = std::max(1, std::min(nchunk, (pl.nc + cb - 1) / cb));
   int cpc = (pl.nc + nchunk - 1) / nchunk;
   cpc = (cpc + cb - 1) / cb * cb;
@@ -128,14 +134,19 @@ static void choose_launch(Plan& pl) {
   pl.f1h_cpc = cpc;
   pl.f1h_nchunk = (pl.nc + cpc - 1) / cpc;
 
-  pl.f3_lpb = std::max(1, std::min(32, (lds_f2 - pl.ny) / (2 * pl.ny)));
-  pl.f3_tb = std::max(1, std::min(16, (lds_f2 - pl.ny) / (2 * (pl.ny + 1))));
+  const int lpb_max = std::max(1, std::min(32, (lds_f2 - pl.ny) / (2 * lsy)));
+  const int nlines = pl.compressed ? pl.B * pl.np * pl.K : 1;
+  pl.f3_lpb = std::max(1, std::min(lpb_max, nlines / 1024));
+  pl.f3_tb = std::max(1, std::min(16, (lds_f2 - pl.ny) / (2 * lsy)));
 
   if (pl.compressed) {
     const int kd = 2 * pl.ns;
-    const long tiles = (long)((pl.ny + 63) / 64) * ((2 * pl.K + 63) / 64) * pl.B * pl.np;
+    pl.gemm_cvar = 2 * pl.K >= 128 ? 0 : 3;
+    pl.gemm_evar = 1;
+    const int tm = compress_tile_rows(pl), tn = compress_tile_cols(pl);
+    const long tiles = (long)((pl.ny + tn - 1) / tn) * ((2 * pl.K + tm - 1) / tm) * pl.B * pl.np;
     int ks = (int)std::max<long>(1, (1024 + tiles - 1) / tiles);
-    ks = std::min(ks, std::max(1, kd / 64));
+    ks = std::min(std::min(ks, std::max(1, kd / 128)), kMaxKsplit);
     pl.gemm_ksplit = ks;
   }
 }
@@ -175,6 +186,8 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
   GPJC_TRY(dalloc(&pl.tw_y, (size_t)pl.ny));
   GPJC_TRY(dalloc(&pl.lines, (size_t)pl.ms));
   GPJC_TRY(dalloc(&pl.maskf, (size_t)pl.ny));
+  GPJC_TRY(dalloc(&pl.zeros, 64));
+  GPJC_HIP(hipMemsetAsync(pl.zeros, 0, 64 * sizeof(float), stream));
   GPJC_TRY(dalloc(&pl.W, (size_t)pl.B * pl.nc * pl.ny * pl.nt));
   GPJC_TRY(dalloc(&pl.part, (size_t)pl.f1h_nchunk * pl.B * npix));
   const size_t ni = pl.img_elems();
@@ -192,7 +205,7 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
     GPJC_TRY(dalloc(&pl.A128, (size_t)pl.G * pl.K * pl.ns));
     GPJC_TRY(dalloc(&pl.Aexp, (size_t)pl.G * 2 * pl.K * 2 * pl.ns));
     GPJC_TRY(dalloc(&pl.AH, (size_t)pl.G * 2 * pl.ns * 2 * pl.Kp));
-    GPJC_TRY(dalloc(&pl.Zp, (size_t)pl.gemm_ksplit * pl.B * pl.np * pl.K * pl.ny));
+    GPJC_TRY(dalloc(&pl.Zp, (size_t)kMaxKsplit * pl.B * pl.np * pl.K * pl.ny));
     GPJC_TRY(dalloc(&pl.Zt, (size_t)pl.B * pl.np * pl.ny * pl.Kp));
     GPJC_HIP(hipMemsetAsync(pl.Zt, 0, sizeof(float2) * (size_t)pl.B * pl.np * pl.ny * pl.Kp, stream));
     GPJC_HIP(hipMemcpyAsync(pl.pgroup, pl.pgroup_h.data(), sizeof(int) * pl.np, hipMemcpyHostToDevice, stream));
@@ -437,6 +450,30 @@ int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches) {
     h_ms[t.stage[k]] += ms;
     h_launches[t.stage[k]] += 1;
   }
+  return GPJC_OK;
+}
+
+int gpjc_set_gemm_config(gpjc_plan* plan, int compress_variant, int expand_variant, int ksplit) {
+  GPJC_TRY(check_plan(plan));
+  if (!plan->compressed) return fail(GPJC_E_INVAL, "GEMM configuration needs a compressed plan");
+  if (compress_variant < 0 || compress_variant >= gemm_compress_variants() || expand_variant < 0 ||
+      expand_variant >= gemm_expand_variants())
+    return fail(GPJC_E_INVAL, "unknown GEMM variant");
+  if (ksplit < 1 || ksplit > kMaxKsplit) return fail(GPJC_E_INVAL, "ksplit out of range");
+  plan->gemm_cvar = compress_variant;
+  plan->gemm_evar = expand_variant;
+  plan->gemm_ksplit = ksplit;
+  return GPJC_OK;
+}
+
+int gpjc_get_gemm_config(const gpjc_plan* plan, int* compress_variant, int* expand_variant, int* ksplit,
+                         int* n_compress_variants, int* n_expand_variants) {
+  GPJC_TRY(check_plan(plan));
+  if (compress_variant) *compress_variant = plan->gemm_cvar;
+  if (expand_variant) *expand_variant = plan->gemm_evar;
+  if (ksplit) *ksplit = plan->gemm_ksplit;
+  if (n_compress_variants) *n_compress_variants = gemm_compress_variants();
+  if (n_expand_variants) *n_expand_variants = gemm_expand_variants();
   return GPJC_OK;
 }
 

@@ -1,0 +1,60 @@
+// Device helpers shared by the operator sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace gpjc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Reduced-precision storage of complex values (round to nearest even).
+__device__ inline uint32_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0u;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ inline float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ inline uint32_t f32_to_f16_bits(float f) {
+  _Float16 h = (_Float16)f;
+  return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float f16_bits_to_f32(uint32_t h) { return (float)__builtin_bit_cast(_Float16, (uint16_t)h); }
+
+template <Store ST>
+__device__ inline uint32_t to_bits16(float f) {
+  if constexpr (ST == Store::BF16) return f32_to_bf16_bits(f);
+  else return f32_to_f16_bits(f);
+}
+
+template <Store ST>
+__device__ inline void store_c(void* base, size_t i, float2 v) {
+  if constexpr (ST == Store::F32) {
+    reinterpret_cast<float2*>(base)[i] = v;
+  } else {
+    reinterpret_cast<uint32_t*>(base)[i] = to_bits16<ST>(v.x) | (to_bits16<ST>(v.y) << 16);
+  }
+}
+template <Store ST>
+__device__ inline float2 load_c(const void* base, size_t i) {
+  if constexpr (ST == Store::F32) {
+    return reinterpret_cast<const float2*>(base)[i];
+  } else {
+    const uint32_t w = reinterpret_cast<const uint32_t*>(base)[i];
+    if constexpr (ST == Store::BF16) return make_float2(bf16_bits_to_f32(w & 0xffffu), bf16_bits_to_f32(w >> 16));
+    else return make_float2(f16_bits_to_f32(w & 0xffffu), f16_bits_to_f32(w >> 16));
+  }
+}
+
+// Work-group id remapped so that consecutive logical tiles share one XCD
+// (work-groups are dealt round-robin over the 8 XCDs, each with its own L2).
+__device__ inline int xcd_logical(int linear, int total) {
+  const int per = total / 8, rem = total % 8;
+  const int xcd = linear % 8, slot = linear / 8;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+}  // namespace gpjc

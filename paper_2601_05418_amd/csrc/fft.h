@@ -146,8 +146,16 @@ __host__ __device__ inline void dft_fwd(float2* v) {
   }
 }
 
-// One Stockham pass over `nlines` lines of length N (line l starts at l*stride).
-// tw[m] = exp(-2 pi i m / N), m in [0, N).
+// LDS position of element e of a line: one padding slot after every 8
+// elements, so the stride-R stores of a Stockham pass and the stride-os
+// gathers of the readout stages spread over the banks.
+__host__ __device__ constexpr int fpad(int e) { return e + (e >> 3); }
+// Line stride (in complex elements) of a padded line of length N; odd, so
+// lines accessed at equal offsets also land on different banks.
+__host__ __device__ constexpr int fline(int n) { return n + (n >> 3) + 1; }
+
+// One Stockham pass over `nlines` padded lines of length N (line l starts at
+// l*stride).  tw[m] = exp(-2 pi i m / N), m in [0, N).
 template <int N, int NS, int R>
 __host__ __device__ inline void stockham_pass(const float2* __restrict__ in, float2* __restrict__ out,
                                               const float2* __restrict__ tw, int nlines, int stride,
@@ -162,7 +170,7 @@ __host__ __device__ inline void stockham_pass(const float2* __restrict__ in, flo
     float2* dst = out + line * stride;
     float2 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[j + r * NB];
+    for (int r = 0; r < R; ++r) v[r] = src[fpad(j + r * NB)];
     if constexpr (NS > 1) {
       const int k = j % NS;
 #pragma unroll
@@ -171,12 +179,13 @@ __host__ __device__ inline void stockham_pass(const float2* __restrict__ in, flo
     dft_fwd<R>(v);
     const int idx = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[idx + r * NS] = v[r];
+    for (int r = 0; r < R; ++r) dst[fpad(idx + r * NS)] = v[r];
   }
 }
 
-// Forward FFT of `nlines` lines; data starts in `a`, `b` is scratch of the
-// same extent.  `sync` separates passes (a workgroup barrier on the device).
+// Forward FFT of `nlines` padded lines (element e of line l at
+// l*stride + fpad(e)); data starts in `a`, `b` is scratch of the same
+// extent.  `sync` separates passes (a workgroup barrier on the device).
 // Returns the buffer holding the result.
 template <int N, int P = 0, int NS = 1, class Sync>
 __host__ __device__ inline float2* fft_lines(float2* a, float2* b, const float2* tw, int nlines, int stride,

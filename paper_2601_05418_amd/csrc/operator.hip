@@ -18,59 +18,13 @@
 
 #include <cmath>
 
+#include "devutil.h"
 #include "fft.h"
 #include "plan.h"
 
 namespace gpjc {
 
-// ---------------------------------------------------------------------------
-// Reduced-precision storage of complex values (round to nearest even).
-// ---------------------------------------------------------------------------
-__device__ inline uint32_t f32_to_bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0u;  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-__device__ inline float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
-__device__ inline uint32_t f32_to_f16_bits(float f) {
-  _Float16 h = (_Float16)f;
-  return (uint32_t)__builtin_bit_cast(uint16_t, h);
-}
-__device__ inline float f16_bits_to_f32(uint32_t h) {
-  return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
-}
-
-template <Store ST>
-__device__ inline void store_c(void* base, size_t i, float2 v) {
-  if constexpr (ST == Store::F32) {
-    reinterpret_cast<float2*>(base)[i] = v;
-  } else if constexpr (ST == Store::BF16) {
-    reinterpret_cast<uint32_t*>(base)[i] = f32_to_bf16_bits(v.x) | (f32_to_bf16_bits(v.y) << 16);
-  } else {
-    reinterpret_cast<uint32_t*>(base)[i] = f32_to_f16_bits(v.x) | (f32_to_f16_bits(v.y) << 16);
-  }
-}
-template <Store ST>
-__device__ inline float2 load_c(const void* base, size_t i) {
-  if constexpr (ST == Store::F32) {
-    return reinterpret_cast<const float2*>(base)[i];
-  } else {
-    const uint32_t w = reinterpret_cast<const uint32_t*>(base)[i];
-    if constexpr (ST == Store::BF16) return make_float2(bf16_bits_to_f32(w & 0xffffu), bf16_bits_to_f32(w >> 16));
-    else return make_float2(f16_bits_to_f32(w & 0xffffu), f16_bits_to_f32(w >> 16));
-  }
-}
-
 __device__ inline void wg_sync() { __syncthreads(); }
-
-// Work-group id remapped so that consecutive logical tiles share one XCD
-// (work-groups are dealt round-robin over the 8 XCDs, each with its own L2).
-__device__ inline int xcd_logical(int linear, int total) {
-  const int per = total / 8, rem = total % 8;
-  const int xcd = linear % 8, slot = linear / 8;
-  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
-}
 
 // ---------------------------------------------------------------------------
 // Tables: psfp, twin, FFT twiddles (FP64 evaluation, rounded once).
@@ -119,15 +73,22 @@ int launch_prep_tables(Plan& pl) {
   return GPJC_OK;
 }
 
+// t / os for t < 2^16 and a small runtime os, through a float reciprocal:
+// (t + 0.5) / os stays at least 0.5 / os away from every integer, far more
+// than the float rounding of the product.
+__device__ inline int div_os(int t, float inv_os) { return (int)(((float)t + 0.5f) * inv_os); }
+
 // ---------------------------------------------------------------------------
 // F1: W[b][n][y][t] = psfp[y][t] * FFT_Nx(coil * img * twin[s])[q]
-// grid (row blocks, nc, B); `rows` image rows per work-group.
+// grid (row blocks, nc, B); `rows` image rows per work-group.  LDS lines are
+// padded (fft.h): line (r, s) holds the s-th sub-transform of row r.
 // ---------------------------------------------------------------------------
 template <int NX, Store ST>
 __global__ __launch_bounds__(256) void k_readout_fwd(const float2* __restrict__ img, const float2* __restrict__ coils,
                                                      const float2* __restrict__ psfp, const float2* __restrict__ twin,
                                                      const float2* __restrict__ tw, void* __restrict__ W, int ny,
-                                                     int nc, int os, int rows) {
+                                                     int nc, int os, float inv_os, int rows) {
+  constexpr int LS = fline(NX);
   extern __shared__ float2 sm[];
   const int tid = threadIdx.x;
   const int nt = os * NX;
@@ -136,24 +97,41 @@ __global__ __launch_bounds__(256) void k_readout_fwd(const float2* __restrict__ 
   const int nr = min(rows, ny - y0);
   float2* twl = sm;
   float2* bufA = sm + NX;
-  float2* bufB = bufA + rows * os * NX;
+  float2* bufB = bufA + rows * os * LS;
   for (int i = tid; i < NX; i += 256) twl[i] = tw[i];
   const float2* cp = coils + ((size_t)n * ny + y0) * NX;
   const float2* ip = img + ((size_t)b * ny + y0) * NX;
   for (int i = tid; i < nr * NX; i += 256) {
     const int r = i / NX, x = i - r * NX;
     const float2 u = cmul(cp[i], ip[i]);
-    float2* dst = bufA + r * os * NX + x;
-    for (int s = 0; s < os; ++s) dst[s * NX] = cmul(u, twin[s * NX + x]);
+    float2* dst = bufA + r * os * LS + fpad(x);
+    for (int s = 0; s < os; ++s) dst[s * LS] = cmul(u, twin[s * NX + x]);
+  }
+  // PSF samples of the first row are fetched before the transform so their
+  // latency overlaps it (nt <= 16 * 256 samples per row).
+  constexpr int PF = 16;
+  float2 pv[PF];
+  const float2* ps0 = psfp + (size_t)y0 * nt;
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int t = tid + 256 * k;
+    if (t < nt) pv[k] = ps0[t];
   }
   __syncthreads();
-  const float2* res = fft_lines<NX>(bufA, bufB, twl, nr * os, NX, tid, 256, wg_sync);
-  const size_t obase = (((size_t)b * nc + n) * ny + y0) * nt;
-  const float2* ps = psfp + (size_t)y0 * nt;
-  for (int i = tid; i < nr * nt; i += 256) {
-    const int r = i / nt, t = i - r * nt;
-    const int q = t / os, s = t - q * os;
-    store_c<ST>(W, obase + i, cmul(ps[i], res[(r * os + s) * NX + q]));
+  const float2* res = fft_lines<NX>(bufA, bufB, twl, nr * os, LS, tid, 256, wg_sync);
+  for (int r = 0; r < nr; ++r) {
+    const size_t ob = (((size_t)b * nc + n) * ny + y0 + r) * nt;
+    const float2* ps = psfp + (size_t)(y0 + r) * nt;
+    const float2* rr = res + r * os * LS;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int t = tid + 256 * k;
+      if (t < nt) {
+        const int q = div_os(t, inv_os), s = t - q * os;
+        const float2 psv = r == 0 ? pv[k] : ps[t];
+        store_c<ST>(W, ob + t, cmul(psv, rr[s * LS + fpad(q)]));
+      }
+    }
   }
 }
 
@@ -163,7 +141,8 @@ template <int NX, Store ST>
 __global__ __launch_bounds__(256) void k_readout_adj(const void* __restrict__ W, const float2* __restrict__ coils,
                                                      const float2* __restrict__ psfp, const float2* __restrict__ twin,
                                                      const float2* __restrict__ tw, float2* __restrict__ part, int ny,
-                                                     int nc, int os, int cb, int cpc, int B) {
+                                                     int nc, int os, float inv_os, int cb, int cpc, int B) {
+  constexpr int LS = fline(NX);
   extern __shared__ float2 sm[];
   constexpr int PER = (NX + 255) / 256;
   const int tid = threadIdx.x;
@@ -171,7 +150,7 @@ __global__ __launch_bounds__(256) void k_readout_adj(const void* __restrict__ W,
   const int y = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
   float2* twl = sm;
   float2* bufA = sm + NX;
-  float2* bufB = bufA + cb * os * NX;
+  float2* bufB = bufA + cb * os * LS;
   for (int i = tid; i < NX; i += 256) twl[i] = tw[i];
   float2 acc[PER];
 #pragma unroll
@@ -180,21 +159,24 @@ __global__ __launch_bounds__(256) void k_readout_adj(const void* __restrict__ W,
   const float2* ps = psfp + (size_t)y * nt;
   for (int n0 = nb; n0 < ne; n0 += cb) {
     const int ncb = min(cb, ne - n0);
-    for (int i = tid; i < ncb * nt; i += 256) {
-      const int c = i / nt, t = i - c * nt;
-      const int q = t / os, s = t - q * os;
-      const float2 w = load_c<ST>(W, (((size_t)b * nc + n0 + c) * ny + y) * nt + t);
-      bufA[(c * os + s) * NX + q] = cmulc(ps[t], w);  // conj(conj(psf) * w)
+    for (int c = 0; c < ncb; ++c) {
+      const size_t wb = (((size_t)b * nc + n0 + c) * ny + y) * nt;
+      float2* dst = bufA + c * os * LS;
+      for (int t = tid; t < nt; t += 256) {
+        const int q = div_os(t, inv_os), s = t - q * os;
+        dst[s * LS + fpad(q)] = cmulc(ps[t], load_c<ST>(W, wb + t));  // conj(conj(psf) * w)
+      }
     }
     __syncthreads();
-    const float2* res = fft_lines<NX>(bufA, bufB, twl, ncb * os, NX, tid, 256, wg_sync);
+    const float2* res = fft_lines<NX>(bufA, bufB, twl, ncb * os, LS, tid, 256, wg_sync);
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int x = tid + e * 256;
       if (x < NX) {
         for (int c = 0; c < ncb; ++c) {
           float2 v = make_float2(0.f, 0.f);
-          for (int s = 0; s < os; ++s) v = cadd(v, cmul(res[(c * os + s) * NX + x], twin[s * NX + x]));
+          const float2* rc = res + c * os * LS + fpad(x);
+          for (int s = 0; s < os; ++s) v = cadd(v, cmul(rc[s * LS], twin[s * NX + x]));
           // v holds conj of the cropped line; acc += conj(coil) * line
           const float2 cv = coils[((size_t)(n0 + c) * ny + y) * NX + x];
           acc[e] = cadd(acc[e], cconj(cmul(v, cv)));
@@ -231,12 +213,13 @@ __device__ inline float pe_post(int ky) {
 template <int NY>
 __device__ inline void load_z_lines(float2* A, const float2* __restrict__ Zp, int ksplit, size_t zstride, int l0,
                                     int nl, int tid) {
+  constexpr int LS = fline(NY);
   for (int i = tid; i < nl * NY; i += 256) {
-    const int y = i % NY;
+    const int li = i / NY, y = i - li * NY;
     const size_t g = (size_t)l0 * NY + i;
     float2 v = Zp[g];
     for (int ks = 1; ks < ksplit; ++ks) v = cadd(v, Zp[ks * zstride + g]);
-    A[i] = (y & 1) ? make_float2(-v.x, -v.y) : v;
+    A[li * LS + fpad(y)] = (y & 1) ? make_float2(-v.x, -v.y) : v;
   }
 }
 
@@ -244,21 +227,22 @@ template <int NY>
 __global__ __launch_bounds__(256) void k_pe_fwd(const float2* __restrict__ Zp, int ksplit, size_t zstride,
                                                 float2* __restrict__ out, const int* __restrict__ lines, int ms,
                                                 int nlines, int lpb, const float2* __restrict__ tw) {
+  constexpr int LS = fline(NY);
   extern __shared__ float2 sm[];
   const int tid = threadIdx.x;
   float2* twl = sm;
   float2* A = sm + NY;
-  float2* Bf = A + lpb * NY;
+  float2* Bf = A + lpb * LS;
   for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
   const int l0 = blockIdx.x * lpb;
   const int nl = min(lpb, nlines - l0);
   load_z_lines<NY>(A, Zp, ksplit, zstride, l0, nl, tid);
   __syncthreads();
-  const float2* res = fft_lines<NY>(A, Bf, twl, nl, NY, tid, 256, wg_sync);
+  const float2* res = fft_lines<NY>(A, Bf, twl, nl, LS, tid, 256, wg_sync);
   for (int i = tid; i < nl * ms; i += 256) {
     const int li = i / ms, m = i - li * ms;
     const int ky = lines[m];
-    out[(size_t)l0 * ms + i] = cscale(res[li * NY + ky], pe_post<NY>(ky));
+    out[(size_t)l0 * ms + i] = cscale(res[li * LS + fpad(ky)], pe_post<NY>(ky));
   }
 }
 
@@ -267,28 +251,29 @@ template <int NY>
 __global__ __launch_bounds__(256) void k_pe_adj(const float2* __restrict__ in, float2* __restrict__ Zt,
                                                 const int* __restrict__ lines, int ms, int nlines, int lpb, int K,
                                                 int kp, const float2* __restrict__ tw) {
+  constexpr int LS = fline(NY);
   extern __shared__ float2 sm[];
   const int tid = threadIdx.x;
   float2* twl = sm;
   float2* A = sm + NY;
-  float2* Bf = A + lpb * NY;
+  float2* Bf = A + lpb * LS;
   for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
   const int l0 = blockIdx.x * lpb;
   const int nl = min(lpb, nlines - l0);
-  for (int i = tid; i < nl * NY; i += 256) A[i] = make_float2(0.f, 0.f);
+  for (int i = tid; i < nl * LS; i += 256) A[i] = make_float2(0.f, 0.f);
   __syncthreads();
   for (int i = tid; i < nl * ms; i += 256) {
     const int li = i / ms, m = i - li * ms;
     const int ky = lines[m];
-    A[li * NY + ky] = cscale(cconj(in[(size_t)l0 * ms + i]), pe_post<NY>(ky));
+    A[li * LS + fpad(ky)] = cscale(cconj(in[(size_t)l0 * ms + i]), pe_post<NY>(ky));
   }
   __syncthreads();
-  const float2* res = fft_lines<NY>(A, Bf, twl, nl, NY, tid, 256, wg_sync);
+  const float2* res = fft_lines<NY>(A, Bf, twl, nl, LS, tid, 256, wg_sync);
   for (int i = tid; i < nl * NY; i += 256) {
     const int y = i / nl, li = i - y * nl;
     const int l = l0 + li;
     const int bp = l / K, k = l - bp * K;
-    float2 v = cconj(res[li * NY + y]);
+    float2 v = cconj(res[li * LS + fpad(y)]);
     if (y & 1) v = make_float2(-v.x, -v.y);
     Zt[((size_t)bp * NY + y) * kp + k] = v;
   }
@@ -300,30 +285,32 @@ __global__ __launch_bounds__(256) void k_pe_normal(const float2* __restrict__ Zp
                                                    float2* __restrict__ Zt, const float* __restrict__ maskf,
                                                    int nlines, int lpb, int K, int kp,
                                                    const float2* __restrict__ tw) {
+  constexpr int LS = fline(NY);
   extern __shared__ float2 sm[];
   const int tid = threadIdx.x;
   float2* twl = sm;
   float2* A = sm + NY;
-  float2* Bf = A + lpb * NY;
+  float2* Bf = A + lpb * LS;
   for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
   const int l0 = blockIdx.x * lpb;
   const int nl = min(lpb, nlines - l0);
   load_z_lines<NY>(A, Zp, ksplit, zstride, l0, nl, tid);
   __syncthreads();
-  float2* res = fft_lines<NY>(A, Bf, twl, nl, NY, tid, 256, wg_sync);
+  float2* res = fft_lines<NY>(A, Bf, twl, nl, LS, tid, 256, wg_sync);
   const float inv = 1.0f / (float)NY;
   for (int i = tid; i < nl * NY; i += 256) {
-    const int ky = i % NY;
-    res[i] = cconj(cscale(res[i], maskf[ky] * inv));
+    const int li = i / NY, ky = i - li * NY;
+    float2& v = res[li * LS + fpad(ky)];
+    v = cconj(cscale(v, maskf[ky] * inv));
   }
   __syncthreads();
   float2* other = (res == A) ? Bf : A;
-  const float2* res2 = fft_lines<NY>(res, other, twl, nl, NY, tid, 256, wg_sync);
+  const float2* res2 = fft_lines<NY>(res, other, twl, nl, LS, tid, 256, wg_sync);
   for (int i = tid; i < nl * NY; i += 256) {
     const int y = i / nl, li = i - y * nl;
     const int l = l0 + li;
     const int bp = l / K, k = l - bp * K;
-    float2 v = cconj(res2[li * NY + y]);
+    float2 v = cconj(res2[li * LS + fpad(y)]);
     if (y & 1) v = make_float2(-v.x, -v.y);
     Zt[((size_t)bp * NY + y) * kp + k] = v;
   }
@@ -331,7 +318,7 @@ __global__ __launch_bounds__(256) void k_pe_normal(const float2* __restrict__ Zp
 
 // ---------------------------------------------------------------------------
 // F3 on uncompressed columns W[(b,n)][y][t] (stride nt).  Work-group: one
-// (b, n) and `tb` consecutive t.  LDS lines padded to NY + 1.
+// (b, n) and `tb` consecutive t.
 // ---------------------------------------------------------------------------
 template <int NY, Store ST>
 __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, void* __restrict__ Wout,
@@ -339,8 +326,8 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
                                                  const int* __restrict__ lines, const float* __restrict__ maskf,
                                                  int ms, int nt, int tb, int mode, const float2* __restrict__ tw) {
   // mode 0: forward W -> out_s [(b,n)][ms][nt]; 1: adjoint in_s -> Wout; 2: normal Win -> Wout
+  constexpr int LS = fline(NY);
   extern __shared__ float2 sm[];
-  constexpr int LS = NY + 1;
   const int tid = threadIdx.x;
   float2* twl = sm;
   float2* A = sm + NY;
@@ -355,13 +342,13 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
     for (int i = tid; i < ms * ntb; i += 256) {
       const int m = i / ntb, c = i - m * ntb;
       const int ky = lines[m];
-      A[c * LS + ky] = cscale(cconj(in_s[(bn * ms + m) * nt + t0 + c]), pe_post<NY>(ky));
+      A[c * LS + fpad(ky)] = cscale(cconj(in_s[(bn * ms + m) * nt + t0 + c]), pe_post<NY>(ky));
     }
   } else {
     for (int i = tid; i < NY * ntb; i += 256) {
       const int y = i / ntb, c = i - y * ntb;
       float2 v = load_c<ST>(Win, (bn * NY + y) * nt + t0 + c);
-      A[c * LS + y] = (y & 1) ? make_float2(-v.x, -v.y) : v;
+      A[c * LS + fpad(y)] = (y & 1) ? make_float2(-v.x, -v.y) : v;
     }
   }
   __syncthreads();
@@ -370,7 +357,7 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
     for (int i = tid; i < ms * ntb; i += 256) {
       const int m = i / ntb, c = i - m * ntb;
       const int ky = lines[m];
-      out_s[(bn * ms + m) * nt + t0 + c] = cscale(res[c * LS + ky], pe_post<NY>(ky));
+      out_s[(bn * ms + m) * nt + t0 + c] = cscale(res[c * LS + fpad(ky)], pe_post<NY>(ky));
     }
     return;
   }
@@ -378,7 +365,8 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
     const float inv = 1.0f / (float)NY;
     for (int i = tid; i < ntb * NY; i += 256) {
       const int c = i / NY, ky = i - c * NY;
-      res[c * LS + ky] = cconj(cscale(res[c * LS + ky], maskf[ky] * inv));
+      float2& v = res[c * LS + fpad(ky)];
+      v = cconj(cscale(v, maskf[ky] * inv));
     }
     __syncthreads();
     float2* other = (res == A) ? Bf : A;
@@ -386,215 +374,9 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
   }
   for (int i = tid; i < NY * ntb; i += 256) {
     const int y = i / ntb, c = i - y * ntb;
-    float2 v = cconj(res[c * LS + y]);
+    float2 v = cconj(res[c * LS + fpad(y)]);
     if (y & 1) v = make_float2(-v.x, -v.y);
     store_c<ST>(Wout, (bn * NY + y) * nt + t0 + c, v);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Group contraction on FP32 MFMA (v_mfma_f32_16x16x4_f32).
-//
-// A complex product C = A B is carried as one real product of the expanded
-// matrices [[Ar, -Ai], [Ai, Ar]] acting on interleaved (re, im) columns, so
-// both operands are read straight from their natural interleaved layouts.
-// Both operands are walked along the contraction index kk with one float4
-// per lane: in a block of 16 kk, lane (i, q) (i = lane % 16, q = lane / 16)
-// holds kk = kb + 4q .. kb + 4q + 3 of its row i and feeds element e to the
-// e-th MFMA, so the four MFMAs together cover all 16 kk.
-// Work-group 256 = 2 x 2 waves, wave tile 32 x 32, work-group tile 64 x 64.
-// ---------------------------------------------------------------------------
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-struct GemmCompressArgs {
-  const float* A;   // [G][M][KD], M = 2K rows (k, re/im), KD = 2 ns
-  const float* in;  // float view of [B][nc][N][nt] complex
-  float2* out;      // [ksplit][B][np][K][N]
-  const int* pgroup;
-  int M, N, KD, nc, nt, P, np, K, B, ksplit, kchunk;
-  size_t split_stride;
-};
-
-__global__ __launch_bounds__(256) void k_gemm_compress_f32(GemmCompressArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lq = lane >> 4;
-  const int tiles_n = (a.N + 63) / 64, tiles_m = (a.M + 63) / 64;
-  const int total = tiles_n * tiles_m * a.B * a.np * a.ksplit;
-  const int logical = xcd_logical(blockIdx.x, total);
-  const int tn = logical % tiles_n;
-  int rest = logical / tiles_n;
-  const int tm = rest % tiles_m;
-  const int z = rest / tiles_m;
-  const int ks = z % a.ksplit, bp = z / a.ksplit;
-  const int b = bp / a.np, p = bp - b * a.np;
-  const int g = a.pgroup[p];
-  const int row0 = tm * 64 + (wave >> 1) * 32;
-  const int col0 = tn * 64 + (wave & 1) * 32;
-  const int twoP = 2 * a.P;
-  const size_t coil_stride = (size_t)a.N * a.nt * 2;
-
-  const float* arow[2];
-  bool va[2];
-  const float* brow[2];
-  bool vb[2];
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    const int r = row0 + 16 * m + li;
-    va[m] = r < a.M;
-    arow[m] = a.A + ((size_t)g * a.M + (va[m] ? r : 0)) * a.KD;
-    const int c = col0 + 16 * m + li;
-    vb[m] = c < a.N;
-    brow[m] = a.in + (((size_t)b * a.nc) * a.N + (vb[m] ? c : 0)) * a.nt * 2 + (size_t)p * twoP;
-  }
-  floatx4 acc[2][2];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[m][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  const int kbeg = ks * a.kchunk;
-  const int kend = min(a.KD, kbeg + a.kchunk);
-  for (int kb = kbeg; kb < kend; kb += 16) {
-    const int kk = kb + 4 * lq;
-    const bool vk = kk < kend;
-    const int n = kk / twoP;
-    const int jj = kk - n * twoP;
-    floatx4 av[2], bv[2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      av[m] = (va[m] && vk) ? *reinterpret_cast<const floatx4*>(arow[m] + kk) : floatx4{0.f, 0.f, 0.f, 0.f};
-      bv[m] = (vb[m] && vk) ? *reinterpret_cast<const floatx4*>(brow[m] + n * coil_stride + jj)
-                            : floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m][e], bv[c][e], acc[m][c], 0, 0, 0);
-  }
-  // acc[m][c][r] = C[row0 + 16 m + 4 lq + r][col0 + 16 c + li]; rows pair up as (k, re), (k, im).
-  float2* out = a.out + ks * a.split_stride + ((size_t)b * a.np + p) * a.K * a.N;
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int row = row0 + 16 * m + 4 * lq;
-      const int col = col0 + 16 * c + li;
-      if (col < a.N) {
-        if (row < a.M) out[(size_t)(row >> 1) * a.N + col] = make_float2(acc[m][c][0], acc[m][c][1]);
-        if (row + 2 < a.M) out[(size_t)((row >> 1) + 1) * a.N + col] = make_float2(acc[m][c][2], acc[m][c][3]);
-      }
-    }
-}
-
-struct GemmExpandArgs {
-  const float* Zt;  // [B][np][ny][KD] floats, KD = 2 kp
-  const float* AH;  // [G][N][KD], N = 2 ns
-  void* W;          // [B][nc][ny][nt] complex (storage per Store)
-  const int* pgroup;
-  int M, N, KD, nc, nt, P, np, B;
-};
-
-template <Store ST>
-__global__ __launch_bounds__(256) void k_gemm_expand_f32(GemmExpandArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lq = lane >> 4;
-  const int tiles_n = (a.N + 63) / 64, tiles_m = (a.M + 63) / 64;
-  const int total = tiles_n * tiles_m * a.B * a.np;
-  const int logical = xcd_logical(blockIdx.x, total);
-  const int tn = logical % tiles_n;
-  int rest = logical / tiles_n;
-  const int tm = rest % tiles_m;
-  const int bp = rest / tiles_m;
-  const int b = bp / a.np, p = bp - b * a.np;
-  const int g = a.pgroup[p];
-  const int row0 = tm * 64 + (wave >> 1) * 32;
-  const int col0 = tn * 64 + (wave & 1) * 32;
-
-  const float* arow[2];
-  bool va[2];
-  const float* brow[2];
-  bool vb[2];
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    const int r = row0 + 16 * m + li;
-    va[m] = r < a.M;
-    arow[m] = a.Zt + ((size_t)bp * a.M + (va[m] ? r : 0)) * a.KD;
-    const int c = col0 + 16 * m + li;
-    vb[m] = c < a.N;
-    brow[m] = a.AH + ((size_t)g * a.N + (vb[m] ? c : 0)) * a.KD;
-  }
-  floatx4 acc[2][2];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[m][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int kb = 0; kb < a.KD; kb += 16) {
-    const int kk = kb + 4 * lq;
-    floatx4 av[2], bv[2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      av[m] = va[m] ? *reinterpret_cast<const floatx4*>(arow[m] + kk) : floatx4{0.f, 0.f, 0.f, 0.f};
-      bv[m] = vb[m] ? *reinterpret_cast<const floatx4*>(brow[m] + kk) : floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m][e], bv[c][e], acc[m][c], 0, 0, 0);
-  }
-  // C[y][col], col = (n, j, re/im) -> W[b][n][y][p P + j]
-  const int twoP = 2 * a.P;
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int col = col0 + 16 * c + li;
-    if (col >= a.N) continue;
-    const int n = col / twoP, jj = col - n * twoP;
-    const size_t cbase = ((size_t)b * a.nc + n) * a.M;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int y = row0 + 16 * m + 4 * lq + r;
-        if (y < a.M) {
-          const size_t fi = (cbase + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
-          if constexpr (ST == Store::F32) {
-            reinterpret_cast<float*>(a.W)[fi] = acc[m][c][r];
-          } else if constexpr (ST == Store::BF16) {
-            reinterpret_cast<uint16_t*>(a.W)[fi] = (uint16_t)f32_to_bf16_bits(acc[m][c][r]);
-          } else {
-            reinterpret_cast<uint16_t*>(a.W)[fi] = (uint16_t)f32_to_f16_bits(acc[m][c][r]);
-          }
-        }
-      }
-  }
-}
-
-// Real forms of the bank: Aexp [G][2K][2ns] (compressing), AH [G][2ns][2kp] (expanding).
-__global__ void k_expand_bank(const double2* __restrict__ A, float* __restrict__ Aexp, float* __restrict__ AH, int G,
-                              int K, int kp, int ns) {
-  const size_t total = (size_t)G * K * ns;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx % ns);
-    const int k = (int)((idx / ns) % K);
-    const int g = (int)(idx / ((size_t)ns * K));
-    const double2 v = A[idx];
-    const float ar = (float)v.x, ai = (float)v.y;
-    float* e0 = Aexp + ((size_t)g * 2 * K + 2 * k) * 2 * ns;
-    float* e1 = e0 + 2 * ns;
-    e0[2 * i] = ar;
-    e0[2 * i + 1] = -ai;
-    e1[2 * i] = ai;
-    e1[2 * i + 1] = ar;
-    float* h0 = AH + ((size_t)g * 2 * ns + 2 * i) * 2 * kp;
-    float* h1 = h0 + 2 * kp;
-    h0[2 * k] = ar;
-    h0[2 * k + 1] = ai;
-    h1[2 * k] = -ai;
-    h1[2 * k + 1] = ar;
   }
 }
 
@@ -628,10 +410,10 @@ struct ReadoutFwd {
     static int run(const Plan& pl, const float2* img) {
       StageScope sc(pl, GPJC_STAGE_READOUT_FWD);
       const int rows = pl.f1_rows;
-      const size_t lds = (size_t)(NX + 2 * rows * pl.os * NX) * sizeof(float2);
+      const size_t lds = (size_t)(NX + 2 * rows * pl.os * fline(NX)) * sizeof(float2);
       dim3 grid((pl.ny + rows - 1) / rows, pl.nc, pl.B);
       hipLaunchKernelGGL((k_readout_fwd<NX, ST>), grid, dim3(256), lds, pl.stream, img, pl.coils, pl.psfp, pl.twin,
-                         pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, rows);
+                         pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, 1.0f / pl.os, rows);
       GPJC_HIP(hipGetLastError());
       return GPJC_OK;
     }
@@ -644,10 +426,11 @@ struct ReadoutAdj {
   struct L {
     static int run(const Plan& pl) {
       StageScope sc(pl, GPJC_STAGE_READOUT_ADJ);
-      const size_t lds = (size_t)(NX + 2 * pl.f1h_cb * pl.os * NX) * sizeof(float2);
+      const size_t lds = (size_t)(NX + 2 * pl.f1h_cb * pl.os * fline(NX)) * sizeof(float2);
       dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
       hipLaunchKernelGGL((k_readout_adj<NX, ST>), grid, dim3(256), lds, pl.stream, (const void*)pl.W, pl.coils,
-                         pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, pl.f1h_cb, pl.f1h_cpc, pl.B);
+                         pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, 1.0f / pl.os, pl.f1h_cb, pl.f1h_cpc,
+                         pl.B);
       GPJC_HIP(hipGetLastError());
       return GPJC_OK;
     }
@@ -659,7 +442,7 @@ struct PeFwd {
   static int run(const Plan& pl, float2* out) {
     StageScope sc(pl, GPJC_STAGE_PE_FWD);
     const int nlines = pl.B * pl.np * pl.K;
-    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * NY) * sizeof(float2);
+    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
     const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
     hipLaunchKernelGGL(k_pe_fwd<NY>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream, pl.Zp,
                        pl.gemm_ksplit, zs, out, pl.lines, pl.ms, nlines, pl.f3_lpb, pl.tw_y);
@@ -673,7 +456,7 @@ struct PeAdj {
   static int run(const Plan& pl, const float2* in) {
     StageScope sc(pl, GPJC_STAGE_PE_ADJ);
     const int nlines = pl.B * pl.np * pl.K;
-    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * NY) * sizeof(float2);
+    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
     hipLaunchKernelGGL(k_pe_adj<NY>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream, in,
                        pl.Zt, pl.lines, pl.ms, nlines, pl.f3_lpb, pl.K, pl.Kp, pl.tw_y);
     GPJC_HIP(hipGetLastError());
@@ -686,7 +469,7 @@ struct PeNormal {
   static int run(const Plan& pl) {
     StageScope sc(pl, GPJC_STAGE_PE_NORMAL);
     const int nlines = pl.B * pl.np * pl.K;
-    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * NY) * sizeof(float2);
+    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
     const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
     hipLaunchKernelGGL(k_pe_normal<NY>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream,
                        pl.Zp, pl.gemm_ksplit, zs, pl.Zt, pl.maskf, nlines, pl.f3_lpb, pl.K, pl.Kp, pl.tw_y);
@@ -702,7 +485,7 @@ struct PeCols {
     static int run(const Plan& pl, int mode, const float2* in_s, float2* out_s) {
       StageScope sc(pl, GPJC_STAGE_PE_COLS);
       const int tb = pl.f3_tb;
-      const size_t lds = (size_t)(NY + 2 * tb * (NY + 1)) * sizeof(float2);
+      const size_t lds = (size_t)(NY + 2 * tb * fline(NY)) * sizeof(float2);
       dim3 grid((pl.nt + tb - 1) / tb, pl.B * pl.nc);
       hipLaunchKernelGGL((k_pe_cols<NY, ST>), grid, dim3(256), lds, pl.stream, (const void*)pl.W, (void*)pl.W, in_s,
                          out_s, pl.lines, pl.maskf, pl.ms, pl.nt, tb, mode, pl.tw_y);
@@ -749,72 +532,6 @@ int launch_pe_cols_adj(const Plan& pl, const float2* in) {
 }
 int launch_pe_cols_normal(const Plan& pl) {
   return dispatch_n<PeCols<Store::F32>::L>(pl.ny, pl, 2, (const float2*)nullptr, (float2*)nullptr);
-}
-
-static int gemm_compress(const Plan& pl, const float* in, int ncol, float2* out, int ksplit) {
-  StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS);
-  GemmCompressArgs a;
-  a.A = pl.Aexp;
-  a.in = in;
-  a.out = out;
-  a.pgroup = pl.pgroup;
-  a.M = 2 * pl.K;
-  a.N = ncol;
-  a.KD = 2 * pl.ns;
-  a.nc = pl.nc;
-  a.nt = pl.nt;
-  a.P = pl.P;
-  a.np = pl.np;
-  a.K = pl.K;
-  a.B = pl.B;
-  a.ksplit = ksplit;
-  a.kchunk = ((a.KD + ksplit - 1) / ksplit + 15) / 16 * 16;
-  a.split_stride = (size_t)pl.B * pl.np * pl.K * ncol;
-  const int total = ((ncol + 63) / 64) * ((a.M + 63) / 64) * pl.B * pl.np * ksplit;
-  hipLaunchKernelGGL(k_gemm_compress_f32, dim3(total), dim3(256), 0, pl.stream, a);
-  GPJC_HIP(hipGetLastError());
-  return GPJC_OK;
-}
-
-int launch_group_compress(const Plan& pl, Store st) {
-  if (st != Store::F32) return fail(GPJC_E_UNSUPPORTED, "reduced-precision contraction not built");
-  return gemm_compress(pl, reinterpret_cast<const float*>(pl.W), pl.ny, pl.Zp, pl.gemm_ksplit);
-}
-
-int launch_compress_data(const Plan& pl, const float2* ksp, float2* out) {
-  return gemm_compress(pl, reinterpret_cast<const float*>(ksp), pl.ms, out, 1);
-}
-
-int launch_group_expand(const Plan& pl, Store st) {
-  StageScope sc(pl, GPJC_STAGE_GROUP_EXPAND);
-  GemmExpandArgs a;
-  a.Zt = reinterpret_cast<const float*>(pl.Zt);
-  a.AH = pl.AH;
-  a.W = pl.W;
-  a.pgroup = pl.pgroup;
-  a.M = pl.ny;
-  a.N = 2 * pl.ns;
-  a.KD = 2 * pl.Kp;
-  a.nc = pl.nc;
-  a.nt = pl.nt;
-  a.P = pl.P;
-  a.np = pl.np;
-  a.B = pl.B;
-  const int total = ((a.N + 63) / 64) * ((a.M + 63) / 64) * pl.B * pl.np;
-  if (st != Store::F32) return fail(GPJC_E_UNSUPPORTED, "reduced-precision contraction not built");
-  hipLaunchKernelGGL(k_gemm_expand_f32<Store::F32>, dim3(total), dim3(256), 0, pl.stream, a);
-  GPJC_HIP(hipGetLastError());
-  return GPJC_OK;
-}
-
-int launch_expand_bank(Plan& pl) {
-  GPJC_HIP(hipMemsetAsync(pl.AH, 0, (size_t)pl.G * 2 * pl.ns * 2 * pl.Kp * sizeof(float), pl.stream));
-  const size_t total = (size_t)pl.G * pl.K * pl.ns;
-  const int blocks = (int)std::min<size_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_expand_bank, dim3(blocks), dim3(256), 0, pl.stream, pl.A128, pl.Aexp, pl.AH, pl.G, pl.K,
-                     pl.Kp, pl.ns);
-  GPJC_HIP(hipGetLastError());
-  return GPJC_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -56,6 +56,8 @@ struct Plan {
   int f3_lpb = 1;           // phase-encode lines per workgroup
   int f3_tb = 1;            // readout columns per uncompressed phase-encode workgroup
   int gemm_ksplit = 1;      // contraction split of the compressing group GEMM
+  int gemm_cvar = 0;        // tile shape of the compressing contraction
+  int gemm_evar = 0;        // tile shape of the expanding contraction
 
   // device: geometry tables
   float2* coils = nullptr;  // [nc][ny][nx]
@@ -67,6 +69,7 @@ struct Plan {
   int* lines = nullptr;     // [ms]
   int* pgroup = nullptr;    // [np]
   float* maskf = nullptr;   // [ny] 0 / 1
+  float* zeros = nullptr;   // [64] zero-filled; source of masked-out loads
 
   // device: compression bank
   bool have_bank = false;
@@ -126,6 +129,12 @@ int launch_pe_cols_fwd(const Plan& pl, float2* out);
 int launch_pe_cols_adj(const Plan& pl, const float2* in);
 int launch_pe_cols_normal(const Plan& pl);
 int launch_expand_bank(Plan& pl);
+// Work-group tile of the compressing contraction (rows of 2K x columns).
+int compress_tile_rows(const Plan& pl);
+int gemm_compress_variants();
+int gemm_expand_variants();
+constexpr int kMaxKsplit = 8;
+int compress_tile_cols(const Plan& pl);
 int launch_compress_data(const Plan& pl, const float2* ksp, float2* out);
 
 // Whole operators: images in, images (as partial sums in pl.part) or data out.

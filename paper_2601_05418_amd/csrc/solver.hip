@@ -303,61 +303,86 @@ __device__ inline void haar_tile(float2 (&c)[1 << LEV][1 << LEV], bool inverse) 
   }
 }
 
-// v = y - (A y - b) / L; x = W^H soft(W v, thr) (final low-pass untouched);
-// y <- x + mom (x - x_prev); x_prev <- x.
+// Haar transform of a 2^L x 2^L tile held one coefficient per lane (lane
+// e = i * S + j for tile row i, column j).  Level l combines lanes whose row
+// and column are multiples of 2^l: along x with the lane 2^l columns away,
+// then along y with the lane 2^l rows away; the average stays on the lane
+// with the lower index, the difference moves to the other.  After L levels
+// lane 0 holds the tile's low-pass coefficient and every other lane one
+// detail coefficient -- the Mallat coefficient set, stored permuted.
 template <int LEV>
-__global__ __launch_bounds__(64) void k_fista_step(const float2* __restrict__ part, int nchunk,
-                                                   const float2* __restrict__ bvec, float2* __restrict__ yv,
-                                                   float2* __restrict__ xprev, int nx, int ny, int B, float invL,
-                                                   float thr, float mom) {
+__device__ inline float2 haar_lanes(float2 v, int i, int j, bool inverse) {
   constexpr int S = 1 << LEV;
+  constexpr float rs = 0.70710678118654752440f;
+  auto step = [&](int mask, bool hi, bool active) {
+    const float2 o = make_float2(__shfl_xor(v.x, mask, 64), __shfl_xor(v.y, mask, 64));
+    if (!active) return;
+    if (!inverse) v = hi ? cscale(csub(o, v), rs) : cscale(cadd(v, o), rs);
+    else v = hi ? cscale(csub(o, v), rs) : cscale(cadd(v, o), rs);
+  };
+  if (!inverse) {
+#pragma unroll
+    for (int l = 0; l < LEV; ++l) {
+      const int st = 1 << l;
+      const bool act = (i % st == 0) && (j % st == 0);
+      step(st, (j & st) != 0, act);       // along x
+      step(st * S, (i & st) != 0, act);   // along y
+    }
+  } else {
+#pragma unroll
+    for (int l = LEV - 1; l >= 0; --l) {
+      const int st = 1 << l;
+      const bool act = (i % st == 0) && (j % st == 0);
+      step(st * S, (i & st) != 0, act);   // along y
+      step(st, (j & st) != 0, act);       // along x
+    }
+  }
+  return v;
+}
+
+// v = y - (A y - b) / L; x = W^H soft(W v, thr) (final low-pass untouched);
+// y <- x + mom (x - x_prev); x_prev <- x.  One lane per pixel, 2^L x 2^L
+// pixels per tile, whole tiles per wave.
+template <int LEV>
+__global__ __launch_bounds__(256) void k_fista_step(const float2* __restrict__ part, int nchunk,
+                                                    const float2* __restrict__ bvec, float2* __restrict__ yv,
+                                                    float2* __restrict__ xprev, int nx, int ny, int B, float invL,
+                                                    float thr, float mom) {
+  constexpr int S = 1 << LEV, T = S * S;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tile = gid / T, e = gid - tile * T;
+  const int i = e / S, j = e - i * S;
   const int tx_n = nx / S, ty_n = ny / S;
-  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tile >= B * tx_n * ty_n) return;
-  const int b = tile / (tx_n * ty_n);
-  const int rem = tile - b * tx_n * ty_n;
+  const int ntiles = B * tx_n * ty_n;
+  const bool valid = tile < ntiles;
+  const int tt = valid ? tile : 0;
+  const int b = tt / (tx_n * ty_n);
+  const int rem = tt - b * tx_n * ty_n;
   const int ty = rem / tx_n, tx = rem - ty * tx_n;
   const size_t n = (size_t)B * nx * ny;
-  float2 c[S][S];
-#pragma unroll
-  for (int i = 0; i < S; ++i)
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const size_t idx = ((size_t)b * ny + ty * S + i) * nx + tx * S + j;
-      const float2 g = csub(sum_part(part, nchunk, n, idx), bvec[idx]);
-      const float2 yy = yv[idx];
-      c[i][j] = make_float2(fmaf(-invL, g.x, yy.x), fmaf(-invL, g.y, yy.y));
-    }
-  haar_tile<LEV>(c, false);
-#pragma unroll
-  for (int i = 0; i < S; ++i)
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      if (i == 0 && j == 0) continue;
-      const float2 z = c[i][j];
-      const float mag = sqrtf(z.x * z.x + z.y * z.y);
-      const float sc = mag > thr ? 1.0f - thr / mag : 0.0f;
-      c[i][j] = cscale(z, sc);
-    }
-  haar_tile<LEV>(c, true);
-#pragma unroll
-  for (int i = 0; i < S; ++i)
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const size_t idx = ((size_t)b * ny + ty * S + i) * nx + tx * S + j;
-      const float2 xn = c[i][j], xo = xprev[idx];
-      yv[idx] = make_float2(fmaf(mom, xn.x - xo.x, xn.x), fmaf(mom, xn.y - xo.y, xn.y));
-      xprev[idx] = xn;
-    }
+  const size_t idx = ((size_t)b * ny + ty * S + i) * nx + tx * S + j;
+  const float2 g = csub(sum_part(part, nchunk, n, idx), bvec[idx]);
+  const float2 yy = yv[idx];
+  float2 c = make_float2(fmaf(-invL, g.x, yy.x), fmaf(-invL, g.y, yy.y));
+  c = haar_lanes<LEV>(c, i, j, false);
+  if (e != 0) {
+    const float mag = sqrtf(c.x * c.x + c.y * c.y);
+    c = cscale(c, mag > thr ? 1.0f - thr / mag : 0.0f);
+  }
+  c = haar_lanes<LEV>(c, i, j, true);
+  if (valid) {
+    const float2 xo = xprev[idx];
+    yv[idx] = make_float2(fmaf(mom, c.x - xo.x, c.x), fmaf(mom, c.y - xo.y, c.y));
+    xprev[idx] = c;
+  }
 }
 
 template <int LEV>
 static int launch_fista_step(const Plan& pl, float invL, float thr, float mom) {
   StageScope sc(pl, GPJC_STAGE_SOLVER);
-  constexpr int S = 1 << LEV;
-  const int tiles = pl.B * (pl.nx / S) * (pl.ny / S);
-  hipLaunchKernelGGL(k_fista_step<LEV>, dim3((tiles + 63) / 64), dim3(64), 0, pl.stream, pl.part, pl.f1h_nchunk,
-                     pl.vb, pl.vp, pl.vx, pl.nx, pl.ny, pl.B, invL, thr, mom);
+  const size_t lanes = pl.img_elems();
+  hipLaunchKernelGGL(k_fista_step<LEV>, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, pl.stream, pl.part,
+                     pl.f1h_nchunk, pl.vb, pl.vp, pl.vx, pl.nx, pl.ny, pl.B, invL, thr, mom);
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
 }

@@ -11,12 +11,17 @@
 template <int N>
 static double check(std::mt19937& rng) {
   const int nl = 3;
+  const int ls = gpjc::fline(N);
   std::normal_distribution<float> nd;
-  std::vector<float2> a(nl * N), b(nl * N), tw(N);
+  std::vector<float2> a(nl * ls), b(nl * ls), tw(N), in(nl * N);
   for (int m = 0; m < N; ++m) tw[m] = make_float2((float)std::cos(-2 * M_PI * m / N), (float)std::sin(-2 * M_PI * m / N));
-  for (auto& v : a) v = make_float2(nd(rng), nd(rng));
-  std::vector<float2> in = a;
-  float2* res = gpjc::fft_lines<N>(a.data(), b.data(), tw.data(), nl, N, 0, 1, [] {});
+  for (auto& v : in) v = make_float2(nd(rng), nd(rng));
+  for (int l = 0; l < nl; ++l)
+    for (int n = 0; n < N; ++n) a[l * ls + gpjc::fpad(n)] = in[l * N + n];
+  float2* res_buf = gpjc::fft_lines<N>(a.data(), b.data(), tw.data(), nl, ls, 0, 1, [] {});
+  std::vector<float2> res(nl * N);
+  for (int l = 0; l < nl; ++l)
+    for (int n = 0; n < N; ++n) res[l * N + n] = res_buf[l * ls + gpjc::fpad(n)];
   double err = 0, ref = 0;
   for (int l = 0; l < nl; ++l)
     for (int k = 0; k < N; ++k) {
