@@ -55,7 +55,13 @@ def stage_work(g, stage, prec, ksplit_read=1):
     B, nx, ny, nc, nt = 1, g.nx, g.ny, g.nc, g.nt
     wbytes = 8 if prec == "fp32" else 4
     if stage in ("group_compress", "group_expand"):
-        return "mfma", 8.0 * B * g.k * nc * nt * ny, "flop"
+        if prec == "fp32":  # arithmetic intensity ~48 flop/B, above the FP32 MFMA ridge (~20)
+            return "mfma", 8.0 * B * g.k * nc * nt * ny, "flop"
+        # 16-bit operands: ~90 flop/B, far below the BF16/FP16 ridge (~300): HBM-bound.
+        # W (16-bit) once, the 16-bit real-form bank once, Z in FP32 (compress) / 16-bit (expand).
+        bank = 2.0 * g.n_groups * (2 * g.k) * (2 * g.ns)
+        z = (8.0 if stage == "group_compress" else 4.0) * B * g.n_patches * g.k * ny
+        return "hbm", wbytes * B * nc * ny * nt + bank + z, "byte"
     if stage in ("readout_fwd", "readout_adj"):
         return "hbm", 8.0 * (B * nx * ny + nc * nx * ny + ny * nt) + wbytes * B * nc * ny * nt, "byte"
     if stage == "pe_normal":

@@ -52,10 +52,15 @@ typedef struct { float re, im; } gpjc_c64;
 typedef struct { double re, im; } gpjc_c128;
 
 /* Arithmetic of the group contraction and PSF product inside the operator.
- * FP32: everything FP32 (FP32 MFMA).  BF16 / FP16: the hybrid readout data W
- * and the compression matrices are rounded to BF16 / FP16 (round to nearest
- * even) and contracted on MFMA with FP32 accumulation; FFTs and the
- * phase-encode stage stay FP32. */
+ * FP32: everything FP32 (FP32 MFMA).  BF16 / FP16 (compressed plans with
+ * patch_len % 4 == 0, else GPJC_E_UNSUPPORTED): the operands of both group
+ * contractions are rounded to BF16 / FP16 (round to nearest even) and
+ * contracted on MFMA with FP32 accumulation -- the compression matrices, the
+ * hybrid data W after the PSF product (forward) and after the expanding
+ * contraction (adjoint), and the phase-encode output Z^T feeding the
+ * expanding contraction.  FFTs, coil products and the phase-encode stage
+ * compute in FP32.  FP16 needs every stored value below 65504 in magnitude
+ * (non-finite results surface as GPJC_E_NUMERIC in the solvers). */
 typedef enum { GPJC_FP32 = 0, GPJC_BF16 = 1, GPJC_FP16 = 2 } gpjc_prec;
 
 enum {
@@ -127,8 +132,11 @@ int gpjc_normal(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gp
  * d_y in gpjc_forward's output layout, d_x [B][ny][nx] holds x0 on entry and
  * the result on exit; all B images form one joint system.  Dot products are
  * accumulated in FP64 with a fixed reduction order.  With prec != FP32 and
- * refine_every > 0 the residual is recomputed every refine_every iterations
- * as E'^H y - E'^H E' x with the FP32 operator and the search restarted.
+ * refine_every > 0, b = E'^H y and r0 come from the FP32 operator, the
+ * search directions from the prec operator, and every refine_every
+ * iterations the residual is recomputed as b - E'^H E' x with the FP32
+ * operator and the search restarted (iterative refinement: the iterates
+ * converge to the FP32 solution).
  * h_resid [iters+1] (optional) receives ||r_k||_2; synchronises if given.
  * GPJC_E_NUMERIC if a residual or step is NaN/Inf (checked at the end). */
 int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x,

@@ -54,10 +54,11 @@ static void free_plan(Plan* pl) {
                   pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->red,  pl->hist,  pl->flag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 2; ++i) {
     if (pl->Aexp16[i]) (void)hipFree(pl->Aexp16[i]);
     if (pl->AH16[i]) (void)hipFree(pl->AH16[i]);
   }
+  if (pl->Zt16) (void)hipFree(pl->Zt16);
   for (hipEvent_t e : pl->timing.ev) (void)hipEventDestroy(e);
   pl->timing.ev.clear();
 }
@@ -208,6 +209,14 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
     GPJC_TRY(dalloc(&pl.Zp, (size_t)kMaxKsplit * pl.B * pl.np * pl.K * pl.ny));
     GPJC_TRY(dalloc(&pl.Zt, (size_t)pl.B * pl.np * pl.ny * pl.Kp));
     GPJC_HIP(hipMemsetAsync(pl.Zt, 0, sizeof(float2) * (size_t)pl.B * pl.np * pl.ny * pl.Kp, stream));
+    if (pl.P % 4 == 0) {  // 16-bit contractions: bank copies and a 16-bit Z^T (pads stay zero)
+      for (int i = 0; i < 2; ++i) {
+        GPJC_TRY(dalloc(&pl.Aexp16[i], (size_t)pl.G * 2 * pl.K * 2 * pl.ns));
+        GPJC_TRY(dalloc(&pl.AH16[i], (size_t)pl.G * 2 * pl.ns * 2 * pl.Kp));
+      }
+      GPJC_TRY(dalloc(&pl.Zt16, (size_t)pl.B * pl.np * pl.ny * pl.Kp));
+      GPJC_HIP(hipMemsetAsync(pl.Zt16, 0, sizeof(uint32_t) * (size_t)pl.B * pl.np * pl.ny * pl.Kp, stream));
+    }
     GPJC_HIP(hipMemcpyAsync(pl.pgroup, pl.pgroup_h.data(), sizeof(int) * pl.np, hipMemcpyHostToDevice, stream));
   }
   std::vector<float> mf(pl.ny);
@@ -256,6 +265,8 @@ static int check_prec(const Plan& pl, int prec, Store* st) {
   if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
   if (prec != GPJC_FP32 && !pl.compressed)
     return fail(GPJC_E_UNSUPPORTED, "the uncompressed operator is FP32 only");
+  if (prec != GPJC_FP32 && pl.P % 4)
+    return fail(GPJC_E_UNSUPPORTED, "16-bit contractions need patch_len divisible by 4");
   *st = prec == GPJC_FP32 ? Store::F32 : prec == GPJC_BF16 ? Store::BF16 : Store::F16;
   return GPJC_OK;
 }

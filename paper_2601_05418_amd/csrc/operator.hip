@@ -246,9 +246,9 @@ __global__ __launch_bounds__(256) void k_pe_fwd(const float2* __restrict__ Zp, i
   }
 }
 
-// Adjoint: zero-fill, inverse DFT; writes Zt[(b,p)][y][k] (k contiguous, stride kp).
-template <int NY>
-__global__ __launch_bounds__(256) void k_pe_adj(const float2* __restrict__ in, float2* __restrict__ Zt,
+// Adjoint: zero-fill, inverse DFT; writes Zt[(b,p)][y][k] (k contiguous, stride kp), stored as ST.
+template <int NY, Store ST>
+__global__ __launch_bounds__(256) void k_pe_adj(const float2* __restrict__ in, void* __restrict__ Zt,
                                                 const int* __restrict__ lines, int ms, int nlines, int lpb, int K,
                                                 int kp, const float2* __restrict__ tw) {
   constexpr int LS = fline(NY);
@@ -275,14 +275,14 @@ __global__ __launch_bounds__(256) void k_pe_adj(const float2* __restrict__ in, f
     const int bp = l / K, k = l - bp * K;
     float2 v = cconj(res[li * LS + fpad(y)]);
     if (y & 1) v = make_float2(-v.x, -v.y);
-    Zt[((size_t)bp * NY + y) * kp + k] = v;
+    store_c<ST>(Zt, ((size_t)bp * NY + y) * kp + k, v);
   }
 }
 
 // Normal y-stage: (-1)^y conj(FFT(conj(mask/Ny * FFT((-1)^y z)))) -> Zt.
-template <int NY>
+template <int NY, Store ST>
 __global__ __launch_bounds__(256) void k_pe_normal(const float2* __restrict__ Zp, int ksplit, size_t zstride,
-                                                   float2* __restrict__ Zt, const float* __restrict__ maskf,
+                                                   void* __restrict__ Zt, const float* __restrict__ maskf,
                                                    int nlines, int lpb, int K, int kp,
                                                    const float2* __restrict__ tw) {
   constexpr int LS = fline(NY);
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_pe_normal(const float2* __restrict__ Zp
     const int bp = l / K, k = l - bp * K;
     float2 v = cconj(res2[li * LS + fpad(y)]);
     if (y & 1) v = make_float2(-v.x, -v.y);
-    Zt[((size_t)bp * NY + y) * kp + k] = v;
+    store_c<ST>(Zt, ((size_t)bp * NY + y) * kp + k, v);
   }
 }
 
@@ -451,31 +451,43 @@ struct PeFwd {
   }
 };
 
-template <int NY>
+// Z^T in the storage the expanding contraction reads for precision st.
+static void* zt_for(const Plan& pl, Store st) {
+  return st == Store::F32 ? static_cast<void*>(pl.Zt) : static_cast<void*>(pl.Zt16);
+}
+
+template <Store ST>
 struct PeAdj {
-  static int run(const Plan& pl, const float2* in) {
-    StageScope sc(pl, GPJC_STAGE_PE_ADJ);
-    const int nlines = pl.B * pl.np * pl.K;
-    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
-    hipLaunchKernelGGL(k_pe_adj<NY>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream, in,
-                       pl.Zt, pl.lines, pl.ms, nlines, pl.f3_lpb, pl.K, pl.Kp, pl.tw_y);
-    GPJC_HIP(hipGetLastError());
-    return GPJC_OK;
-  }
+  template <int NY>
+  struct L {
+    static int run(const Plan& pl, const float2* in) {
+      StageScope sc(pl, GPJC_STAGE_PE_ADJ);
+      const int nlines = pl.B * pl.np * pl.K;
+      const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
+      hipLaunchKernelGGL((k_pe_adj<NY, ST>), dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream,
+                         in, zt_for(pl, ST), pl.lines, pl.ms, nlines, pl.f3_lpb, pl.K, pl.Kp, pl.tw_y);
+      GPJC_HIP(hipGetLastError());
+      return GPJC_OK;
+    }
+  };
 };
 
-template <int NY>
+template <Store ST>
 struct PeNormal {
-  static int run(const Plan& pl) {
-    StageScope sc(pl, GPJC_STAGE_PE_NORMAL);
-    const int nlines = pl.B * pl.np * pl.K;
-    const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
-    const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
-    hipLaunchKernelGGL(k_pe_normal<NY>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream,
-                       pl.Zp, pl.gemm_ksplit, zs, pl.Zt, pl.maskf, nlines, pl.f3_lpb, pl.K, pl.Kp, pl.tw_y);
-    GPJC_HIP(hipGetLastError());
-    return GPJC_OK;
-  }
+  template <int NY>
+  struct L {
+    static int run(const Plan& pl) {
+      StageScope sc(pl, GPJC_STAGE_PE_NORMAL);
+      const int nlines = pl.B * pl.np * pl.K;
+      const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
+      const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
+      hipLaunchKernelGGL((k_pe_normal<NY, ST>), dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds,
+                         pl.stream, pl.Zp, pl.gemm_ksplit, zs, zt_for(pl, ST), pl.maskf, nlines, pl.f3_lpb, pl.K,
+                         pl.Kp, pl.tw_y);
+      GPJC_HIP(hipGetLastError());
+      return GPJC_OK;
+    }
+  };
 };
 
 template <Store ST>
@@ -521,8 +533,20 @@ int launch_combine(const Plan& pl, float2* out) {
 }
 
 int launch_pe_fwd(const Plan& pl, float2* out) { return dispatch_n<PeFwd>(pl.ny, pl, out); }
-int launch_pe_adj(const Plan& pl, const float2* in) { return dispatch_n<PeAdj>(pl.ny, pl, in); }
-int launch_pe_normal(const Plan& pl) { return dispatch_n<PeNormal>(pl.ny, pl); }
+int launch_pe_adj(const Plan& pl, const float2* in, Store st) {
+  switch (st) {
+    case Store::F32: return dispatch_n<PeAdj<Store::F32>::L>(pl.ny, pl, in);
+    case Store::BF16: return dispatch_n<PeAdj<Store::BF16>::L>(pl.ny, pl, in);
+    default: return dispatch_n<PeAdj<Store::F16>::L>(pl.ny, pl, in);
+  }
+}
+int launch_pe_normal(const Plan& pl, Store st) {
+  switch (st) {
+    case Store::F32: return dispatch_n<PeNormal<Store::F32>::L>(pl.ny, pl);
+    case Store::BF16: return dispatch_n<PeNormal<Store::BF16>::L>(pl.ny, pl);
+    default: return dispatch_n<PeNormal<Store::F16>::L>(pl.ny, pl);
+  }
+}
 
 int launch_pe_cols_fwd(const Plan& pl, float2* out) {
   return dispatch_n<PeCols<Store::F32>::L>(pl.ny, pl, 0, (const float2*)nullptr, out);
@@ -552,7 +576,7 @@ int op_adjoint_part(const Plan& pl, Store st, const float2* in) {
     GPJC_TRY(launch_pe_cols_adj(pl, in));
     return launch_readout_adj(pl, Store::F32);
   }
-  GPJC_TRY(launch_pe_adj(pl, in));
+  GPJC_TRY(launch_pe_adj(pl, in, st));
   GPJC_TRY(launch_group_expand(pl, st));
   return launch_readout_adj(pl, st);
 }
@@ -565,7 +589,7 @@ int op_normal_part(const Plan& pl, Store st, const float2* img) {
   }
   GPJC_TRY(launch_readout_fwd(pl, img, st));
   GPJC_TRY(launch_group_compress(pl, st));
-  GPJC_TRY(launch_pe_normal(pl));
+  GPJC_TRY(launch_pe_normal(pl, st));
   GPJC_TRY(launch_group_expand(pl, st));
   return launch_readout_adj(pl, st);
 }

@@ -76,13 +76,15 @@ struct Plan {
   double2* A128 = nullptr;  // [G][K][ns]
   float* Aexp = nullptr;    // [G][2K][2ns]   real form for compressing
   float* AH = nullptr;      // [G][2ns][2Kp]  real form for expanding
-  uint16_t* Aexp16[3] = {nullptr, nullptr, nullptr};  // [prec] reduced copies
-  uint16_t* AH16[3] = {nullptr, nullptr, nullptr};
+  // 16-bit copies of Aexp / AH, index 0 = BF16, 1 = FP16 (same layouts)
+  uint16_t* Aexp16[2] = {nullptr, nullptr};
+  uint16_t* AH16[2] = {nullptr, nullptr};
 
   // device: workspaces
   float2* W = nullptr;      // [B][nc][ny][nt] (also holds 16-bit W)
   float2* Zp = nullptr;     // [ksplit][B][np][K][ny]
   float2* Zt = nullptr;     // [B][np][ny][Kp]
+  uint32_t* Zt16 = nullptr; // [B][np][ny][Kp] 16-bit (re, im) pairs, for the 16-bit contractions
   float2* part = nullptr;   // [f1h_nchunk][B][ny][nx]
 
   // device: solver state
@@ -123,8 +125,8 @@ int launch_combine(const Plan& pl, float2* out);
 int launch_group_compress(const Plan& pl, Store st);
 int launch_group_expand(const Plan& pl, Store st);
 int launch_pe_fwd(const Plan& pl, float2* out);
-int launch_pe_adj(const Plan& pl, const float2* in);
-int launch_pe_normal(const Plan& pl);
+int launch_pe_adj(const Plan& pl, const float2* in, Store st);
+int launch_pe_normal(const Plan& pl, Store st);
 int launch_pe_cols_fwd(const Plan& pl, float2* out);
 int launch_pe_cols_adj(const Plan& pl, const float2* in);
 int launch_pe_cols_normal(const Plan& pl);

@@ -170,13 +170,17 @@ int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine
   double* red_pq = pl.red;
   double* red_rr[2] = {pl.red + nb, pl.red + 2 * nb};
   const bool refine = refine_every > 0 && st != Store::F32;
+  // With refinement, b and every true residual come from the FP32 operator,
+  // so the iterates converge to the FP32 solution; only the search
+  // directions see the reduced-precision operator.
+  const Store sb = refine ? Store::F32 : st;
   GPJC_HIP(hipMemsetAsync(pl.flag, 0, sizeof(int), pl.stream));
   // b = E'^H y
-  GPJC_TRY(op_adjoint_part(pl, st, y));
+  GPJC_TRY(op_adjoint_part(pl, sb, y));
   GPJC_TRY(launch_combine(pl, pl.vb));
   GPJC_TRY(copy_vec(pl, x, pl.vx, n));
   // r0 = b - A x0
-  GPJC_TRY(op_normal_part(pl, st, pl.vx));
+  GPJC_TRY(op_normal_part(pl, sb, pl.vx));
   hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
                      red_rr[0], n);
   hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, red_rr[0], nb, pl.hist);

@@ -88,3 +88,45 @@ def rel_l2(a, ref):
 def max_rel(a, ref):
     """Largest element error relative to the largest reference magnitude."""
     return float(np.max(np.abs(np.asarray(a) - ref)) / np.max(np.abs(ref)))
+
+
+# ---------------------------------------------------------------------------
+# Error model of the 16-bit operator: the oracle's stages in FP64 with the
+# values rounded (nearest even) exactly where the library stores 16-bit
+# operands -- the bank (after its FP32 copy), W after the PSF product, Z^T
+# after the phase-encode stage, and W after the expanding contraction.
+# ---------------------------------------------------------------------------
+def _round_bf16(x):
+    u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _round_f16(x):
+    return np.asarray(x, np.float32).astype(np.float16).astype(np.float64)
+
+
+def round16(z, prec):
+    r = _round_bf16 if prec == "bf16" else _round_f16
+    z = np.asarray(z, np.complex64)  # the library holds these values in FP32 first
+    return r(z.real) + 1j * r(z.imag)
+
+
+def rounded_ops(sl, bank, prec):
+    g = sl.geom
+    nt = g.os * g.nx
+    bq = round16(bank, prec)
+
+    def fwd_z(x):
+        w = round16(oe.readout_encode(x, sl.coils, sl.psf, g.os), prec)
+        return oe.group_compress(w, bq, g.patch_group, g.patch_len)
+
+    def adj_z(zt):
+        w = round16(oe.group_expand(round16(zt, prec), bq, g.patch_group, g.patch_len, g.nc, nt), prec)
+        return oe.readout_encode_adj(w, sl.coils, sl.psf, g.os)
+
+    return dict(
+        fwd=lambda x: oe.pe_encode(fwd_z(x), g.mask),
+        adj=lambda y: adj_z(oe.pe_encode_adj(y, g.mask)),
+        nrm=lambda x: adj_z(oe.pe_encode_adj(oe.pe_encode(fwd_z(x), g.mask), g.mask)),
+    )

@@ -1,0 +1,131 @@
+"""Reduced-precision operator (BF16 / FP16 group contractions, FP32
+accumulation) and CG with FP32 residual refinement.
+
+Bounds: relative L2 per application <= 2e-3 (BF16) and <= 5e-4 (FP16)
+against the FP64 oracle.  The error model -- the oracle's stages with
+round-to-nearest-even applied exactly where the library stores 16-bit
+operands (tests/helpers.rounded_ops) -- must explain the GPU result far more
+closely than the raw error: a flipped rounding decision costs one 16-bit ulp
+(2^-8 BF16, 2^-11 FP16 relative) on about 1e-7 / ulp of the entries, which
+bounds the GPU-vs-model distance near 1e-4 (BF16) and 2e-5 (FP16).
+
+Refined CG is checked against the least-squares solution x* (the oracle's
+FP64 CG run to convergence) on the small-slice shapes at R = 2 + 8 ACS: with
+b and every refreshed residual from the FP32 operator, BF16 / FP16 search
+directions still reach NRMSE <= 1e-4, while the same BF16 run without
+refreshes stalls near the BF16 operator error.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import solvers as osv
+from paper_2601_05418_amd import gpjc, synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {"bf16": 2e-3, "fp16": 5e-4}
+MODEL = {"bf16": 2e-4, "fp16": 4e-5}
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, np.complex64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def make(case):
+    sl = H.rounded_slice(H.CASES[case]())
+    a = H.oracle_bank(sl)[0]
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    return sl, a, plan
+
+
+def check(name, out, ref, model, prec):
+    e, m = H.rel_l2(out, ref), H.rel_l2(out, model)
+    print(f"{name} {prec}: rel_l2 vs FP64 {e:.3e}, vs rounding model {m:.3e}", flush=True)
+    assert e <= BOUND[prec]
+    assert m <= MODEL[prec]
+    assert m <= 0.2 * e  # the model explains the error
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("case", list(H.CASES))
+def test_reduced_precision_operator(gpu_lib, case, prec):
+    sl, a, plan = make(case)
+    g = sl.geom
+    ops = H.oracle_ops(sl, a)
+    mod = H.rounded_ops(sl, a, prec)
+    rng = np.random.default_rng(11)
+    x = H.round64(sl.image + 0.1 * H.crandn(rng, (g.ny, g.nx)))
+    y = H.round64(ops["fwd"](sl.image) + 0.05 * H.crandn(rng, plan.data_shape()[1:]))
+    check("forward", host(plan.forward(dev(x[None]), prec=prec))[0], ops["fwd"](x), mod["fwd"](x), prec)
+    check("adjoint", host(plan.adjoint(dev(y[None]), prec=prec))[0], ops["adj"](y), mod["adj"](y), prec)
+    check("normal", host(plan.normal(dev(x[None]), prec=prec))[0], ops["nrm"](x), mod["nrm"](x), prec)
+
+
+def test_reduced_precision_batched_and_repeatable(gpu_lib):
+    """B = 2 images through the BF16 path match two B = 1 calls (the launch
+    shapes, hence FP32 summation orders, differ with B), and an FP32 call in
+    between leaves the 16-bit state intact (bit for bit)."""
+    sl = H.rounded_slice(H.CASES["rect"]())
+    a = H.oracle_bank(sl)[0]
+    p1 = gpjc.Plan.from_slice(sl)
+    p2 = gpjc.Plan.from_slice(sl, batch=2)
+    for p in (p1, p2):
+        p.set_compression(torch.as_tensor(a).cuda())
+    rng = np.random.default_rng(12)
+    x = H.round64(H.crandn(rng, (2, sl.geom.ny, sl.geom.nx)))
+    both = host(p2.normal(dev(x), prec="bf16"))
+    one = [host(p1.normal(dev(x[i:i + 1]), prec="bf16"))[0] for i in range(2)]
+    p1.normal(dev(x[:1]), prec="fp32")
+    again = host(p1.normal(dev(x[1:2]), prec="bf16"))[0]
+    for i in range(2):
+        assert H.rel_l2(both[i], one[i]) <= 1e-5
+    assert np.array_equal(again, one[1])
+
+
+def test_reduced_precision_needs_patch_multiple_of_4(gpu_lib):
+    sl = H.rounded_slice(synth._make_rect(0, nx=32, ny=32, nc=2, os_=3, patch_len=6, k=4, accel=2, acs=4,
+                                          cycles=2, phase_max=1.0))
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(H.random_bank(sl.geom)).cuda())
+    x = dev(np.zeros((1, 32, 32)))
+    with pytest.raises(gpjc.GpjcError) as ei:
+        plan.normal(x, prec="bf16")
+    assert ei.value.status == gpjc.GPJC_E_UNSUPPORTED
+    plan.normal(x, prec="fp32")  # FP32 still serves this geometry
+
+
+def well_conditioned_small():
+    sl = synth.small_slice(0)
+    return H.rounded_slice(dataclasses.replace(sl, geom=dataclasses.replace(sl.geom, mask=synth.pe_mask(64, 2, 8))))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_refined_cg_reaches_least_squares_solution(gpu_lib, prec):
+    sl = well_conditioned_small()
+    a = H.oracle_bank(sl)[0]
+    ops = H.oracle_ops(sl, a)
+    y = H.round64(ops["fwd"](sl.image))
+    b = ops["adj"](y)
+    xs, hs = osv.cg(ops["nrm"], b, 60)
+    assert hs[-1] <= 1e-9 * hs[0]  # converged reference
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    x32 = host(plan.recon_cg(dev(y[None]), 40))[0]
+    xr = host(plan.recon_cg(dev(y[None]), 40, prec=prec, refine_every=10))[0]
+    xn = host(plan.recon_cg(dev(y[None]), 40, prec=prec))[0]
+    e32, er, en = osv.nrmse(x32, xs), osv.nrmse(xr, xs), osv.nrmse(xn, xs)
+    print(f"{prec}: NRMSE vs x*: fp32 {e32:.2e}, refined {er:.2e}, unrefined {en:.2e}", flush=True)
+    assert e32 <= H.NRMSE_RECON
+    assert er <= H.NRMSE_RECON
+    if prec == "bf16":
+        assert en > 3 * H.NRMSE_RECON  # without refreshes the BF16 operator error remains
