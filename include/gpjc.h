@@ -192,6 +192,42 @@ int gpjc_set_gemm_config(gpjc_plan* plan, int compress_variant, int expand_varia
 int gpjc_get_gemm_config(const gpjc_plan* plan, int* compress_variant, int* expand_variant, int* ksplit,
                          int* n_compress_variants, int* n_expand_variants);
 
+/* Tile autotuning of the group contractions: times every built tile shape
+ * (and contraction split) of both contractions on the plan's own buffers and
+ * installs the fastest, as gpjc_set_gemm_config would.  Results are cached
+ * per (precision, Ns, K, Ny, B*Np) bucket for the process and, if cache_path
+ * is not NULL, in that text file (appended; read on first use), so later
+ * plans of the same bucket -- in this or another process -- skip the timing.
+ * h_choice [4] (optional): compress variant, expand variant, split, and 1 if
+ * the bucket was found in the cache.  Overwrites the plan's operator
+ * workspaces; synchronises. */
+int gpjc_autotune(gpjc_plan* plan, gpjc_prec prec, const char* cache_path, int* h_choice);
+
+/* Batches of independent slices (Section 3.4 solves independent
+ * subproblems in parallel): n plans of any geometries, reconstructed
+ * together.  A batch keeps one captured HIP graph per precision holding one
+ * CG iteration of every slice and replays it for every iteration; slices are
+ * spread over `lanes` streams (0 = 4, at most 16 and n), longest first, so
+ * their kernels overlap.  The plans stay owned by the caller and must
+ * outlive the batch; a plan may belong to one batch at a time, and must not
+ * be used on its own while a batch call runs.  Changing a plan's tile
+ * configuration makes the next batch call capture again. */
+typedef struct gpjc_batch gpjc_batch;
+int gpjc_batch_create(gpjc_plan* const* plans, int n, int lanes, gpjc_batch** out);
+int gpjc_batch_destroy(gpjc_batch* batch);
+/* Number of streams; h_lane_of [n] (optional) receives each slice's stream. */
+int gpjc_batch_lanes(const gpjc_batch* batch, int* h_lane_of);
+/* gpjc_recon_cg for every slice i on d_y[i] / d_x[i] (host arrays of n
+ * device pointers), one schedule for all: the same result, bit for bit, as
+ * n separate gpjc_recon_cg calls with the same plans.  h_resid [n][iters+1]
+ * (optional).  Waits for work already queued on the plans' streams, and
+ * returns when the batch is done.  GPJC_E_NUMERIC names the first failing
+ * slice. */
+int gpjc_batch_recon_cg(gpjc_batch* batch, gpjc_prec prec, const gpjc_c64* const* d_y, gpjc_c64* const* d_x,
+                        int iters, int refine_every, double* h_resid);
+/* gpjc_autotune for every plan of the batch. */
+int gpjc_batch_autotune(gpjc_batch* batch, gpjc_prec prec, const char* cache_path);
+
 const char* gpjc_status_string(int status);
 const char* gpjc_last_error(void);
 /* Path of the HIP runtime library this build is bound to in this process. */

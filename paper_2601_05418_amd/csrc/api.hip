@@ -12,7 +12,6 @@
 #include "fft.h"
 #include "plan.h"
 
-struct gpjc_plan : gpjc::Plan {};
 
 namespace gpjc {
 
@@ -261,7 +260,7 @@ static int check_plan(const gpjc_plan* plan) {
   return GPJC_OK;
 }
 
-static int check_prec(const Plan& pl, int prec, Store* st) {
+int check_prec(const Plan& pl, int prec, Store* st) {
   if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
   if (prec != GPJC_FP32 && !pl.compressed)
     return fail(GPJC_E_UNSUPPORTED, "the uncompressed operator is FP32 only");
@@ -271,7 +270,7 @@ static int check_prec(const Plan& pl, int prec, Store* st) {
   return GPJC_OK;
 }
 
-static int check_bank(const Plan& pl) {
+int check_bank(const Plan& pl) {
   if (pl.compressed && !pl.have_bank)
     return fail(GPJC_E_STATE, "no compression bank: call gpjc_calibrate or gpjc_set_compression first");
   return GPJC_OK;
@@ -474,6 +473,7 @@ int gpjc_set_gemm_config(gpjc_plan* plan, int compress_variant, int expand_varia
   plan->gemm_cvar = compress_variant;
   plan->gemm_evar = expand_variant;
   plan->gemm_ksplit = ksplit;
+  ++plan->config_gen;
   return GPJC_OK;
 }
 

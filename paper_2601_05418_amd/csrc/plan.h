@@ -58,6 +58,7 @@ struct Plan {
   int gemm_ksplit = 1;      // contraction split of the compressing group GEMM
   int gemm_cvar = 0;        // tile shape of the compressing contraction
   int gemm_evar = 0;        // tile shape of the expanding contraction
+  long config_gen = 0;      // bumped whenever the launch configuration changes
 
   // device: geometry tables
   float2* coils = nullptr;  // [nc][ny][nx]
@@ -117,6 +118,10 @@ struct StageScope {
   }
 };
 
+// Argument checks shared by the entry points (api.hip).
+int check_prec(const Plan& pl, int prec, Store* st);
+int check_bank(const Plan& pl);
+
 // ---- operator stages (operator.hip) ----
 int launch_prep_tables(Plan& pl);
 int launch_readout_fwd(const Plan& pl, const float2* img, Store st);
@@ -149,6 +154,14 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
 
 // ---- solvers (solver.hip) ----
 int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid);
+// CG in parts (a batch captures cg_iteration once and replays it):
+int cg_setup(Plan& pl, Store st, bool refine, const float2* y, const float2* x0);
+int cg_iteration(const Plan& pl, Store st, bool refresh);
+int cg_finish(const Plan& pl, float2* x, int iters, double* h_resid, int* h_flag);
+bool cg_refresh_at(int it, int iters, int refine_every, Store st);
+
+// ---- GEMM tile autotuning (tune.hip) ----
+int autotune(Plan& pl, Store st, const char* cache_path, int* h_choice);
 int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lip,
               int levels, double* h_obj);
 
@@ -159,3 +172,6 @@ int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
 bool fft_size_supported(int n);
 
 }  // namespace gpjc
+
+// The opaque handle of the C ABI is the plan itself.
+struct gpjc_plan : gpjc::Plan {};

@@ -71,10 +71,26 @@ __global__ __launch_bounds__(256) void k_copy(const float2* __restrict__ a, floa
     b[i] = a[i];
 }
 
-// r = b - A x (A x given as partial images), p = r, partial <r, r>.
+// CG state on the device: the squared-residual partials alternate between two
+// slots of red_rr (slot t & 1 after t iterations), and the iteration count t
+// lives in device memory (incremented by k_cg_q), so one iteration is the
+// same launch sequence every time and can be captured once and replayed.
+__device__ inline double* rr_slot(double* base, int nb, int t) { return base + (t & 1) * nb; }
+
+// Resets the numeric flag and the iteration counter (a kernel, not a memset,
+// so that a captured solve holds no memset nodes).
+__global__ void k_cg_reset(int* __restrict__ flag, int* __restrict__ iter) {
+  if (threadIdx.x == 0) {
+    *flag = 0;
+    *iter = 0;
+  }
+}
+
+// r = b - A x (A x given as partial images), p = r, partial <r, r> into slot t.
 __global__ __launch_bounds__(256) void k_cg_start(const float2* __restrict__ part, int nchunk,
                                                   const float2* __restrict__ bvec, float2* __restrict__ r,
-                                                  float2* __restrict__ p, double* __restrict__ red_rr, size_t n) {
+                                                  float2* __restrict__ p, double* __restrict__ red_rr, int nb,
+                                                  const int* __restrict__ iter, size_t n) {
   __shared__ double sh[8];
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -84,19 +100,22 @@ __global__ __launch_bounds__(256) void k_cg_start(const float2* __restrict__ par
     acc += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) red_rr[blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_slot(red_rr, nb, *iter)[blockIdx.x] = s;
 }
 
-// hist = sqrt(sum of partials); single block.
-__global__ void k_store_norm(const double* __restrict__ red, int nb, double* __restrict__ hist) {
+// hist[t] = sqrt(sum of slot t's partials); single block.
+__global__ void k_store_norm(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
+                             double* __restrict__ hist) {
   __shared__ double sh[8];
-  const double s = sum_partials(red, nb, sh);
-  if (threadIdx.x == 0) *hist = sqrt(s);
+  const int t = *iter;
+  const double s = sum_partials(red_rr + (t & 1) * nb, nb, sh);
+  if (threadIdx.x == 0) hist[t] = sqrt(s);
 }
 
-// q = A p (from partials), partial Re <p, q>.
+// q = A p (from partials), partial Re <p, q>; advances the iteration count.
 __global__ __launch_bounds__(256) void k_cg_q(const float2* __restrict__ part, int nchunk, const float2* __restrict__ p,
-                                              float2* __restrict__ q, double* __restrict__ red_pq, size_t n) {
+                                              float2* __restrict__ q, double* __restrict__ red_pq, int* __restrict__ iter,
+                                              size_t n) {
   __shared__ double sh[8];
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -107,17 +126,19 @@ __global__ __launch_bounds__(256) void k_cg_q(const float2* __restrict__ part, i
   }
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) red_pq[blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *iter += 1;  // no other block of this kernel reads it
 }
 
-// alpha = rr / pq; x += alpha p; r -= alpha q; partial <r, r> into red_new.
-__global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ red_pq,
-                                                   const double* __restrict__ red_old, double* __restrict__ red_new,
-                                                   int nb, float2* __restrict__ x, float2* __restrict__ r,
-                                                   const float2* __restrict__ p, const float2* __restrict__ q,
-                                                   size_t n, int* __restrict__ flag) {
+// alpha = rr / pq; x += alpha p; r -= alpha q; partial <r, r> into slot t
+// (the old residual is in slot t - 1).
+__global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ red_pq, double* __restrict__ red_rr,
+                                                   int nb, const int* __restrict__ iter, float2* __restrict__ x,
+                                                   float2* __restrict__ r, const float2* __restrict__ p,
+                                                   const float2* __restrict__ q, size_t n, int* __restrict__ flag) {
   __shared__ double sh[8];
+  const int t = *iter;
   const double pq = sum_partials(red_pq, nb, sh);
-  const double rr = sum_partials(red_old, nb, sh);
+  const double rr = sum_partials(rr_slot(red_rr, nb, t - 1), nb, sh);
   if (!isfinite(pq) || !isfinite(rr)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
   }
@@ -134,22 +155,23 @@ __global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ re
     acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) red_new[blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_slot(red_rr, nb, t)[blockIdx.x] = s;
 }
 
-// beta = rr_new / rr_old; p = r + beta p; hist = ||r||.
-__global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ red_new, const double* __restrict__ red_old,
-                                                int nb, const float2* __restrict__ r, float2* __restrict__ p, size_t n,
+// beta = rr_t / rr_{t-1}; p = r + beta p; hist[t] = ||r||.
+__global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
+                                                const float2* __restrict__ r, float2* __restrict__ p, size_t n,
                                                 double* __restrict__ hist) {
   __shared__ double sh[8];
-  const double rn = sum_partials(red_new, nb, sh);
-  const double ro = sum_partials(red_old, nb, sh);
+  const int t = *iter;
+  const double rn = sum_partials(red_rr + (t & 1) * nb, nb, sh);
+  const double ro = sum_partials(red_rr + ((t - 1) & 1) * nb, nb, sh);
   const float beta = (float)((ro > 0.0) ? rn / ro : 0.0);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const float2 rv = r[i], pv = p[i];
     p[i] = make_float2(fmaf(beta, pv.x, rv.x), fmaf(beta, pv.y, rv.y));
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *hist = sqrt(rn);
+  if (blockIdx.x == 0 && threadIdx.x == 0) hist[t] = sqrt(rn);
 }
 
 static int fill_zero(const Plan& pl, float2* v, size_t n) {
@@ -164,58 +186,79 @@ static int copy_vec(const Plan& pl, const float2* a, float2* b, size_t n) {
   return GPJC_OK;
 }
 
-int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid) {
+// The solve in three parts so that a batch can capture cg_iteration once.
+int cg_setup(Plan& pl, Store st, bool refine, const float2* y, const float2* x0) {
   const size_t n = pl.img_elems();
   const int nb = kRedBlocks;
-  double* red_pq = pl.red;
-  double* red_rr[2] = {pl.red + nb, pl.red + 2 * nb};
-  const bool refine = refine_every > 0 && st != Store::F32;
   // With refinement, b and every true residual come from the FP32 operator,
   // so the iterates converge to the FP32 solution; only the search
   // directions see the reduced-precision operator.
   const Store sb = refine ? Store::F32 : st;
-  GPJC_HIP(hipMemsetAsync(pl.flag, 0, sizeof(int), pl.stream));
+  int* iter = pl.flag + 1;
+  hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, pl.stream, pl.flag, iter);
+  GPJC_HIP(hipGetLastError());
   // b = E'^H y
   GPJC_TRY(op_adjoint_part(pl, sb, y));
   GPJC_TRY(launch_combine(pl, pl.vb));
-  GPJC_TRY(copy_vec(pl, x, pl.vx, n));
+  GPJC_TRY(copy_vec(pl, x0, pl.vx, n));
   // r0 = b - A x0
   GPJC_TRY(op_normal_part(pl, sb, pl.vx));
   hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
-                     red_rr[0], n);
-  hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, red_rr[0], nb, pl.hist);
+                     pl.red + nb, nb, iter, n);
+  hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, pl.red + nb, nb, iter, pl.hist);
   GPJC_HIP(hipGetLastError());
-  for (int it = 0; it < iters; ++it) {
-    double* r_old = red_rr[it & 1];
-    double* r_new = red_rr[(it + 1) & 1];
-    GPJC_TRY(op_normal_part(pl, st, pl.vp));
-    {
-      StageScope sc(pl, GPJC_STAGE_SOLVER);
-      hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vp, pl.vq, red_pq,
-                         n);
-      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, pl.stream, red_pq, r_old, r_new, nb, pl.vx, pl.vr,
-                         pl.vp, pl.vq, n, pl.flag);
-    }
-    GPJC_HIP(hipGetLastError());
-    if (refine && (it + 1) % refine_every == 0 && it + 1 < iters) {
-      GPJC_TRY(op_normal_part(pl, Store::F32, pl.vx));
-      StageScope sc(pl, GPJC_STAGE_SOLVER);
-      hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
-                         r_new, n);
-      hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, r_new, nb, pl.hist + it + 1);
-    } else {
-      StageScope sc(pl, GPJC_STAGE_SOLVER);
-      hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, pl.stream, r_new, r_old, nb, pl.vr, pl.vp, n,
-                         pl.hist + it + 1);
-    }
-    GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int cg_iteration(const Plan& pl, Store st, bool refresh) {
+  const size_t n = pl.img_elems();
+  const int nb = kRedBlocks;
+  int* iter = pl.flag + 1;
+  double* red_pq = pl.red;
+  double* red_rr = pl.red + nb;
+  GPJC_TRY(op_normal_part(pl, st, pl.vp));
+  {
+    StageScope sc(pl, GPJC_STAGE_SOLVER);
+    hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vp, pl.vq, red_pq, iter,
+                       n);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, pl.stream, red_pq, red_rr, nb, iter, pl.vx, pl.vr, pl.vp,
+                       pl.vq, n, pl.flag);
   }
-  GPJC_TRY(copy_vec(pl, pl.vx, x, n));
-  int flag = 0;
-  if (h_resid) {
+  GPJC_HIP(hipGetLastError());
+  if (refresh) {
+    GPJC_TRY(op_normal_part(pl, Store::F32, pl.vx));
+    StageScope sc(pl, GPJC_STAGE_SOLVER);
+    hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
+                       red_rr, nb, iter, n);
+    hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, red_rr, nb, iter, pl.hist);
+  } else {
+    StageScope sc(pl, GPJC_STAGE_SOLVER);
+    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, pl.stream, red_rr, nb, iter, pl.vr, pl.vp, n, pl.hist);
+  }
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+// Copies the result out; queues the history (h_resid, iters + 1 entries, may
+// be NULL) and the numeric flag (h_flag) to the host without synchronising.
+int cg_finish(const Plan& pl, float2* x, int iters, double* h_resid, int* h_flag) {
+  GPJC_TRY(copy_vec(pl, pl.vx, x, pl.img_elems()));
+  if (h_resid)
     GPJC_HIP(hipMemcpyAsync(h_resid, pl.hist, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost, pl.stream));
-  }
-  GPJC_HIP(hipMemcpyAsync(&flag, pl.flag, sizeof(int), hipMemcpyDeviceToHost, pl.stream));
+  GPJC_HIP(hipMemcpyAsync(h_flag, pl.flag, sizeof(int), hipMemcpyDeviceToHost, pl.stream));
+  return GPJC_OK;
+}
+
+bool cg_refresh_at(int it, int iters, int refine_every, Store st) {
+  return refine_every > 0 && st != Store::F32 && (it + 1) % refine_every == 0 && it + 1 < iters;
+}
+
+int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid) {
+  const bool refine = refine_every > 0 && st != Store::F32;
+  GPJC_TRY(cg_setup(pl, st, refine, y, x));
+  for (int it = 0; it < iters; ++it) GPJC_TRY(cg_iteration(pl, st, cg_refresh_at(it, iters, refine_every, st)));
+  int flag = 0;
+  GPJC_TRY(cg_finish(pl, x, iters, h_resid, &flag));
   GPJC_HIP(hipStreamSynchronize(pl.stream));
   if (flag) return fail(GPJC_E_NUMERIC, "CG: non-finite residual or curvature");
   return GPJC_OK;

@@ -1,0 +1,183 @@
+// Tile-shape autotuning of the group contractions.
+//
+// The best tile shape and contraction split depend on the contraction sizes
+// (2K rows, 2 Ns contraction length, Ny columns, B Np independent products)
+// and on the operand precision.  A plan is tuned by timing every built
+// variant of each contraction on its own buffers (HIP events on the plan's
+// stream, best of three launches after one warm-up) and keeping the fastest.
+// Results are cached per (precision, Ns, K, Ny, B Np) bucket for the life of
+// the process and, given a cache file, across processes: one text line per
+// bucket, later lines overriding earlier ones.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <set>
+#include <sstream>
+#include <string>
+
+#include "plan.h"
+
+namespace gpjc {
+
+namespace {
+
+struct Choice {
+  int cvar, evar, ksplit;
+};
+
+std::mutex g_mu;
+std::map<std::string, Choice> g_cache;
+std::set<std::string> g_loaded;
+
+const char* prec_name(Store st) { return st == Store::F32 ? "fp32" : st == Store::BF16 ? "bf16" : "fp16"; }
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+int pow2_up(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+std::string bucket_key(const Plan& pl, Store st) {
+  std::ostringstream k;
+  k << prec_name(st) << "/ns" << round_up(pl.ns, 64) << "/k" << pl.Kp << "/ny" << round_up(pl.ny, 32) << "/cols"
+    << pow2_up(pl.B * pl.np);
+  return k.str();
+}
+
+void load_file(const char* path) {
+  if (!path || g_loaded.count(path)) return;
+  g_loaded.insert(path);
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string tag, key;
+    Choice c;
+    if (in >> tag >> key >> c.cvar >> c.evar >> c.ksplit && tag == "gpjc-tune-v1") {
+      if (c.cvar >= 0 && c.cvar < gemm_compress_variants() && c.evar >= 0 && c.evar < gemm_expand_variants() &&
+          c.ksplit >= 1 && c.ksplit <= kMaxKsplit)
+        g_cache[key] = c;
+    }
+  }
+}
+
+void append_file(const char* path, const std::string& key, const Choice& c, float us_c, float us_e) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << "gpjc-tune-v1 " << key << " " << c.cvar << " " << c.evar << " " << c.ksplit << "  # " << us_c << " us "
+    << us_e << " us\n";
+}
+
+// Average duration in microseconds of `fn` (best of three after a warm-up).
+template <class F>
+int time_us(const Plan& pl, hipEvent_t e0, hipEvent_t e1, F fn, float* us) {
+  GPJC_TRY(fn());
+  float best = 1e30f;
+  for (int r = 0; r < 3; ++r) {
+    GPJC_HIP(hipEventRecord(e0, pl.stream));
+    GPJC_TRY(fn());
+    GPJC_HIP(hipEventRecord(e1, pl.stream));
+    GPJC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GPJC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    best = std::min(best, ms * 1e3f);
+  }
+  *us = best;
+  return GPJC_OK;
+}
+
+struct Events {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Events() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+int measure(Plan& pl, Store st, Choice* out, float* us_c, float* us_e) {
+  Events ev;
+  GPJC_HIP(hipEventCreate(&ev.a));
+  GPJC_HIP(hipEventCreate(&ev.b));
+  const bool timing = pl.timing.on;
+  pl.timing.on = false;
+  const Choice keep{pl.gemm_cvar, pl.gemm_evar, pl.gemm_ksplit};
+  // Operands with defined contents: W from the readout stage of a zero image.
+  GPJC_HIP(hipMemsetAsync(pl.vx, 0, sizeof(float2) * pl.img_elems(), pl.stream));
+  int status = launch_readout_fwd(pl, pl.vx, st);
+  Choice best = keep;
+  float bc = 1e30f, be = 1e30f;
+  const int kd = 2 * pl.ns;
+  for (int v = 0; status == GPJC_OK && v < gemm_compress_variants(); ++v)
+    for (int ks = 1; status == GPJC_OK && ks <= kMaxKsplit && (ks == 1 || kd / ks >= 128); ks *= 2) {
+      pl.gemm_cvar = v;
+      pl.gemm_ksplit = ks;
+      float us = 0.f;
+      status = time_us(pl, ev.a, ev.b, [&] { return launch_group_compress(pl, st); }, &us);
+      if (status == GPJC_OK && us < bc) {
+        bc = us;
+        best.cvar = v;
+        best.ksplit = ks;
+      }
+    }
+  for (int v = 0; status == GPJC_OK && v < gemm_expand_variants(); ++v) {
+    pl.gemm_evar = v;
+    float us = 0.f;
+    status = time_us(pl, ev.a, ev.b, [&] { return launch_group_expand(pl, st); }, &us);
+    if (status == GPJC_OK && us < be) {
+      be = us;
+      best.evar = v;
+    }
+  }
+  pl.timing.on = timing;
+  pl.gemm_cvar = keep.cvar;
+  pl.gemm_evar = keep.evar;
+  pl.gemm_ksplit = keep.ksplit;
+  if (status != GPJC_OK) return status;
+  *out = best;
+  *us_c = bc;
+  *us_e = be;
+  return GPJC_OK;
+}
+
+}  // namespace
+
+int autotune(Plan& pl, Store st, const char* cache_path, int* h_choice) {
+  if (!pl.compressed) return fail(GPJC_E_INVAL, "autotuning needs a compressed plan");
+  const std::string key = bucket_key(pl, st);
+  Choice c;
+  bool hit = false;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file(cache_path);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      c = it->second;
+      hit = true;
+    }
+  }
+  if (!hit) {
+    float us_c = 0.f, us_e = 0.f;
+    GPJC_TRY(measure(pl, st, &c, &us_c, &us_e));
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[key] = c;
+    append_file(cache_path, key, c, us_c, us_e);
+  }
+  pl.gemm_cvar = c.cvar;
+  pl.gemm_evar = c.evar;
+  pl.gemm_ksplit = c.ksplit;
+  ++pl.config_gen;
+  if (h_choice) {
+    h_choice[0] = c.cvar;
+    h_choice[1] = c.evar;
+    h_choice[2] = c.ksplit;
+    h_choice[3] = hit ? 1 : 0;
+  }
+  return GPJC_OK;
+}
+
+}  // namespace gpjc

@@ -73,6 +73,12 @@ _SIGS = {
     "gpjc_stage_times": (_I, [_VP, _VP, _VP]),
     "gpjc_set_gemm_config": (_I, [_VP, _I, _I, _I]),
     "gpjc_get_gemm_config": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "gpjc_autotune": (_I, [_VP, _I, ctypes.c_char_p, _VP]),
+    "gpjc_batch_create": (_I, [_VP, _I, _I, ctypes.POINTER(_VP)]),
+    "gpjc_batch_destroy": (_I, [_VP]),
+    "gpjc_batch_lanes": (_I, [_VP, _VP]),
+    "gpjc_batch_recon_cg": (_I, [_VP, _I, _VP, _VP, _I, _I, _VP]),
+    "gpjc_batch_autotune": (_I, [_VP, _I, ctypes.c_char_p]),
     "gpjc_status_string": (ctypes.c_char_p, [_I]),
     "gpjc_last_error": (ctypes.c_char_p, []),
     "gpjc_runtime_path": (ctypes.c_char_p, []),
@@ -301,3 +307,70 @@ class Plan:
         _check(self.lib.gpjc_get_gemm_config(self.handle, *[ctypes.byref(x) for x in v]))
         return {"compress": v[0].value, "expand": v[1].value, "ksplit": v[2].value,
                 "n_compress": v[3].value, "n_expand": v[4].value}
+
+    def autotune(self, prec="fp32", cache_path=None):
+        """Times the contraction tile shapes on this plan and installs the
+        fastest; returns the choice and whether the bucket came from the cache."""
+        ch = (ctypes.c_int * 4)()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        torch.cuda.synchronize(self.device)
+        _check(self.lib.gpjc_autotune(self.handle, _prec(prec), path, ch))
+        return {"compress": ch[0], "expand": ch[1], "ksplit": ch[2], "cached": bool(ch[3])}
+
+
+class Batch:
+    """Independent slices (one Plan each, any geometries) reconstructed
+    together: one captured HIP graph replays a CG iteration of every slice."""
+
+    def __init__(self, plans, lanes=0):
+        self.lib = load()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        handle = ctypes.c_void_p()
+        _check(self.lib.gpjc_batch_create(arr, len(self.plans), int(lanes), ctypes.byref(handle)))
+        self.handle = handle
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gpjc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def lanes(self):
+        lane_of = (ctypes.c_int * len(self.plans))()
+        n = self.lib.gpjc_batch_lanes(self.handle, lane_of)
+        if n < 0:
+            _check(n)
+        return n, list(lane_of)
+
+    def recon_cg(self, ys, iters, xs=None, prec="fp32", refine_every=0, want_resid=False):
+        """ys: one data tensor per slice (the plan's data_shape()); xs: initial
+        images (copied) or None for zeros.  Returns the images (and residual
+        histories [n][iters+1])."""
+        n = len(self.plans)
+        if len(ys) != n or (xs is not None and len(xs) != n):
+            raise ValueError("one input per slice")
+        yin, xout = [], []
+        for i, p in enumerate(self.plans):
+            yin.append(_dev_tensor(ys[i], torch.complex64, p.device))
+            x = torch.zeros(p.image_shape(), dtype=torch.complex64, device=p.device) if xs is None \
+                else _dev_tensor(xs[i], torch.complex64, p.device).clone()
+            xout.append(x)
+        ya = (ctypes.c_void_p * n)(*[t.data_ptr() for t in yin])
+        xa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xout])
+        hist = np.zeros((n, iters + 1), np.float64) if want_resid else None
+        torch.cuda.synchronize()
+        _check(self.lib.gpjc_batch_recon_cg(self.handle, _prec(prec), ya, xa, int(iters), int(refine_every),
+                                            None if hist is None else hist.ctypes.data_as(ctypes.c_void_p)))
+        return (xout, hist) if want_resid else xout
+
+    def autotune(self, prec="fp32", cache_path=None):
+        path = None if cache_path is None else os.fsencode(cache_path)
+        torch.cuda.synchronize()
+        _check(self.lib.gpjc_batch_autotune(self.handle, _prec(prec), path))
+

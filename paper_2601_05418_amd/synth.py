@@ -230,9 +230,9 @@ def unrolled_slices(batch: int = 8, seed: int = 0) -> List[Slice]:
 
 def batch_draws(n_slices: int = 64, seed: int = 0) -> List[Slice]:
     """Uneven slices: N in {128..256 step 32}, Nc in {16, 24, 32}, os 6 or 8,
-    patch length a divisor of nt in [16, 48] with 16-96 patches, K such that
-    the compression factor is U(12, 20), R in {3, 4, 5} with 8 calibration
-    lines, wave 7 cycles / +-6 rad, one group per patch."""
+    patch length an even divisor of nt in [16, 48] with 16-96 patches, K such
+    that the compression factor is U(12, 20), R in {3, 4, 5} with 8
+    calibration lines, wave 7 cycles / +-6 rad, one group per patch."""
     rs = _streams(4, seed)
     draw = rs[_DRAWS]
     out = []
@@ -241,7 +241,7 @@ def batch_draws(n_slices: int = 64, seed: int = 0) -> List[Slice]:
         nc = int(draw.choice([16, 24, 32]))
         os_ = int(draw.choice([6, 8]))
         nt = os_ * n
-        cands = [p for p in range(16, 49) if nt % p == 0 and 16 <= nt // p <= 96]
+        cands = [p for p in range(16, 49, 2) if nt % p == 0 and 16 <= nt // p <= 96]
         p = int(draw.choice(cands))
         f = float(draw.uniform(12.0, 20.0))
         k = max(1, int(round(nc * p / f)))
@@ -268,3 +268,20 @@ def _make_rect(seed, nx, ny, nc, os_, patch_len, k, accel, acs, cycles, phase_ma
     return Slice(geom, ellipse_phantom(nx, ny, rs[_PHANTOM]),
                  gaussian_coils(nx, ny, nc, rs[_COILS]), wave_psf(ny, nt, cycles, phase_max),
                  None, None, cycles, phase_max)
+
+
+def orthonormal_bank(n_groups: int, k: int, nc: int, patch_len: int, rng: np.random.Generator) -> np.ndarray:
+    """A random bank [G][K][nc][P] with orthonormal rows, cheap at any size:
+    row r of group g is a distinct Fourier row of length Ns = nc P (random
+    choice of frequencies) times random unit phases on both sides.  For
+    workloads whose cost, not content, is measured."""
+    ns = nc * patch_len
+    j = np.arange(ns)
+    out = np.empty((n_groups, k, ns), np.complex128)
+    for g in range(n_groups):
+        freq = rng.choice(ns, size=k, replace=False)
+        row_ph = np.exp(2j * np.pi * rng.random(k))
+        col_ph = np.exp(2j * np.pi * rng.random(ns))
+        out[g] = row_ph[:, None] * np.exp(-2j * np.pi * np.outer(freq, j) / ns) * col_ph[None, :] / np.sqrt(ns)
+    return out.reshape(n_groups, k, nc, patch_len)
+

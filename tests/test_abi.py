@@ -87,3 +87,21 @@ def test_null_plan_calls():
     assert lib.gpjc_forward(None, 0, FAKE, FAKE) == gpjc.GPJC_E_INVAL
     assert lib.gpjc_recon_cg(None, 0, FAKE, FAKE, 5, 0, None) == gpjc.GPJC_E_INVAL
     assert lib.gpjc_plan_destroy(None) == gpjc.GPJC_OK
+
+
+def test_batch_and_autotune_argument_errors():
+    """Rejected before any HIP call: no plans, NULL handles, duplicates."""
+    lib = gpjc.load()
+    out = ctypes.c_void_p()
+    assert lib.gpjc_batch_create(None, 0, 0, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.gpjc_batch_create(arr, 2, 0, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+    assert b"NULL" in lib.gpjc_last_error()
+    fake = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    assert lib.gpjc_batch_create(fake, 2, 0, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+    assert b"twice" in lib.gpjc_last_error()
+    assert lib.gpjc_batch_create(fake, 1, -1, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+    assert lib.gpjc_batch_recon_cg(None, 0, None, None, 5, 0, None) == gpjc.GPJC_E_INVAL
+    assert lib.gpjc_batch_autotune(None, 0, None) == gpjc.GPJC_E_INVAL
+    assert lib.gpjc_batch_destroy(None) == gpjc.GPJC_E_INVAL
+    assert lib.gpjc_autotune(None, 0, None, None) == gpjc.GPJC_E_INVAL

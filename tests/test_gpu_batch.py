@@ -1,0 +1,200 @@
+"""Batched CG over independent, uneven slices (one captured iteration graph
+replayed per iteration) and tile autotuning.
+
+The batch runs the same kernels with the same launch shapes as separate
+gpjc_recon_cg calls, so its images and residual histories must equal those
+bit for bit; the graph is replayed across several calls with eager work in
+between, and every replay is checked.  Parity with the oracle is
+same-schedule CG (NRMSE <= 1e-4).  The 64-slice workload uses random
+orthonormal banks and random data: its cost, not its content, matters, and
+two of its slices are checked against the oracle at full size.
+"""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import encoding as oe
+from oracle import solvers as osv
+from paper_2601_05418_amd import gpjc, synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, np.complex64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def uneven_slices():
+    return [
+        H.rounded_slice(H.CASES["small"]()),
+        H.rounded_slice(H.CASES["rect"]()),
+        H.rounded_slice(H.CASES["periodic"]()),
+        H.rounded_slice(synth._make_rect(5, nx=48, ny=64, nc=3, os_=2, patch_len=8, k=6, accel=2, acs=4,
+                                         cycles=2, phase_max=1.5)),
+        H.rounded_slice(synth._make_rect(6, nx=80, ny=32, nc=5, os_=3, patch_len=12, k=10, accel=3, acs=4,
+                                         cycles=3, phase_max=2.0)),
+    ]
+
+
+def plans_for(slices, seed=0):
+    plans, banks, ys = [], [], []
+    rng = np.random.default_rng(seed)
+    for sl in slices:
+        g = sl.geom
+        a = H.random_bank(g, seed)
+        p = gpjc.Plan.from_slice(sl)
+        p.set_compression(torch.as_tensor(a).cuda())
+        plans.append(p)
+        banks.append(a)
+        ys.append(H.round64(H.crandn(rng, p.data_shape())))
+    return plans, banks, ys
+
+
+def separate(plans, ys, iters, prec="fp32", refine_every=0):
+    out = []
+    for p, y in zip(plans, ys):
+        x, h = p.recon_cg(dev(y), iters, prec=prec, refine_every=refine_every, want_resid=True)
+        out.append((host(x), h))
+    return out
+
+
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_batch_equals_separate_solves_on_every_replay(gpu_lib, lanes):
+    slices = uneven_slices()
+    plans, _, ys = plans_for(slices)
+    ref = separate(plans, ys, 12)
+    batch = gpjc.Batch(plans, lanes=lanes)
+    n, lane_of = batch.lanes()
+    assert n == lanes and sorted(set(lane_of)) == list(range(lanes))
+    for rep in range(3):
+        xs, hs = batch.recon_cg([dev(y) for y in ys], 12, want_resid=True)
+        for i in range(len(plans)):
+            assert np.array_equal(host(xs[i]), ref[i][0]), (rep, i)
+            assert np.array_equal(hs[i], ref[i][1]), (rep, i)
+        # eager work on the same plans between replays
+        plans[rep % len(plans)].normal(dev(np.ones(plans[rep % len(plans)].image_shape())))
+        torch.cuda.synchronize()
+    batch.close()
+
+
+def test_batch_initial_guess_and_zero_iterations(gpu_lib):
+    slices = uneven_slices()[:3]
+    plans, _, ys = plans_for(slices, seed=1)
+    rng = np.random.default_rng(3)
+    x0 = [H.round64(H.crandn(rng, p.image_shape())) for p in plans]
+    batch = gpjc.Batch(plans)
+    xs = batch.recon_cg([dev(y) for y in ys], 0, xs=[dev(x) for x in x0])
+    for i in range(3):
+        assert np.array_equal(host(xs[i]), x0[i])
+    xs = batch.recon_cg([dev(y) for y in ys], 7, xs=[dev(x) for x in x0])
+    for i, p in enumerate(plans):
+        ref = host(p.recon_cg(dev(ys[i]), 7, x0=dev(x0[i])))
+        assert np.array_equal(host(xs[i]), ref)
+
+
+def test_batch_refined_bf16_equals_separate(gpu_lib):
+    slices = [s for s in uneven_slices() if s.geom.patch_len % 4 == 0]
+    plans, _, ys = plans_for(slices, seed=2)
+    ref = separate(plans, ys, 25, prec="bf16", refine_every=10)
+    batch = gpjc.Batch(plans, lanes=2)
+    for rep in range(2):
+        xs, hs = batch.recon_cg([dev(y) for y in ys], 25, prec="bf16", refine_every=10, want_resid=True)
+        for i in range(len(plans)):
+            assert np.array_equal(host(xs[i]), ref[i][0]), (rep, i)
+            assert np.array_equal(hs[i], ref[i][1]), (rep, i)
+
+
+def test_batch_against_oracle_same_schedule(gpu_lib):
+    slices = uneven_slices()
+    plans, banks, ys = plans_for(slices, seed=4)
+    xs = gpjc.Batch(plans).recon_cg([dev(y) for y in ys], 15)
+    for i in (0, 1, 4):
+        sl, g = slices[i], slices[i].geom
+        nrm = lambda v: oe.normal(v, sl.coils, sl.psf, g.mask, g.os, banks[i], g.patch_group, g.patch_len)
+        b = oe.adjoint(ys[i][0], sl.coils, sl.psf, g.mask, g.os, banks[i], g.patch_group, g.patch_len)
+        xo, _ = osv.cg(nrm, b, 15)
+        e = osv.nrmse(host(xs[i])[0], xo)
+        print(f"slice {i}: NRMSE vs oracle CG-15 {e:.2e}", flush=True)
+        assert e <= H.NRMSE_RECON
+
+
+def test_batch_recaptures_after_config_change(gpu_lib):
+    slices = uneven_slices()[:2]
+    plans, _, ys = plans_for(slices, seed=5)
+    batch = gpjc.Batch(plans, lanes=2)
+    batch.recon_cg([dev(y) for y in ys], 5)
+    cfg = plans[0].gemm_config()
+    plans[0].set_gemm_config((cfg["compress"] + 1) % cfg["n_compress"], (cfg["expand"] + 1) % cfg["n_expand"], 1)
+    ref = separate(plans, ys, 5)
+    xs = batch.recon_cg([dev(y) for y in ys], 5)
+    for i in range(2):
+        assert np.array_equal(host(xs[i]), ref[i][0])
+
+
+def test_autotune_cache(gpu_lib, tmp_path):
+    path = str(tmp_path / "tune.txt")
+    sl = H.rounded_slice(H.CASES["rect"]())
+    a = H.oracle_bank(sl)[0]
+    p1, p2 = gpjc.Plan.from_slice(sl), gpjc.Plan.from_slice(sl)
+    for p in (p1, p2):
+        p.set_compression(torch.as_tensor(a).cuda())
+    c1 = p1.autotune("fp32", path)
+    assert not c1["cached"]
+    cfg = p1.gemm_config()
+    assert (cfg["compress"], cfg["expand"], cfg["ksplit"]) == (c1["compress"], c1["expand"], c1["ksplit"])
+    c2 = p2.autotune("fp32", path)
+    assert c2["cached"] and (c2["compress"], c2["expand"], c2["ksplit"]) == (c1["compress"], c1["expand"], c1["ksplit"])
+    lines = [l for l in open(path) if l.startswith("gpjc-tune-v1 ")]
+    assert len(lines) == 1 and "fp32/" in lines[0]
+    cb = p1.autotune("bf16", path)  # another bucket
+    assert not cb["cached"]
+    assert len([l for l in open(path) if l.startswith("gpjc-tune-v1 ")]) == 2
+    # the tuned operator still meets the FP32 bound
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(H.crandn(np.random.default_rng(8), (sl.geom.ny, sl.geom.nx)))
+    assert H.rel_l2(host(p1.normal(dev(x[None])))[0], ops["nrm"](x)) <= H.REL_L2_FP32
+
+
+def c4_plans(n=64):
+    slices = synth.batch_draws(n, 0)
+    rng = np.random.default_rng(77)
+    plans, banks, ys = [], [], []
+    for sl in slices:
+        g = sl.geom
+        sl = H.rounded_slice(sl)
+        a = synth.orthonormal_bank(g.n_groups, g.k, g.nc, g.patch_len, rng)
+        p = gpjc.Plan.from_slice(sl)
+        p.set_compression(torch.as_tensor(a).cuda())
+        plans.append(p)
+        banks.append(a)
+        ys.append(H.round64(synth.unit_noise(p.data_shape(), rng)))
+    return slices, plans, banks, ys
+
+
+def test_batch_64_uneven_slices(gpu_lib):
+    slices, plans, banks, ys = c4_plans()
+    print(f"64 slices: W total {sum(p.nc * p.ny * p.nt * 8 for p in plans) / 1e9:.2f} GB", flush=True)
+    batch = gpjc.Batch(plans)
+    xs, hs = batch.recon_cg([dev(y) for y in ys], 20, want_resid=True)
+    assert np.all(np.isfinite(hs)) and np.all(hs[:, -1] < hs[:, 0])
+    # two full-size slices against the oracle's same-schedule CG
+    order = sorted(range(64), key=lambda i: plans[i].nc * plans[i].ny * plans[i].nt)
+    for i in order[:2]:
+        sl = H.rounded_slice(slices[i])
+        g = sl.geom
+        nrm = lambda v: oe.normal(v, sl.coils, sl.psf, g.mask, g.os, banks[i], g.patch_group, g.patch_len)
+        b = oe.adjoint(ys[i][0], sl.coils, sl.psf, g.mask, g.os, banks[i], g.patch_group, g.patch_len)
+        xo, _ = osv.cg(nrm, b, 20)
+        e = osv.nrmse(host(xs[i])[0], xo)
+        print(f"slice {i} ({g.nx}x{g.ny}, nc {g.nc}, os {g.os}, P {g.patch_len}, K {g.k}): NRMSE {e:.2e}",
+              flush=True)
+        assert e <= H.NRMSE_RECON
