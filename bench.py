@@ -146,6 +146,52 @@ def batch_bench(steps, warmup, prec, tune_path):
     }
 
 
+def unrolled_bench(steps, warmup, prec):
+    """Unrolled reconstruction network: 8 images of 256 x 256, 32 coils, os 8
+    (2048 samples), 64 groups of 32 samples, K = 80, R = 4; 10 gradient steps
+    with learnable step sizes, checkpointed every 2 steps; one training step
+    = forward + backward of 1/2 ||x_10 - x_true||^2 (random orthonormal bank)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_05418_amd import autograd as ga
+    from paper_2601_05418_amd import gpjc, synth
+    slices = synth.unrolled_slices(8, 0)
+    sl = slices[0]
+    g = sl.geom
+    rng = np.random.default_rng(41)
+    plan = gpjc.Plan.from_slice(sl, batch=8)
+    plan.set_compression(torch.as_tensor(synth.orthonormal_bank(g.n_groups, g.k, g.nc, g.patch_len, rng)).cuda())
+    truth = torch.as_tensor(np.ascontiguousarray(np.stack([s.image for s in slices]), np.complex64)).cuda()
+    y = plan.forward(truth)
+    x0 = torch.as_tensor(np.ascontiguousarray(synth.unit_noise(plan.image_shape(), rng), np.complex64)).cuda()
+    lip = plan.power_iteration(x0, 30, prec=prec) * 1.01
+    net = ga.UnrolledGD(plan, steps=10, alpha0=1.0 / lip, checkpoint_every=2, prec=prec)
+
+    def train_step():
+        net.zero_grad(set_to_none=True)
+        loss = 0.5 * (net(y) - truth).abs().pow(2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(warmup):
+        train_step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        loss = train_step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    plan.close()
+    return {
+        "workload": "unrolled GD, 8 x 256x256, 32 coils, os 8, 64 groups of 32, K=80, R=4; 10 steps, "
+                    "checkpoint every 2; forward + backward",
+        "precision": prec, "s_per_training_step": dt,
+        "normal_equivalents_per_step": 30, "op_apps_per_s": 30 * 8 / dt,
+        "final_loss": float(loss.detach()),
+    }
+
+
 def cpu_baseline(sl, budget_s):
     """The oracle's E'^H E' on the host cores: as many applications as fit in
     the time budget (at least one)."""
@@ -197,6 +243,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched CG measurement")
+    ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled-network training step")
     ap.add_argument("--tune-cache", default=None, help="tile autotuning cache file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (reference for byte counters)")
@@ -348,6 +395,10 @@ def main():
         plan.close()
         result["batch"] = batch_bench(max(1, args.steps // 2), 1, args.prec, args.tune_cache)
         log(f"batch: {result['batch']['s_per_batch']:.3f} s per 64 slices")
+    if not args.no_unrolled:
+        log("unrolled network training step ...")
+        result["unrolled"] = unrolled_bench(max(1, args.steps // 2), 1, args.prec)
+        log(f"unrolled: {result['unrolled']['s_per_training_step'] * 1e3:.1f} ms per training step")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(sl, args.cpu_seconds)

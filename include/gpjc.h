@@ -142,6 +142,25 @@ int gpjc_normal(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gp
 int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x,
                   int iters, int refine_every, double* h_resid);
 
+/* One gradient-descent step on 1/2 ||E' x - y||^2 (Eq. 16's objective),
+ * for unrolled reconstruction networks: with b = E'^H y precomputed (d_b,
+ * gpjc_adjoint's output layout [B][ny][nx]) and the step size in device
+ * memory (d_alpha, one float, so a learnable step needs no host sync),
+ *   d_r_out = E'^H E' x - b          (optional, the residual of the step)
+ *   d_x_out = x - alpha * (E'^H E' x - b).
+ * d_x_out must not alias d_x or d_b. */
+int gpjc_gd_step(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x, const gpjc_c64* d_b,
+                 const float* d_alpha, gpjc_c64* d_x_out, gpjc_c64* d_r_out);
+/* Backward of gpjc_gd_step for a real loss L, given g = dL/dx_out (the
+ * conjugate-Wirtinger gradient PyTorch uses: dL = Re <g, dx_out>) and the
+ * step's residual d_r:
+ *   d_gx_out     = g - alpha E'^H E' g     (dL/dx; optional)
+ *   d_gb_out     = alpha g                 (dL/db; optional)
+ *   d_galpha_out = -Re <g, r>              (dL/dalpha, one float on the device,
+ *                                          FP64 fixed-order reduction). */
+int gpjc_gd_step_backward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_g, const float* d_alpha,
+                          const gpjc_c64* d_r, gpjc_c64* d_gx_out, gpjc_c64* d_gb_out, float* d_galpha_out);
+
 /* FISTA (Eq. 17 with the wavelet term, TV weight 0) on
  * 1/2 ||E' x - y||^2 + lambda ||W x||_1, W the orthonormal separable Haar
  * transform with haar_levels levels (1..3, nx and ny divisible by

@@ -378,6 +378,36 @@ int gpjc_normal(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gp
   return finish(*plan, launch_combine(*plan, reinterpret_cast<float2*>(d_out)));
 }
 
+int gpjc_gd_step(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x, const gpjc_c64* d_b,
+                 const float* d_alpha, gpjc_c64* d_x_out, gpjc_c64* d_r_out) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_x || !d_b || !d_alpha || !d_x_out) return fail(GPJC_E_INVAL, "NULL buffer");
+  if (!aligned(d_x, 8) || !aligned(d_b, 8) || !aligned(d_x_out, 8) || !aligned(d_r_out, 8) || !aligned(d_alpha, 4))
+    return fail(GPJC_E_INVAL, "misaligned buffer");
+  if (d_x_out == d_x || d_x_out == d_b) return fail(GPJC_E_INVAL, "d_x_out must not alias d_x or d_b");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, run_gd_step(*plan, st, reinterpret_cast<const float2*>(d_x), reinterpret_cast<const float2*>(d_b),
+                                   d_alpha, reinterpret_cast<float2*>(d_x_out), reinterpret_cast<float2*>(d_r_out)));
+}
+
+int gpjc_gd_step_backward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_g, const float* d_alpha,
+                          const gpjc_c64* d_r, gpjc_c64* d_gx_out, gpjc_c64* d_gb_out, float* d_galpha_out) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!d_g || !d_alpha || !d_r || !d_galpha_out) return fail(GPJC_E_INVAL, "NULL buffer");
+  if (!aligned(d_g, 8) || !aligned(d_r, 8) || !aligned(d_gx_out, 8) || !aligned(d_gb_out, 8) ||
+      !aligned(d_alpha, 4) || !aligned(d_galpha_out, 4))
+    return fail(GPJC_E_INVAL, "misaligned buffer");
+  if (d_gx_out && (d_gx_out == d_g || d_gx_out == d_r)) return fail(GPJC_E_INVAL, "d_gx_out must not alias inputs");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, run_gd_step_backward(*plan, st, reinterpret_cast<const float2*>(d_g), d_alpha,
+                                            reinterpret_cast<const float2*>(d_r), reinterpret_cast<float2*>(d_gx_out),
+                                            reinterpret_cast<float2*>(d_gb_out), d_galpha_out));
+}
+
 int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, int refine_every,
                   double* h_resid) {
   GPJC_TRY(check_plan(plan));

@@ -166,6 +166,10 @@ int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double 
               int levels, double* h_obj);
 
 int run_power_iteration(Plan& pl, Store st, const float2* x0, int iters, double* h_lambda);
+int run_gd_step(const Plan& pl, Store st, const float2* x, const float2* b, const float* alpha, float2* x_out,
+                float2* r_out);
+int run_gd_step_backward(const Plan& pl, Store st, const float2* g, const float* alpha, const float2* r, float2* gx,
+                         float2* gb, float* galpha);
 int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
 
 // Lengths the FFT kernels are instantiated for.

@@ -265,6 +265,74 @@ int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine
 }
 
 // ---------------------------------------------------------------------------
+// One gradient step on 1/2 ||E' x - y||^2 and its backward, for unrolled
+// reconstruction: x_out = x - alpha (E'^H E' x - b) with b = E'^H y.
+// For a real loss L and upstream gradient g = dL/dx_out (the conjugate
+// Wirtinger convention, dL = Re <g, dx_out>):
+//   dL/dx     = (I - alpha E'^H E') g      (E'^H E' is Hermitian, alpha real)
+//   dL/db     = alpha g
+//   dL/dalpha = -Re <g, E'^H E' x - b>
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gd_update(const float2* __restrict__ part, int nchunk,
+                                                   const float2* __restrict__ x, const float2* __restrict__ b,
+                                                   const float* __restrict__ alpha, float2* __restrict__ x_out,
+                                                   float2* __restrict__ r_out, size_t n) {
+  const float a = *alpha;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 r = csub(sum_part(part, nchunk, n, i), b[i]);
+    const float2 xv = x[i];
+    x_out[i] = make_float2(fmaf(-a, r.x, xv.x), fmaf(-a, r.y, xv.y));
+    if (r_out) r_out[i] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gd_backward(const float2* __restrict__ part, int nchunk,
+                                                     const float2* __restrict__ g, const float2* __restrict__ r,
+                                                     const float* __restrict__ alpha, float2* __restrict__ gx,
+                                                     float2* __restrict__ gb, double* __restrict__ red, size_t n) {
+  __shared__ double sh[8];
+  const float a = *alpha;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 q = sum_part(part, nchunk, n, i);
+    const float2 gv = g[i];
+    if (gx) gx[i] = make_float2(fmaf(-a, q.x, gv.x), fmaf(-a, q.y, gv.y));
+    if (gb) gb[i] = make_float2(a * gv.x, a * gv.y);
+    const float2 rv = r[i];
+    acc += (double)gv.x * rv.x + (double)gv.y * rv.y;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+__global__ void k_store_neg_sum(const double* __restrict__ red, int nb, float* __restrict__ out) {
+  __shared__ double sh[8];
+  const double s = sum_partials(red, nb, sh);
+  if (threadIdx.x == 0) *out = (float)(-s);
+}
+
+int run_gd_step(const Plan& pl, Store st, const float2* x, const float2* b, const float* alpha, float2* x_out,
+                float2* r_out) {
+  GPJC_TRY(op_normal_part(pl, st, x));
+  StageScope sc(pl, GPJC_STAGE_SOLVER);
+  hipLaunchKernelGGL(k_gd_update, dim3(kRedBlocks), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, x, b, alpha,
+                     x_out, r_out, pl.img_elems());
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int run_gd_step_backward(const Plan& pl, Store st, const float2* g, const float* alpha, const float2* r, float2* gx,
+                         float2* gb, float* galpha) {
+  GPJC_TRY(op_normal_part(pl, st, g));
+  StageScope sc(pl, GPJC_STAGE_SOLVER);
+  hipLaunchKernelGGL(k_gd_backward, dim3(kRedBlocks), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, g, r, alpha,
+                     gx, gb, pl.red, pl.img_elems());
+  hipLaunchKernelGGL(k_store_neg_sum, dim3(1), dim3(256), 0, pl.stream, pl.red, kRedBlocks, galpha);
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // FISTA
 // ---------------------------------------------------------------------------
 template <int LEV>

@@ -73,6 +73,8 @@ _SIGS = {
     "gpjc_stage_times": (_I, [_VP, _VP, _VP]),
     "gpjc_set_gemm_config": (_I, [_VP, _I, _I, _I]),
     "gpjc_get_gemm_config": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "gpjc_gd_step": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
+    "gpjc_gd_step_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "gpjc_autotune": (_I, [_VP, _I, ctypes.c_char_p, _VP]),
     "gpjc_batch_create": (_I, [_VP, _I, _I, ctypes.POINTER(_VP)]),
     "gpjc_batch_destroy": (_I, [_VP]),
@@ -123,15 +125,22 @@ def _ptr(t: Optional[torch.Tensor]):
     """Device pointer of an output tensor (must be contiguous)."""
     if t is None:
         return None
-    if not t.is_contiguous():
-        raise ValueError("output tensor must be contiguous")
+    if not t.is_contiguous() or t.is_conj() or t.is_neg():
+        raise ValueError("output tensor must be contiguous and not a conjugate / negative view")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _materialise(t: torch.Tensor) -> torch.Tensor:
+    """Contiguous tensor whose memory holds its values: lazily conjugated or
+    negated views (PyTorch's conj / neg bits) are resolved, as the library
+    reads raw memory."""
+    return t.resolve_conj().resolve_neg().contiguous()
 
 
 def _dev_tensor(x, dtype, device):
     if isinstance(x, torch.Tensor):
-        return x.to(device=device, dtype=dtype).contiguous()
-    return torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dtype).contiguous()
+        return _materialise(x.to(device=device, dtype=dtype))
+    return _materialise(torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dtype))
 
 
 def _prec(p) -> int:
@@ -212,7 +221,7 @@ class Plan:
         outlives the queued work."""
         if not isinstance(t, torch.Tensor):
             t = torch.as_tensor(np.ascontiguousarray(t))
-        t = t.to(device=self.device, dtype=dtype).contiguous()
+        t = _materialise(t.to(device=self.device, dtype=dtype))
         self._inputs.append(t)
         return ctypes.c_void_p(t.data_ptr())
 
@@ -307,6 +316,26 @@ class Plan:
         _check(self.lib.gpjc_get_gemm_config(self.handle, *[ctypes.byref(x) for x in v]))
         return {"compress": v[0].value, "expand": v[1].value, "ksplit": v[2].value,
                 "n_compress": v[3].value, "n_expand": v[4].value}
+
+    def gd_step(self, x, b, alpha, prec="fp32", want_residual=True):
+        """x - alpha (E'^H E' x - b) and the residual E'^H E' x - b; alpha is a
+        one-element float32 device tensor."""
+        self._begin()
+        xo = self._empty(self.image_shape())
+        r = self._empty(self.image_shape()) if want_residual else None
+        _check(self.lib.gpjc_gd_step(self.handle, _prec(prec), self._in(x), self._in(b),
+                                     self._in(alpha, torch.float32), _ptr(xo), _ptr(r)))
+        return xo, r
+
+    def gd_step_backward(self, g, alpha, r, prec="fp32", want_gx=True, want_gb=True):
+        """(dL/dx, dL/db, dL/dalpha) of gd_step for upstream gradient g."""
+        self._begin()
+        gx = self._empty(self.image_shape()) if want_gx else None
+        gb = self._empty(self.image_shape()) if want_gb else None
+        ga = torch.empty((), dtype=torch.float32, device=self.device)
+        _check(self.lib.gpjc_gd_step_backward(self.handle, _prec(prec), self._in(g), self._in(alpha, torch.float32),
+                                              self._in(r), _ptr(gx), _ptr(gb), _ptr(ga)))
+        return gx, gb, ga
 
     def autotune(self, prec="fp32", cache_path=None):
         """Times the contraction tile shapes on this plan and installs the

@@ -105,3 +105,17 @@ def test_batch_and_autotune_argument_errors():
     assert lib.gpjc_batch_autotune(None, 0, None) == gpjc.GPJC_E_INVAL
     assert lib.gpjc_batch_destroy(None) == gpjc.GPJC_E_INVAL
     assert lib.gpjc_autotune(None, 0, None, None) == gpjc.GPJC_E_INVAL
+
+
+def test_binding_materialises_conjugate_views():
+    """Lazily conjugated / negated views carry their sign in a flag, not in
+    memory; the binding must resolve them before passing raw pointers."""
+    import torch
+    z = torch.tensor([1 + 2j, 3 - 4j], dtype=torch.complex64)
+    assert z.conj().is_conj()
+    assert torch.equal(gpjc._materialise(z.conj()), torch.tensor([1 - 2j, 3 + 4j], dtype=torch.complex64))
+    assert not gpjc._materialise(z.conj()).is_conj()
+    n = torch.tensor([1.0, -2.0])._neg_view()
+    assert torch.equal(gpjc._materialise(n), torch.tensor([-1.0, 2.0]))
+    with pytest.raises(ValueError):
+        gpjc._ptr(z.conj())
