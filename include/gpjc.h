@@ -203,13 +203,14 @@ int gpjc_stage_timing(gpjc_plan* plan, int enable);
 int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches);
 
 /* Work-group tile shape of the two group contractions and the contraction
- * split of the compressing one (1..8).  The defaults come from the plan's
- * shapes; an autotuner may time the variants with gpjc_stage_timing and
- * install the fastest.  Changes only speed, never results beyond FP32
- * summation order. */
-int gpjc_set_gemm_config(gpjc_plan* plan, int compress_variant, int expand_variant, int ksplit);
-int gpjc_get_gemm_config(const gpjc_plan* plan, int* compress_variant, int* expand_variant, int* ksplit,
-                         int* n_compress_variants, int* n_expand_variants);
+ * split of the compressing one (1..8), for one precision class: FP32, or the
+ * two 16-bit types together (BF16 and FP16 share one setting).  Variant
+ * numbers index per-class tables of built shapes.  The defaults come from
+ * the plan's sizes; gpjc_autotune times the variants and installs the
+ * fastest.  Changes only speed, never results beyond FP32 summation order. */
+int gpjc_set_gemm_config(gpjc_plan* plan, gpjc_prec prec, int compress_variant, int expand_variant, int ksplit);
+int gpjc_get_gemm_config(const gpjc_plan* plan, gpjc_prec prec, int* compress_variant, int* expand_variant,
+                         int* ksplit, int* n_compress_variants, int* n_expand_variants);
 
 /* Tile autotuning of the group contractions: times every built tile shape
  * (and contraction split) of both contractions on the plan's own buffers and

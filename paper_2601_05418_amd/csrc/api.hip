@@ -139,16 +139,8 @@ static void choose_launch(Plan& pl) {
   pl.f3_lpb = std::max(1, std::min(lpb_max, nlines / 1024));
   pl.f3_tb = std::max(1, std::min(16, (lds_f2 - pl.ny) / (2 * lsy)));
 
-  if (pl.compressed) {
-    const int kd = 2 * pl.ns;
-    pl.gemm_cvar = 2 * pl.K >= 128 ? 0 : 3;
-    pl.gemm_evar = 1;
-    const int tm = compress_tile_rows(pl), tn = compress_tile_cols(pl);
-    const long tiles = (long)((pl.ny + tn - 1) / tn) * ((2 * pl.K + tm - 1) / tm) * pl.B * pl.np;
-    int ks = (int)std::max<long>(1, (1024 + tiles - 1) / tiles);
-    ks = std::min(std::min(ks, std::max(1, kd / 128)), kMaxKsplit);
-    pl.gemm_ksplit = ks;
-  }
+  if (pl.compressed) default_gemm_config(pl);
+
 }
 
 static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, const gpjc_c64* d_psf,
@@ -170,7 +162,7 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
     pl.np = pl.nt / pl.P;
     pl.G = g->n_groups;
     pl.K = g->k;
-    pl.Kp = (pl.K + 7) / 8 * 8;
+    pl.Kp = (pl.K + 15) / 16 * 16;  // whole 32-element blocks of the 16-bit expanding contraction
     pl.ns = pl.nc * pl.P;
     pl.pgroup_h.assign(g->patch_group, g->patch_group + pl.np);
   }
@@ -493,26 +485,30 @@ int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches) {
   return GPJC_OK;
 }
 
-int gpjc_set_gemm_config(gpjc_plan* plan, int compress_variant, int expand_variant, int ksplit) {
+int gpjc_set_gemm_config(gpjc_plan* plan, gpjc_prec prec, int compress_variant, int expand_variant, int ksplit) {
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "GEMM configuration needs a compressed plan");
+  if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
   if (compress_variant < 0 || compress_variant >= gemm_compress_variants() || expand_variant < 0 ||
       expand_variant >= gemm_expand_variants())
     return fail(GPJC_E_INVAL, "unknown GEMM variant");
   if (ksplit < 1 || ksplit > kMaxKsplit) return fail(GPJC_E_INVAL, "ksplit out of range");
-  plan->gemm_cvar = compress_variant;
-  plan->gemm_evar = expand_variant;
-  plan->gemm_ksplit = ksplit;
+  Plan::GemmCfg& c = plan->cfg(prec == GPJC_FP32 ? Store::F32 : Store::BF16);
+  c.cvar = compress_variant;
+  c.evar = expand_variant;
+  c.ksplit = ksplit;
   ++plan->config_gen;
   return GPJC_OK;
 }
 
-int gpjc_get_gemm_config(const gpjc_plan* plan, int* compress_variant, int* expand_variant, int* ksplit,
-                         int* n_compress_variants, int* n_expand_variants) {
+int gpjc_get_gemm_config(const gpjc_plan* plan, gpjc_prec prec, int* compress_variant, int* expand_variant,
+                         int* ksplit, int* n_compress_variants, int* n_expand_variants) {
   GPJC_TRY(check_plan(plan));
-  if (compress_variant) *compress_variant = plan->gemm_cvar;
-  if (expand_variant) *expand_variant = plan->gemm_evar;
-  if (ksplit) *ksplit = plan->gemm_ksplit;
+  if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
+  const Plan::GemmCfg& c = plan->cfg(prec == GPJC_FP32 ? Store::F32 : Store::BF16);
+  if (compress_variant) *compress_variant = c.cvar;
+  if (expand_variant) *expand_variant = c.evar;
+  if (ksplit) *ksplit = c.ksplit;
   if (n_compress_variants) *n_compress_variants = gemm_compress_variants();
   if (n_expand_variants) *n_expand_variants = gemm_expand_variants();
   return GPJC_OK;

@@ -17,7 +17,7 @@
 // (i, q) holds kk = kb + 8q .. kb + 8q + 7 of row i (16 bytes), one MFMA per
 // block, FP32 accumulation.
 // Either way one 16-byte load per lane and operand tile feeds a block, and
-// loads run kDepth - 1 blocks ahead of the MFMAs.
+// loads run a few blocks (the ring depth less one) ahead of the MFMAs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +34,7 @@ constexpr int kDepth = 3;  // register ring depth of the operand pipeline
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Operand element type and contraction block per storage precision.
 template <Store ST>
@@ -299,6 +300,511 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand(ExpandArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Buffer-addressed forms.  Each lane's operand rows are fixed for the whole
+// contraction, so a lane keeps one 32-bit byte offset per operand tile and
+// every block adds the same (wave-uniform) increment to all of them: the
+// inner loop does no per-lane address arithmetic or masking.  Out-of-range
+// rows, columns and blocks past the end of the chunk get offsets >= 2^31;
+// buffer loads beyond the descriptor's extent return zeros.  This needs each
+// operand region below 2^31 bytes and, for the compressing contraction, 2P a
+// multiple of the block so that every lane crosses a coil boundary at the
+// same block.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOOB = 0x80000000u;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline floatx4 bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+
+// MFMA geometry of the buffer-addressed forms: FP32 uses the 32 x 32 x 2
+// instruction (four independent 32 x 32 accumulators sustain close to the
+// FP32 peak, the 16 x 16 x 4 form does not), the 16-bit types the 16 x 16 x 32
+// one.  A lane (i, h) (i = lane % T, h = lane / T) holds LW consecutive
+// contraction elements kb + LW h .. of its row / column; the result register
+// r of a lane holds row row_of(r, h) and column i of the T x T tile.
+template <Store ST>
+struct Geo {
+  static constexpr int T = 16, KB = 32, LW = 8, NE = 1, NR = 4;
+  using Acc = floatx4;
+  __device__ static int row_of(int r, int h) { return 4 * h + r; }
+  __device__ static Acc step(const floatx4& a, const floatx4& b, int, const Acc& c) { return mma_step<ST>(a, b, 0, c); }
+};
+template <>
+struct Geo<Store::F32> {
+  static constexpr int T = 32, KB = 8, LW = 4, NE = 4, NR = 16;
+  using Acc = floatx16;
+  __device__ static int row_of(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+  __device__ static Acc step(const floatx4& a, const floatx4& b, int e, const Acc& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], c, 0, 0, 0);
+  }
+};
+
+template <int WM, int WN, int MT, int NT, Store ST, int DEPTH>
+__global__ __launch_bounds__(64 * WM * WN) void k_compress_u(CompressArgs a) {
+  using G = Geo<ST>;
+  using E = typename Mma<ST>::E;
+  constexpr int T = G::T, KB = G::KB, LW = G::LW, NE = G::NE, NR = G::NR;
+  constexpr uint32_t BB = KB * sizeof(E);
+  constexpr int TM = WM * MT * T, TN = WN * NT * T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane % T, lh = lane / T;
+  const int wm = wave / WN, wn = wave % WN;
+  const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
+  const int total = tiles_n * tiles_m * a.B * a.np * a.ksplit;
+  const int logical = xcd_logical(blockIdx.x, total);
+  const int tn = logical % tiles_n;
+  const int rest = logical / tiles_n;
+  const int tm = rest % tiles_m, z = rest / tiles_m;
+  const int ks = z % a.ksplit, bp = z / a.ksplit;
+  const int b = bp / a.np, p = bp - b * a.np;
+  const int g = a.pgroup[p];
+  const int row0 = tm * TM + wm * MT * T, col0 = tn * TN + wn * NT * T;
+  const int twoP = 2 * a.P;
+  const size_t cstride = (size_t)a.N * a.nt * 2;  // elements between coils
+
+  const E* Ab = static_cast<const E*>(a.A) + (size_t)g * a.M * a.KD;
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)a.M * a.KD * sizeof(E)));
+  const E* Bb = static_cast<const E*>(a.in) + (size_t)b * a.nc * cstride + (size_t)p * twoP;
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(Bb, (uint32_t)((a.nc * cstride - (size_t)p * twoP) * sizeof(E)));
+
+  const int kbeg = ks * a.kchunk;
+  const int kend = min(a.KD, kbeg + a.kchunk);
+  const int nblk = (kend - kbeg) / KB;
+  int n = kbeg / twoP;  // uniform coil and in-patch position of the block
+  int jj = kbeg - n * twoP;
+  uint32_t va[MT], vb[NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int r = row0 + T * m + li;
+    va[m] = r < a.M ? (uint32_t)(((size_t)r * a.KD + kbeg + LW * lh) * sizeof(E)) : kOOB;
+  }
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    const int cc = col0 + T * c + li;
+    vb[c] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)n * cstride + jj + LW * lh) * sizeof(E)) : kOOB;
+  }
+  if (nblk <= 0) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) va[m] |= kOOB;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) vb[c] |= kOOB;
+  }
+  const uint32_t wrap = (uint32_t)((cstride - (size_t)(twoP - KB)) * sizeof(E));
+  int loaded = 0;
+  auto load = [&](floatx4(&xa)[MT], floatx4(&xb)[NT]) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) xa[m] = bload(rA, va[m]);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) xb[c] = bload(rB, vb[c]);
+    jj += KB;
+    uint32_t inc = BB;
+    if (jj == twoP) {
+      jj = 0;
+      inc = wrap;
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) va[m] += BB;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) vb[c] += inc;
+    if (++loaded == nblk) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m) va[m] |= kOOB;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) vb[c] |= kOOB;
+    }
+  };
+  typename G::Acc acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
+  floatx4 ra[DEPTH][MT], rb[DEPTH][NT];
+#pragma unroll
+  for (int s = 0; s < DEPTH - 1; ++s) load(ra[s], rb[s]);
+  for (int kb = 0; kb < nblk; kb += DEPTH) {
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s) {
+      load(ra[(s + DEPTH - 1) % DEPTH], rb[(s + DEPTH - 1) % DEPTH]);
+      if (kb + s < nblk) {  // uniform: the last round may hold fewer than DEPTH blocks
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(ra[s][m], rb[s][c], e, acc[m][c]);
+      }
+    }
+  }
+  // rows pair up as (k, re), (k, im); row_of(r, h) is even for even r
+  float2* out = a.out + ks * a.split_stride + ((size_t)b * a.np + p) * a.K * a.N;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const int col = col0 + T * c + li;
+#pragma unroll
+      for (int r = 0; r < NR; r += 2) {
+        const int row = row0 + T * m + G::row_of(r, lh);
+        if (col < a.N && row < a.M) out[(size_t)(row >> 1) * a.N + col] = make_float2(acc[m][c][r], acc[m][c][r + 1]);
+      }
+    }
+}
+
+template <int WM, int WN, int MT, int NT, Store ST, int DEPTH>
+__global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
+  using G = Geo<ST>;
+  using E = typename Mma<ST>::E;
+  constexpr int T = G::T, KB = G::KB, LW = G::LW, NE = G::NE, NR = G::NR;
+  constexpr uint32_t BB = KB * sizeof(E);
+  constexpr int TM = WM * MT * T, TN = WN * NT * T;
+  constexpr int LDT = TN + 4;
+  __shared__ float tile[TM * LDT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane % T, lh = lane / T;
+  const int wm = wave / WN, wn = wave % WN;
+  const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
+  const int total = tiles_n * tiles_m * a.B * a.np;
+  const int logical = xcd_logical(blockIdx.x, total);
+  const int tn = logical % tiles_n;
+  const int rest = logical / tiles_n;
+  const int tm = rest % tiles_m, bp = rest / tiles_m;
+  const int b = bp / a.np, p = bp - b * a.np;
+  const int g = a.pgroup[p];
+  const int row0 = tm * TM + wm * MT * T, col0 = tn * TN + wn * NT * T;
+
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(static_cast<const E*>(a.Zt) + (size_t)bp * a.M * a.KD,
+                                              (uint32_t)((size_t)a.M * a.KD * sizeof(E)));
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const E*>(a.AH) + (size_t)g * a.N * a.KD,
+                                              (uint32_t)((size_t)a.N * a.KD * sizeof(E)));
+  const int nblk = a.KD / KB;
+  uint32_t va[MT], vb[NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int r = row0 + T * m + li;
+    va[m] = r < a.M ? (uint32_t)(((size_t)r * a.KD + LW * lh) * sizeof(E)) : kOOB;
+  }
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    const int cc = col0 + T * c + li;
+    vb[c] = cc < a.N ? (uint32_t)(((size_t)cc * a.KD + LW * lh) * sizeof(E)) : kOOB;
+  }
+  int loaded = 0;
+  auto load = [&](floatx4(&xa)[MT], floatx4(&xb)[NT]) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) xa[m] = bload(rA, va[m]);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) xb[c] = bload(rB, vb[c]);
+#pragma unroll
+    for (int m = 0; m < MT; ++m) va[m] += BB;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) vb[c] += BB;
+    if (++loaded == nblk) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m) va[m] |= kOOB;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) vb[c] |= kOOB;
+    }
+  };
+  typename G::Acc acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
+  floatx4 ra[DEPTH][MT], rb[DEPTH][NT];
+#pragma unroll
+  for (int s = 0; s < DEPTH - 1; ++s) load(ra[s], rb[s]);
+  for (int kb = 0; kb < nblk; kb += DEPTH) {
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s) {
+      load(ra[(s + DEPTH - 1) % DEPTH], rb[(s + DEPTH - 1) % DEPTH]);
+      if (kb + s < nblk) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(ra[s][m], rb[s][c], e, acc[m][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        tile[(wm * MT * T + T * m + G::row_of(r, lh)) * LDT + wn * NT * T + T * c + li] = acc[m][c][r];
+  __syncthreads();
+  const int twoP = 2 * a.P;
+  const int rbase = tm * TM, cbase = tn * TN;
+  for (int e = threadIdx.x; e < TM * (TN / 4); e += 64 * WM * WN) {
+    const int rl = e / (TN / 4), cl = (e - rl * (TN / 4)) * 4;
+    const int y = rbase + rl, col = cbase + cl;
+    if (y >= a.M || col >= a.N) continue;
+    const int n = col / twoP, jj = col - n * twoP;
+    const size_t fi = (((size_t)b * a.nc + n) * a.M + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
+    const float* src = tile + rl * LDT + cl;
+    if constexpr (ST == Store::F32) {
+      *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(a.W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
+    } else {
+      uint2 v;
+      v.x = to_bits16<ST>(src[0]) | (to_bits16<ST>(src[1]) << 16);
+      v.y = to_bits16<ST>(src[2]) | (to_bits16<ST>(src[3]) << 16);
+      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.W) + fi) = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 compressing contraction staged through LDS.  The operand layout of an
+// MFMA spans 32 rows per load instruction, so register-direct loads touch 32
+// cache lines each; here the work-group loads k-tiles of 32 elements (one
+// 128-byte line per row) cooperatively, eight lanes per row, into LDS, and
+// the waves read their MFMA fragments from there.  The next k-tile is
+// prefetched into registers while the current one is multiplied.  Row
+// stride 36 floats (144 bytes, an odd multiple of 16): the 16-byte fragment
+// reads of one pass fall on distinct bank groups.  Needs 2P a multiple of 32
+// (a k-tile never crosses a coil) and the k-split chunk a multiple of 32.
+// ---------------------------------------------------------------------------
+template <int WM, int WN, int MT, int NT>
+__global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
+  using G = Geo<Store::F32>;
+  constexpr int T = 32, KT = 32, LS = KT + 4;
+  constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
+  constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;  // 16-byte chunks per thread per k-tile
+  static_assert(AR * NTHR == TM * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
+  __shared__ floatx4 smem[(TM + TN) * LS / 4];
+  float* As = reinterpret_cast<float*>(smem);
+  float* Bs = As + TM * LS;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int wm = wave / WN, wn = wave % WN;
+  const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
+  const int total = tiles_n * tiles_m * a.B * a.np * a.ksplit;
+  const int logical = xcd_logical(blockIdx.x, total);
+  const int tn = logical % tiles_n;
+  const int rest = logical / tiles_n;
+  const int tm = rest % tiles_m, z = rest / tiles_m;
+  const int ks = z % a.ksplit, bp = z / a.ksplit;
+  const int b = bp / a.np, p = bp - b * a.np;
+  const int g = a.pgroup[p];
+  const int twoP = 2 * a.P;
+  const size_t cstride = (size_t)a.N * a.nt * 2;
+
+  const float* Ab = static_cast<const float*>(a.A) + (size_t)g * a.M * a.KD;
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)a.M * a.KD * 4));
+  const float* Bb = static_cast<const float*>(a.in) + (size_t)b * a.nc * cstride + (size_t)p * twoP;
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(Bb, (uint32_t)((a.nc * cstride - (size_t)p * twoP) * 4));
+
+  const int kbeg = ks * a.kchunk;
+  const int kend = min(a.KD, kbeg + a.kchunk);
+  const int nst = max(0, (kend - kbeg) / KT);
+  int n = kbeg / twoP;
+  int jj = kbeg - n * twoP;
+  const int c16 = tid & 7;  // 16-byte chunk of a row handled by this thread
+  uint32_t va[AR], vb[BR];
+#pragma unroll
+  for (int r = 0; r < AR; ++r) {
+    const int row = tm * TM + (tid >> 3) + r * (NTHR / 8);
+    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + kbeg + 4 * c16) * 4) : kOOB;
+  }
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)n * cstride + jj + 4 * c16) * 4) : kOOB;
+  }
+  const uint32_t wrap = (uint32_t)((cstride - (size_t)(twoP - KT)) * 4);
+  floatx4 pa[AR], pb[BR];
+  auto fetch = [&]() {
+#pragma unroll
+    for (int r = 0; r < AR; ++r) pa[r] = bload(rA, va[r]);
+#pragma unroll
+    for (int r = 0; r < BR; ++r) pb[r] = bload(rB, vb[r]);
+    jj += KT;
+    uint32_t inc = KT * 4;
+    if (jj == twoP) {
+      jj = 0;
+      inc = wrap;
+    }
+#pragma unroll
+    for (int r = 0; r < AR; ++r) va[r] += KT * 4;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) vb[r] += inc;
+  };
+  typename G::Acc acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[m][c][r] = 0.f;
+  if (nst > 0) fetch();
+  for (int st = 0; st < nst; ++st) {
+    __syncthreads();  // the previous k-tile has been read
+#pragma unroll
+    for (int r = 0; r < AR; ++r)
+      *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[r];
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+      *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[r];
+    __syncthreads();
+    if (st + 1 < nst) fetch();
+#pragma unroll
+    for (int j = 0; j < KT / 8; ++j) {
+      floatx4 fa[MT], fb[NT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + 8 * j + 4 * lh);
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 8 * j + 4 * lh);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+    }
+  }
+  float2* out = a.out + ks * a.split_stride + ((size_t)b * a.np + p) * a.K * a.N;
+  const int row0 = tm * TM + wm * MT * T, col0 = tn * TN + wn * NT * T;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const int col = col0 + T * c + li;
+#pragma unroll
+      for (int r = 0; r < 16; r += 2) {
+        const int row = row0 + T * m + G::row_of(r, lh);
+        if (col < a.N && row < a.M) out[(size_t)(row >> 1) * a.N + col] = make_float2(acc[m][c][r], acc[m][c][r + 1]);
+      }
+    }
+}
+
+// FP32 expanding contraction staged through LDS, as k_compress_lds: both
+// operands (Z^T rows and rows of the real-form bank) are contiguous along the
+// contraction, which has 2 Kp (a multiple of 32) elements.  The output tile
+// is staged through the same LDS to write whole W row segments.
+template <int WM, int WN, int MT, int NT>
+__global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
+  using G = Geo<Store::F32>;
+  constexpr int T = 32, KT = 32, LS = KT + 4;
+  constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
+  constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;
+  static_assert(AR * NTHR == TM * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
+  constexpr int LDT = TN + 4;
+  constexpr int SM = ((TM + TN) * LS > TM * LDT ? (TM + TN) * LS : TM * LDT);
+  __shared__ floatx4 smem[SM / 4];
+  float* As = reinterpret_cast<float*>(smem);
+  float* Bs = As + TM * LS;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int wm = wave / WN, wn = wave % WN;
+  const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
+  const int total = tiles_n * tiles_m * a.B * a.np;
+  const int logical = xcd_logical(blockIdx.x, total);
+  const int tn = logical % tiles_n;
+  const int rest = logical / tiles_n;
+  const int tm = rest % tiles_m, bp = rest / tiles_m;
+  const int b = bp / a.np, p = bp - b * a.np;
+  const int g = a.pgroup[p];
+
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(static_cast<const float*>(a.Zt) + (size_t)bp * a.M * a.KD,
+                                              (uint32_t)((size_t)a.M * a.KD * 4));
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const float*>(a.AH) + (size_t)g * a.N * a.KD,
+                                              (uint32_t)((size_t)a.N * a.KD * 4));
+  const int nst = a.KD / KT;
+  const int c16 = tid & 7;
+  uint32_t va[AR], vb[BR];
+#pragma unroll
+  for (int r = 0; r < AR; ++r) {
+    const int row = tm * TM + (tid >> 3) + r * (NTHR / 8);
+    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + 4 * c16) * 4) : kOOB;
+  }
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.KD + 4 * c16) * 4) : kOOB;
+  }
+  floatx4 pa[AR], pb[BR];
+  auto fetch = [&]() {
+#pragma unroll
+    for (int r = 0; r < AR; ++r) pa[r] = bload(rA, va[r]);
+#pragma unroll
+    for (int r = 0; r < BR; ++r) pb[r] = bload(rB, vb[r]);
+#pragma unroll
+    for (int r = 0; r < AR; ++r) va[r] += KT * 4;
+#pragma unroll
+    for (int r = 0; r < BR; ++r) vb[r] += KT * 4;
+  };
+  typename G::Acc acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[m][c][r] = 0.f;
+  fetch();
+  for (int st = 0; st < nst; ++st) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < AR; ++r)
+      *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[r];
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+      *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[r];
+    __syncthreads();
+    if (st + 1 < nst) fetch();
+#pragma unroll
+    for (int j = 0; j < KT / 8; ++j) {
+      floatx4 fa[MT], fb[NT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + 8 * j + 4 * lh);
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 8 * j + 4 * lh);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+    }
+  }
+  __syncthreads();  // the operand tiles are dead; the LDS now stages the output tile
+  float* tile = reinterpret_cast<float*>(smem);
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        tile[(wm * MT * T + T * m + G::row_of(r, lh)) * LDT + wn * NT * T + T * c + li] = acc[m][c][r];
+  __syncthreads();
+  const int twoP = 2 * a.P;
+  const int rbase = tm * TM, cbase = tn * TN;
+  for (int e = tid; e < TM * (TN / 4); e += NTHR) {
+    const int rl = e / (TN / 4), cl = (e - rl * (TN / 4)) * 4;
+    const int y = rbase + rl, col = cbase + cl;
+    if (y >= a.M || col >= a.N) continue;
+    const int n = col / twoP, jj = col - n * twoP;
+    const size_t fi = (((size_t)b * a.nc + n) * a.M + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
+    const float* src = tile + rl * LDT + cl;
+    *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(a.W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
+  }
+}
+
 // Real forms of the bank: Aexp [G][2K][2ns] (compressing), AH [G][2ns][2kp]
 // (expanding), in FP32 and, when the 16-bit copies exist, rounded once more
 // (nearest even) to BF16 (index 0) and FP16 (index 1) in the same layouts.
@@ -339,46 +845,112 @@ __global__ void k_expand_bank(const double2* __restrict__ A, BankOut o, int G, i
   }
 }
 
-// Tile-shape tables (waves WM x WN, wave tile MT x NT blocks of 16).
+// Tile-shape tables: waves WM x WN per work-group, wave tile MT x NT MFMA
+// tiles (32 x 32 for the FP32 buffer-addressed forms, 16 x 16 for the 16-bit
+// ones), register-ring depth.  Index 0 is the default of its class.  The
+// general forms (geometries the buffer-addressed ones do not cover) use one
+// fixed shape.
 struct Shape {
-  int wm, wn, mt, nt;
+  int wm, wn, mt, nt, depth;
 };
-constexpr Shape kCompressShapes[] = {{4, 1, 2, 2}, {4, 1, 2, 4}, {2, 2, 2, 2}, {1, 4, 2, 2}, {2, 2, 2, 4}};
-constexpr Shape kExpandShapes[] = {{1, 4, 2, 2}, {1, 4, 2, 4}, {2, 2, 2, 4}, {1, 4, 1, 4}, {2, 2, 2, 2}};
-constexpr int kNumCompress = sizeof(kCompressShapes) / sizeof(Shape);
-constexpr int kNumExpand = sizeof(kExpandShapes) / sizeof(Shape);
+constexpr int kNumShapes = 8;
+constexpr Shape kCompress32[kNumShapes] = {{2, 1, 2, 2, 3}, {1, 1, 4, 1, 3}, {2, 1, 2, 1, 3}, {1, 2, 4, 1, 3},
+                                           {2, 2, 2, 1, 3}, {1, 1, 4, 1, 5}, {2, 1, 2, 2, 4}, {1, 4, 1, 1, 3}};
+constexpr Shape kExpand32[kNumShapes] = {{1, 2, 1, 4, 3}, {1, 4, 1, 2, 3}, {1, 2, 2, 2, 3}, {1, 1, 1, 4, 3},
+                                         {2, 2, 1, 2, 3}, {1, 2, 1, 4, 4}, {1, 4, 1, 1, 3}, {1, 2, 2, 2, 4}};
+constexpr Shape kCompress16[kNumShapes] = {{2, 1, 4, 4, 3}, {2, 1, 4, 4, 4}, {2, 1, 4, 2, 3}, {4, 1, 2, 2, 3},
+                                           {4, 1, 2, 4, 4}, {2, 2, 2, 2, 3}, {1, 4, 2, 2, 3}, {2, 1, 4, 2, 5}};
+constexpr Shape kExpand16[kNumShapes] = {{1, 2, 4, 4, 4}, {1, 2, 4, 4, 3}, {1, 4, 2, 4, 3}, {2, 2, 4, 2, 3},
+                                         {1, 4, 2, 2, 3}, {1, 4, 2, 4, 5}, {2, 2, 2, 4, 3}, {1, 4, 1, 4, 3}};
+constexpr Shape kCompressLds[kNumShapes] = {{4, 1, 1, 1, 0}, {4, 1, 1, 2, 0}, {2, 2, 2, 1, 0}, {2, 1, 2, 1, 0},
+                                            {4, 2, 1, 1, 0}, {2, 2, 1, 2, 0}, {2, 1, 1, 1, 0}, {1, 4, 1, 1, 0}};
+constexpr Shape kExpandLds[kNumShapes] = {{1, 4, 1, 1, 0}, {1, 4, 1, 2, 0}, {2, 2, 1, 1, 0}, {1, 2, 1, 1, 0},
+                                          {2, 4, 1, 1, 0}, {1, 2, 1, 2, 0}, {1, 2, 1, 4, 0}, {2, 2, 1, 2, 0}};
+constexpr Shape kCompressGeneral = {4, 1, 2, 2, 3};
+constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
+
+// Whether the buffer-addressed forms apply (see above).
+bool compress_uniform(const CompressArgs& a, Store st) {
+  const int kb = st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB;
+  const size_t esz = st == Store::F32 ? 4 : 2;
+  return (2 * a.P) % kb == 0 && a.kchunk % kb == 0 && (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB &&
+         (size_t)a.M * a.KD * esz < kOOB;
+}
+bool compress_staged(const CompressArgs& a, Store st) {
+  return st == Store::F32 && (2 * a.P) % 32 == 0 && a.kchunk % 32 == 0 && compress_uniform(a, st);
+}
+bool expand_uniform(const ExpandArgs& a, Store st) {
+  const int kb = st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB;
+  const size_t esz = st == Store::F32 ? 4 : 2;
+  return a.KD % kb == 0 && (size_t)a.M * a.KD * esz < kOOB && (size_t)a.N * a.KD * esz < kOOB;
+}
+
+int tiles(int n, int t) { return (n + t - 1) / t; }
 
 template <int V, Store ST>
-void launch_compress_v(dim3 grid, hipStream_t st, const CompressArgs& a) {
-  constexpr Shape S = kCompressShapes[V];
-  hipLaunchKernelGGL((k_compress<S.wm, S.wn, S.mt, S.nt, ST>), grid, dim3(64 * S.wm * S.wn), 0, st, a);
+void launch_compress_v(hipStream_t s, const CompressArgs& a) {
+  const int rest = a.B * a.np * a.ksplit;
+  if (compress_staged(a, ST)) {
+    constexpr Shape S = kCompressLds[V];
+    const dim3 grid(tiles(a.N, S.wn * S.nt * 32) * tiles(a.M, S.wm * S.mt * 32) * rest);
+    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+  } else if (compress_uniform(a, ST)) {
+    constexpr Shape S = ST == Store::F32 ? kCompress32[V] : kCompress16[V];
+    constexpr int T = Geo<ST>::T;
+    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
+    hipLaunchKernelGGL((k_compress_u<S.wm, S.wn, S.mt, S.nt, ST, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+  } else {
+    constexpr Shape S = kCompressGeneral;
+    const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
+    hipLaunchKernelGGL((k_compress<S.wm, S.wn, S.mt, S.nt, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+  }
 }
 template <int V, Store ST>
-void launch_expand_v(dim3 grid, hipStream_t st, const ExpandArgs& a) {
-  constexpr Shape S = kExpandShapes[V];
-  hipLaunchKernelGGL((k_expand<S.wm, S.wn, S.mt, S.nt, ST>), grid, dim3(64 * S.wm * S.wn), 0, st, a);
+void launch_expand_v(hipStream_t s, const ExpandArgs& a) {
+  const int rest = a.B * a.np;
+  if (ST == Store::F32 && a.KD % 32 == 0 && expand_uniform(a, ST)) {
+    constexpr Shape S = kExpandLds[V];
+    const dim3 grid(tiles(a.N, S.wn * S.nt * 32) * tiles(a.M, S.wm * S.mt * 32) * rest);
+    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+  } else if (expand_uniform(a, ST)) {
+    constexpr Shape S = ST == Store::F32 ? kExpand32[V] : kExpand16[V];
+    constexpr int T = Geo<ST>::T;
+    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
+    hipLaunchKernelGGL((k_expand_u<S.wm, S.wn, S.mt, S.nt, ST, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+  } else {
+    constexpr Shape S = kExpandGeneral;
+    const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
+    hipLaunchKernelGGL((k_expand<S.wm, S.wn, S.mt, S.nt, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+  }
 }
 
 template <Store ST>
-void compress_variant(int v, dim3 grid, hipStream_t st, const CompressArgs& a) {
+void compress_variant(int v, hipStream_t s, const CompressArgs& a) {
   switch (v) {
-    case 0: launch_compress_v<0, ST>(grid, st, a); break;
-    case 1: launch_compress_v<1, ST>(grid, st, a); break;
-    case 2: launch_compress_v<2, ST>(grid, st, a); break;
-    case 3: launch_compress_v<3, ST>(grid, st, a); break;
-    default: launch_compress_v<4, ST>(grid, st, a); break;
+    case 0: launch_compress_v<0, ST>(s, a); break;
+    case 1: launch_compress_v<1, ST>(s, a); break;
+    case 2: launch_compress_v<2, ST>(s, a); break;
+    case 3: launch_compress_v<3, ST>(s, a); break;
+    case 4: launch_compress_v<4, ST>(s, a); break;
+    case 5: launch_compress_v<5, ST>(s, a); break;
+    case 6: launch_compress_v<6, ST>(s, a); break;
+    default: launch_compress_v<7, ST>(s, a); break;
   }
 }
 template <Store ST>
-void expand_variant(int v, dim3 grid, hipStream_t st, const ExpandArgs& a) {
+void expand_variant(int v, hipStream_t s, const ExpandArgs& a) {
   switch (v) {
-    case 0: launch_expand_v<0, ST>(grid, st, a); break;
-    case 1: launch_expand_v<1, ST>(grid, st, a); break;
-    case 2: launch_expand_v<2, ST>(grid, st, a); break;
-    case 3: launch_expand_v<3, ST>(grid, st, a); break;
-    default: launch_expand_v<4, ST>(grid, st, a); break;
+    case 0: launch_expand_v<0, ST>(s, a); break;
+    case 1: launch_expand_v<1, ST>(s, a); break;
+    case 2: launch_expand_v<2, ST>(s, a); break;
+    case 3: launch_expand_v<3, ST>(s, a); break;
+    case 4: launch_expand_v<4, ST>(s, a); break;
+    case 5: launch_expand_v<5, ST>(s, a); break;
+    case 6: launch_expand_v<6, ST>(s, a); break;
+    default: launch_expand_v<7, ST>(s, a); break;
   }
 }
+static_assert(kNumShapes == 8, "the variant switches list every shape");
 
 int bank16_index(const Plan& pl, Store st) {
   const int i = st == Store::BF16 ? 0 : 1;
@@ -387,7 +959,9 @@ int bank16_index(const Plan& pl, Store st) {
   return i;
 }
 
-int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* out, int ksplit) {
+int kblock(Store st) { return st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB; }
+
+int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* out, int ksplit, int cvar) {
   CompressArgs a;
   if (st == Store::F32) {
     a.A = pl.Aexp;
@@ -410,16 +984,13 @@ int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* ou
   a.K = pl.K;
   a.B = pl.B;
   a.ksplit = ksplit;
-  const int kb = st == Store::F32 ? Mma<Store::F32>::KB : Mma<Store::BF16>::KB;
+  const int kb = 32;  // the staged FP32 form takes 32-element k-tiles, the general forms 16 or 32
   a.kchunk = ((a.KD + ksplit - 1) / ksplit + kb - 1) / kb * kb;
   a.split_stride = (size_t)pl.B * pl.np * pl.K * ncol;
-  const Shape S = kCompressShapes[pl.gemm_cvar];
-  const int TM = S.wm * S.mt * 16, TN = S.wn * S.nt * 16;
-  const dim3 grid(((ncol + TN - 1) / TN) * ((a.M + TM - 1) / TM) * pl.B * pl.np * ksplit);
   switch (st) {
-    case Store::F32: compress_variant<Store::F32>(pl.gemm_cvar, grid, pl.stream, a); break;
-    case Store::BF16: compress_variant<Store::BF16>(pl.gemm_cvar, grid, pl.stream, a); break;
-    default: compress_variant<Store::F16>(pl.gemm_cvar, grid, pl.stream, a); break;
+    case Store::F32: compress_variant<Store::F32>(cvar, pl.stream, a); break;
+    case Store::BF16: compress_variant<Store::BF16>(cvar, pl.stream, a); break;
+    default: compress_variant<Store::F16>(cvar, pl.stream, a); break;
   }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
@@ -427,25 +998,36 @@ int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* ou
 
 }  // namespace
 
-int gemm_compress_variants() { return kNumCompress; }
-int gemm_expand_variants() { return kNumExpand; }
-int compress_tile_rows(const Plan& pl) {
-  const Shape S = kCompressShapes[pl.gemm_cvar];
-  return S.wm * S.mt * 16;
-}
-int compress_tile_cols(const Plan& pl) {
-  const Shape S = kCompressShapes[pl.gemm_cvar];
-  return S.wn * S.nt * 16;
+int gemm_compress_variants() { return kNumShapes; }
+int gemm_expand_variants() { return kNumShapes; }
+
+// Defaults: shape 0 of each class (shape 7 for the FP32 compressing contraction
+// when 2K < 64 rows), and a split giving about 1536 (FP32) or 768 (16-bit)
+// work-groups.
+void default_gemm_config(Plan& pl) {
+  for (int c = 0; c < 2; ++c) {
+    const Store st = c == 0 ? Store::F32 : Store::BF16;
+    Plan::GemmCfg& g = pl.cfg(st);
+    g.cvar = (c == 0 && 2 * pl.K < 64) ? 7 : 0;
+    g.evar = 0;
+    const Shape S = c == 0 ? ((2 * pl.P) % 32 == 0 ? kCompressLds[g.cvar] : kCompress32[g.cvar]) : kCompress16[g.cvar];
+    const int T = c == 0 ? 32 : 16;
+    const long t = (long)tiles(pl.ny, S.wn * S.nt * T) * tiles(2 * pl.K, S.wm * S.mt * T) * pl.B * pl.np;
+    const long target = c == 0 ? 1536 : 768;  // work-groups: measured best on the 224 x 224, 32-coil slice
+    int ks = (int)std::max<long>(1, (target + t - 1) / t);
+    ks = std::min(std::min(ks, std::max(1, 2 * pl.ns / 128)), kMaxKsplit);
+    g.ksplit = ks;
+  }
 }
 
 int launch_group_compress(const Plan& pl, Store st) {
   StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS);
-  return gemm_compress(pl, st, pl.W, pl.ny, pl.Zp, pl.gemm_ksplit);
+  return gemm_compress(pl, st, pl.W, pl.ny, pl.Zp, pl.cfg(st).ksplit, pl.cfg(st).cvar);
 }
 
 int launch_compress_data(const Plan& pl, const float2* ksp, float2* out) {
   StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS);
-  return gemm_compress(pl, Store::F32, ksp, pl.ms, out, 1);
+  return gemm_compress(pl, Store::F32, ksp, pl.ms, out, 1, pl.cfg(Store::F32).cvar);
 }
 
 int launch_group_expand(const Plan& pl, Store st) {
@@ -471,13 +1053,10 @@ int launch_group_expand(const Plan& pl, Store st) {
   a.P = pl.P;
   a.np = pl.np;
   a.B = pl.B;
-  const Shape S = kExpandShapes[pl.gemm_evar];
-  const int TM = S.wm * S.mt * 16, TN = S.wn * S.nt * 16;
-  const dim3 grid(((a.N + TN - 1) / TN) * ((a.M + TM - 1) / TM) * pl.B * pl.np);
   switch (st) {
-    case Store::F32: expand_variant<Store::F32>(pl.gemm_evar, grid, pl.stream, a); break;
-    case Store::BF16: expand_variant<Store::BF16>(pl.gemm_evar, grid, pl.stream, a); break;
-    default: expand_variant<Store::F16>(pl.gemm_evar, grid, pl.stream, a); break;
+    case Store::F32: expand_variant<Store::F32>(pl.cfg(st).evar, pl.stream, a); break;
+    case Store::BF16: expand_variant<Store::BF16>(pl.cfg(st).evar, pl.stream, a); break;
+    default: expand_variant<Store::F16>(pl.cfg(st).evar, pl.stream, a); break;
   }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;

@@ -439,13 +439,13 @@ struct ReadoutAdj {
 
 template <int NY>
 struct PeFwd {
-  static int run(const Plan& pl, float2* out) {
+  static int run(const Plan& pl, float2* out, int ksplit) {
     StageScope sc(pl, GPJC_STAGE_PE_FWD);
     const int nlines = pl.B * pl.np * pl.K;
     const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
     const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
     hipLaunchKernelGGL(k_pe_fwd<NY>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream, pl.Zp,
-                       pl.gemm_ksplit, zs, out, pl.lines, pl.ms, nlines, pl.f3_lpb, pl.tw_y);
+                       ksplit, zs, out, pl.lines, pl.ms, nlines, pl.f3_lpb, pl.tw_y);
     GPJC_HIP(hipGetLastError());
     return GPJC_OK;
   }
@@ -482,7 +482,7 @@ struct PeNormal {
       const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
       const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
       hipLaunchKernelGGL((k_pe_normal<NY, ST>), dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds,
-                         pl.stream, pl.Zp, pl.gemm_ksplit, zs, zt_for(pl, ST), pl.maskf, nlines, pl.f3_lpb, pl.K,
+                         pl.stream, pl.Zp, pl.cfg(ST).ksplit, zs, zt_for(pl, ST), pl.maskf, nlines, pl.f3_lpb, pl.K,
                          pl.Kp, pl.tw_y);
       GPJC_HIP(hipGetLastError());
       return GPJC_OK;
@@ -532,7 +532,9 @@ int launch_combine(const Plan& pl, float2* out) {
   return GPJC_OK;
 }
 
-int launch_pe_fwd(const Plan& pl, float2* out) { return dispatch_n<PeFwd>(pl.ny, pl, out); }
+int launch_pe_fwd(const Plan& pl, float2* out, Store st) {
+  return dispatch_n<PeFwd>(pl.ny, pl, out, pl.cfg(st).ksplit);
+}
 int launch_pe_adj(const Plan& pl, const float2* in, Store st) {
   switch (st) {
     case Store::F32: return dispatch_n<PeAdj<Store::F32>::L>(pl.ny, pl, in);
@@ -568,7 +570,7 @@ int op_forward(const Plan& pl, Store st, const float2* img, float2* out) {
   }
   GPJC_TRY(launch_readout_fwd(pl, img, st));
   GPJC_TRY(launch_group_compress(pl, st));
-  return launch_pe_fwd(pl, out);
+  return launch_pe_fwd(pl, out, st);
 }
 
 int op_adjoint_part(const Plan& pl, Store st, const float2* in) {

@@ -55,9 +55,14 @@ struct Plan {
   int f1h_cpc = 1;          // coils per chunk
   int f3_lpb = 1;           // phase-encode lines per workgroup
   int f3_tb = 1;            // readout columns per uncompressed phase-encode workgroup
-  int gemm_ksplit = 1;      // contraction split of the compressing group GEMM
-  int gemm_cvar = 0;        // tile shape of the compressing contraction
-  int gemm_evar = 0;        // tile shape of the expanding contraction
+  // group-contraction configuration per precision class ([0] FP32, [1] BF16 / FP16):
+  // tile shape of the compressing and expanding contractions, split of the compressing one
+  struct GemmCfg {
+    int cvar = 0, evar = 0, ksplit = 1;
+  };
+  GemmCfg gemm[2];
+  const GemmCfg& cfg(Store st) const { return gemm[st == Store::F32 ? 0 : 1]; }
+  GemmCfg& cfg(Store st) { return gemm[st == Store::F32 ? 0 : 1]; }
   long config_gen = 0;      // bumped whenever the launch configuration changes
 
   // device: geometry tables
@@ -129,19 +134,18 @@ int launch_readout_adj(const Plan& pl, Store st);
 int launch_combine(const Plan& pl, float2* out);
 int launch_group_compress(const Plan& pl, Store st);
 int launch_group_expand(const Plan& pl, Store st);
-int launch_pe_fwd(const Plan& pl, float2* out);
+int launch_pe_fwd(const Plan& pl, float2* out, Store st);
 int launch_pe_adj(const Plan& pl, const float2* in, Store st);
 int launch_pe_normal(const Plan& pl, Store st);
 int launch_pe_cols_fwd(const Plan& pl, float2* out);
 int launch_pe_cols_adj(const Plan& pl, const float2* in);
 int launch_pe_cols_normal(const Plan& pl);
 int launch_expand_bank(Plan& pl);
-// Work-group tile of the compressing contraction (rows of 2K x columns).
-int compress_tile_rows(const Plan& pl);
+// Tile shapes built per precision class, and the default configuration of a plan.
 int gemm_compress_variants();
 int gemm_expand_variants();
 constexpr int kMaxKsplit = 8;
-int compress_tile_cols(const Plan& pl);
+void default_gemm_config(Plan& pl);
 int launch_compress_data(const Plan& pl, const float2* ksp, float2* out);
 
 // Whole operators: images in, images (as partial sums in pl.part) or data out.

@@ -105,17 +105,18 @@ int measure(Plan& pl, Store st, Choice* out, float* us_c, float* us_e) {
   GPJC_HIP(hipEventCreate(&ev.b));
   const bool timing = pl.timing.on;
   pl.timing.on = false;
-  const Choice keep{pl.gemm_cvar, pl.gemm_evar, pl.gemm_ksplit};
+  Plan::GemmCfg& cfg = pl.cfg(st);
+  const Plan::GemmCfg keep = cfg;
   // Operands with defined contents: W from the readout stage of a zero image.
   GPJC_HIP(hipMemsetAsync(pl.vx, 0, sizeof(float2) * pl.img_elems(), pl.stream));
   int status = launch_readout_fwd(pl, pl.vx, st);
-  Choice best = keep;
+  Choice best{keep.cvar, keep.evar, keep.ksplit};
   float bc = 1e30f, be = 1e30f;
   const int kd = 2 * pl.ns;
   for (int v = 0; status == GPJC_OK && v < gemm_compress_variants(); ++v)
-    for (int ks = 1; status == GPJC_OK && ks <= kMaxKsplit && (ks == 1 || kd / ks >= 128); ks *= 2) {
-      pl.gemm_cvar = v;
-      pl.gemm_ksplit = ks;
+    for (int ks = 1; status == GPJC_OK && ks <= kMaxKsplit && (ks == 1 || kd / ks >= 64); ks *= 2) {
+      cfg.cvar = v;
+      cfg.ksplit = ks;
       float us = 0.f;
       status = time_us(pl, ev.a, ev.b, [&] { return launch_group_compress(pl, st); }, &us);
       if (status == GPJC_OK && us < bc) {
@@ -125,7 +126,7 @@ int measure(Plan& pl, Store st, Choice* out, float* us_c, float* us_e) {
       }
     }
   for (int v = 0; status == GPJC_OK && v < gemm_expand_variants(); ++v) {
-    pl.gemm_evar = v;
+    cfg.evar = v;
     float us = 0.f;
     status = time_us(pl, ev.a, ev.b, [&] { return launch_group_expand(pl, st); }, &us);
     if (status == GPJC_OK && us < be) {
@@ -134,9 +135,7 @@ int measure(Plan& pl, Store st, Choice* out, float* us_c, float* us_e) {
     }
   }
   pl.timing.on = timing;
-  pl.gemm_cvar = keep.cvar;
-  pl.gemm_evar = keep.evar;
-  pl.gemm_ksplit = keep.ksplit;
+  cfg = keep;
   if (status != GPJC_OK) return status;
   *out = best;
   *us_c = bc;
@@ -167,9 +166,7 @@ int autotune(Plan& pl, Store st, const char* cache_path, int* h_choice) {
     g_cache[key] = c;
     append_file(cache_path, key, c, us_c, us_e);
   }
-  pl.gemm_cvar = c.cvar;
-  pl.gemm_evar = c.evar;
-  pl.gemm_ksplit = c.ksplit;
+  pl.cfg(st) = Plan::GemmCfg{c.cvar, c.evar, c.ksplit};
   ++pl.config_gen;
   if (h_choice) {
     h_choice[0] = c.cvar;

@@ -71,8 +71,8 @@ _SIGS = {
     "gpjc_wavelet_absmax": (_I, [_VP, _VP, _I, _VP]),
     "gpjc_stage_timing": (_I, [_VP, _I]),
     "gpjc_stage_times": (_I, [_VP, _VP, _VP]),
-    "gpjc_set_gemm_config": (_I, [_VP, _I, _I, _I]),
-    "gpjc_get_gemm_config": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "gpjc_set_gemm_config": (_I, [_VP, _I, _I, _I, _I]),
+    "gpjc_get_gemm_config": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
     "gpjc_gd_step": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
     "gpjc_gd_step_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "gpjc_autotune": (_I, [_VP, _I, ctypes.c_char_p, _VP]),
@@ -308,12 +308,13 @@ class Plan:
         _check(self.lib.gpjc_stage_times(self.handle, ms, cnt))
         return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
-    def set_gemm_config(self, compress_variant, expand_variant, ksplit):
-        _check(self.lib.gpjc_set_gemm_config(self.handle, int(compress_variant), int(expand_variant), int(ksplit)))
+    def set_gemm_config(self, compress_variant, expand_variant, ksplit, prec="fp32"):
+        _check(self.lib.gpjc_set_gemm_config(self.handle, _prec(prec), int(compress_variant), int(expand_variant),
+                                             int(ksplit)))
 
-    def gemm_config(self):
+    def gemm_config(self, prec="fp32"):
         v = [ctypes.c_int() for _ in range(5)]
-        _check(self.lib.gpjc_get_gemm_config(self.handle, *[ctypes.byref(x) for x in v]))
+        _check(self.lib.gpjc_get_gemm_config(self.handle, _prec(prec), *[ctypes.byref(x) for x in v]))
         return {"compress": v[0].value, "expand": v[1].value, "ksplit": v[2].value,
                 "n_compress": v[3].value, "n_expand": v[4].value}
 

@@ -149,7 +149,7 @@ def test_autotune_cache(gpu_lib, tmp_path):
         p.set_compression(torch.as_tensor(a).cuda())
     c1 = p1.autotune("fp32", path)
     assert not c1["cached"]
-    cfg = p1.gemm_config()
+    cfg = p1.gemm_config("fp32")
     assert (cfg["compress"], cfg["expand"], cfg["ksplit"]) == (c1["compress"], c1["expand"], c1["ksplit"])
     c2 = p2.autotune("fp32", path)
     assert c2["cached"] and (c2["compress"], c2["expand"], c2["ksplit"]) == (c1["compress"], c1["expand"], c1["ksplit"])
