@@ -120,6 +120,9 @@ static void choose_launch(Plan& pl) {
   int rows = std::max(1, (lds_f2 - pl.nx) / (2 * pl.os * lsx));
   rows = std::min(rows, std::max(1, pl.ny * pl.nc * pl.B / 4096));
   pl.f1_rows = std::max(1, std::min(rows, pl.ny));
+  // the two-pass register-FFT form where its work-group fits
+  pl.f2_threads = 256;
+  pl.f2_cb = two_pass_coils(pl.nx, pl.os, pl.nc, &pl.f2_threads);
 
   // readout adjoint: coils transformed together (up to 2, LDS permitting),
   // and enough coil chunks for about 2048 work-groups (each chunk leaves one

@@ -20,6 +20,7 @@
 
 #include "devutil.h"
 #include "fft.h"
+#include "fft2.h"
 #include "plan.h"
 
 namespace gpjc {
@@ -189,6 +190,94 @@ __global__ __launch_bounds__(256) void k_readout_adj(const void* __restrict__ W,
   for (int e = 0; e < PER; ++e) {
     const int x = tid + e * 256;
     if (x < NX) part[(((size_t)chunk * B + b) * ny + y) * NX + x] = acc[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass form of F1 (N = N1 N2, see fft2.h).  One work-group takes one
+// image row and cb coils, i.e. cb * os sub-transforms of length NX; the first
+// pass is an N1-point DFT per (coil, sub-transform, i2) in registers, the
+// second an N2-point DFT per (coil, sub-transform, k1).  The launch keeps
+// cb * os * N1 <= blockDim.x so every second-pass item has its own thread,
+// which lets results overwrite the exchange buffer after one barrier.  The
+// PSF row is read once for all cb coils.
+// ---------------------------------------------------------------------------
+__device__ inline int udiv(int a, int b) { return (int)(((float)a + 0.5f) / (float)b); }  // a < 2^16, b small
+
+template <int NX, Store ST>
+__global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__ img, const float2* __restrict__ coils,
+                                                      const float2* __restrict__ psfp, const float2* __restrict__ twin,
+                                                      const float2* __restrict__ tw, void* __restrict__ W, int ny,
+                                                      int nc, int os, int cb) {
+  using S = Split<NX>;
+  constexpr int N1 = S::N1, N2 = S::N2, AS = N1 + 1;
+  // pre-twiddle rows padded to N2 (mod 32) float2 slots: the first pass reads
+  // element i2 + N2 i1 of row s with lanes ordered (s, i2), now on distinct banks
+  constexpr int NXW = NX + ((N2 - NX % 32) % 32 + 32) % 32;
+  extern __shared__ float2 sm[];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nt = os * NX;
+  const int y = blockIdx.x, n0 = blockIdx.y * cb, b = blockIdx.z;
+  const int ncb = min(cb, nc - n0);
+  float2* twl = sm;            // [NX]       exp(-2 pi i m / NX)
+  float2* twn = twl + NX;      // [os][NXW]  pre-twiddles
+  float2* u = twn + os * NXW;  // [cb][NX]   coil * image
+  float2* A = u + cb * NX;     // [cb][os][N2][AS], then the output rows [cb][nt]
+  for (int i = tid; i < NX; i += nthr) twl[i] = tw[i];
+  for (int i = tid; i < os * NX; i += nthr) {
+    const int s = i / NX;
+    twn[i + s * (NXW - NX)] = twin[i];
+  }
+  const float2* ip = img + ((size_t)b * ny + y) * NX;
+  for (int i = tid; i < ncb * NX; i += nthr) {
+    const int c = i / NX, x = i - c * NX;
+    u[i] = cmul(coils[((size_t)(n0 + c) * ny + y) * NX + x], ip[x]);
+  }
+  __syncthreads();
+  const int items1 = ncb * os * N2;
+  for (int it = tid; it < items1; it += nthr) {
+    const int r = it / N2, i2 = it - r * N2;  // r = c * os + s
+    const int c = udiv(r, os), s = r - c * os;
+    float2 v[N1];
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) v[i1] = cmul(u[c * NX + i2 + N2 * i1], twn[s * NXW + i2 + N2 * i1]);
+    rdft<N1>(v);
+    float2* dst = A + (r * N2 + i2) * AS;
+    dst[0] = v[0];
+    int m = i2;
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      dst[k1] = cmul(v[k1], twl[m]);
+      m += i2;
+      m = m >= NX ? m - NX : m;
+    }
+  }
+  __syncthreads();
+  const int items2 = ncb * os * N1;
+  const bool act = tid < items2;
+  float2 w[N2];
+  int r2 = 0, k1 = 0;
+  if (act) {
+    r2 = tid / N1;
+    k1 = tid - r2 * N1;
+    const float2* src = A + r2 * N2 * AS + k1;
+#pragma unroll
+    for (int i2 = 0; i2 < N2; ++i2) w[i2] = src[i2 * AS];
+    rdft<N2>(w);
+  }
+  __syncthreads();
+  if (act) {
+    const int c = udiv(r2, os), s = r2 - c * os;
+    float2* o = A + c * nt + s;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) o[(k1 + N1 * k2) * os] = w[k2];
+  }
+  __syncthreads();
+  const float2* ps = psfp + (size_t)y * nt;
+  for (int t = tid; t < nt; t += nthr) {
+    const float2 p = ps[t];
+    for (int c = 0; c < ncb; ++c)
+      store_c<ST>(W, (((size_t)b * nc + n0 + c) * ny + y) * nt + t, cmul(p, A[c * nt + t]));
   }
 }
 
@@ -381,6 +470,31 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
 }
 
 // ---------------------------------------------------------------------------
+// Host-side sizing of the two-pass readout forms (complex elements of LDS).
+// ---------------------------------------------------------------------------
+size_t two_pass_lds_fwd(int nx, int os, int cb) {
+  const int n1 = split_n1(nx), n2 = nx / n1;
+  const int nxw = nx + ((n2 - nx % 32) % 32 + 32) % 32;
+  const size_t a = (size_t)cb * os * n2 * (n1 + 1), o = (size_t)cb * os * nx;
+  return (size_t)nx + (size_t)os * nxw + (size_t)cb * nx + (a > o ? a : o);
+}
+// Coils per work-group of the two-pass forward form (0 = not applicable):
+// every second-pass item needs its own thread (at most 256) and the LDS must
+// fit in 64 KiB.
+int two_pass_coils(int nx, int os, int nc, int* threads) {
+  const int n1 = split_n1(nx), n2 = nx / n1;
+  if (n1 <= 1 || n2 <= 1 || n2 > 32) return 0;
+  for (int cb = std::min(nc, 4); cb >= 1; --cb) {
+    const int items = cb * os * std::max(n1, n2);
+    if (items > 256) continue;
+    if (two_pass_lds_fwd(nx, os, cb) * 8 > 65536) continue;
+    *threads = std::max(64, (items + 63) / 64 * 64);
+    return cb;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Launch dispatch over the instantiated FFT lengths.
 // ---------------------------------------------------------------------------
 #define GPJC_FFT_SIZES(X) \
@@ -409,6 +523,14 @@ struct ReadoutFwd {
   struct L {
     static int run(const Plan& pl, const float2* img) {
       StageScope sc(pl, GPJC_STAGE_READOUT_FWD);
+      if (pl.f2_cb > 0) {
+        const size_t lds = two_pass_lds_fwd(NX, pl.os, pl.f2_cb) * sizeof(float2);
+        dim3 grid(pl.ny, (pl.nc + pl.f2_cb - 1) / pl.f2_cb, pl.B);
+        hipLaunchKernelGGL((k_readout_fwd2<NX, ST>), grid, dim3(pl.f2_threads), lds, pl.stream, img, pl.coils, pl.psfp,
+                           pl.twin, pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, pl.f2_cb);
+        GPJC_HIP(hipGetLastError());
+        return GPJC_OK;
+      }
       const int rows = pl.f1_rows;
       const size_t lds = (size_t)(NX + 2 * rows * pl.os * fline(NX)) * sizeof(float2);
       dim3 grid((pl.ny + rows - 1) / rows, pl.nc, pl.B);
