@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "fft.h"
+#include "fft2.h"
 #include "plan.h"
 
 
@@ -136,6 +137,13 @@ static void choose_launch(Plan& pl) {
   pl.f1h_cb = cb;
   pl.f1h_cpc = cpc;
   pl.f1h_nchunk = (pl.nc + cpc - 1) / cpc;
+  // two-pass adjoint: one coil group (f2_cb coils) per work-group and partial image
+  pl.f2_adj = pl.f2_cb > 0 && (long)pl.f2_cb * pl.os * std::max(split_n1(pl.nx), pl.nx / split_n1(pl.nx)) <= pl.f2_threads &&
+              two_pass_lds_adj(pl.nx, pl.os, pl.f2_cb) * 8 <= 65536;
+  if (pl.f2_adj) {
+    pl.f1h_cpc = pl.f2_cb;
+    pl.f1h_nchunk = (pl.nc + pl.f2_cb - 1) / pl.f2_cb;
+  }
 
   const int lpb_max = std::max(1, std::min(32, (lds_f2 - pl.ny) / (2 * lsy)));
   const int nlines = pl.compressed ? pl.B * pl.np * pl.K : 1;

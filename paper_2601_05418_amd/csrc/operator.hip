@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_readout_adj(const void* __restrict__ W,
 // second an N2-point DFT per (coil, sub-transform, k1).  The launch keeps
 // cb * os * N1 <= blockDim.x so every second-pass item has its own thread,
 // which lets results overwrite the exchange buffer after one barrier.  The
-// PSF row is read once for all cb coils.
+// PSF row is read once for all cb coils; the pre-twiddle table (os x NX) is
+// read through the L1 cache, shared by all work-groups of a CU.
 // ---------------------------------------------------------------------------
 __device__ inline int udiv(int a, int b) { return (int)(((float)a + 0.5f) / (float)b); }  // a < 2^16, b small
 
@@ -211,23 +212,15 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
                                                       int nc, int os, int cb) {
   using S = Split<NX>;
   constexpr int N1 = S::N1, N2 = S::N2, AS = N1 + 1;
-  // pre-twiddle rows padded to N2 (mod 32) float2 slots: the first pass reads
-  // element i2 + N2 i1 of row s with lanes ordered (s, i2), now on distinct banks
-  constexpr int NXW = NX + ((N2 - NX % 32) % 32 + 32) % 32;
   extern __shared__ float2 sm[];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nt = os * NX;
   const int y = blockIdx.x, n0 = blockIdx.y * cb, b = blockIdx.z;
   const int ncb = min(cb, nc - n0);
-  float2* twl = sm;            // [NX]       exp(-2 pi i m / NX)
-  float2* twn = twl + NX;      // [os][NXW]  pre-twiddles
-  float2* u = twn + os * NXW;  // [cb][NX]   coil * image
-  float2* A = u + cb * NX;     // [cb][os][N2][AS], then the output rows [cb][nt]
+  float2* twl = sm;         // [NX]       exp(-2 pi i m / NX)
+  float2* u = twl + NX;     // [cb][NX]   coil * image
+  float2* A = u + cb * NX;  // [cb][os][N2][AS], then the output rows [cb][nt]
   for (int i = tid; i < NX; i += nthr) twl[i] = tw[i];
-  for (int i = tid; i < os * NX; i += nthr) {
-    const int s = i / NX;
-    twn[i + s * (NXW - NX)] = twin[i];
-  }
   const float2* ip = img + ((size_t)b * ny + y) * NX;
   for (int i = tid; i < ncb * NX; i += nthr) {
     const int c = i / NX, x = i - c * NX;
@@ -240,7 +233,7 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
     const int c = udiv(r, os), s = r - c * os;
     float2 v[N1];
 #pragma unroll
-    for (int i1 = 0; i1 < N1; ++i1) v[i1] = cmul(u[c * NX + i2 + N2 * i1], twn[s * NXW + i2 + N2 * i1]);
+    for (int i1 = 0; i1 < N1; ++i1) v[i1] = cmul(u[c * NX + i2 + N2 * i1], twin[s * NX + i2 + N2 * i1]);
     rdft<N1>(v);
     float2* dst = A + (r * N2 + i2) * AS;
     dst[0] = v[0];
@@ -278,6 +271,99 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
     const float2 p = ps[t];
     for (int c = 0; c < ncb; ++c)
       store_c<ST>(W, (((size_t)b * nc + n0 + c) * ny + y) * nt + t, cmul(p, A[c * nt + t]));
+  }
+}
+
+// Two-pass form of F1^H: one work-group per image row and cb coils, leaving
+// one partial image per coil group.  The inputs conj(psf) w are scattered to
+// sub-transform rows (padded to os (mod 32) slots so consecutive samples land
+// on consecutive banks); the inverse DFT of length NX per sub-transform is
+// taken as conj(FFT(conj(.))) with the two passes of the forward form; the
+// sum over sub-transforms of the pre-twiddled results and the coil
+// combination follow.  Pre-twiddles are read from the (L1-resident) table.
+template <int NX, Store ST>
+__global__ __launch_bounds__(256) void k_readout_adj2(const void* __restrict__ W, const float2* __restrict__ coils,
+                                                      const float2* __restrict__ psfp, const float2* __restrict__ twin,
+                                                      const float2* __restrict__ tw, float2* __restrict__ part, int ny,
+                                                      int nc, int os, int cb, int B) {
+  using S = Split<NX>;
+  constexpr int N1 = S::N1, N2 = S::N2, AS = N1 + 1;
+  extern __shared__ float2 sm[];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nt = os * NX;
+  const int nxp = NX + ((os - NX % 32) % 32 + 32) % 32;
+  const int y = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
+  const int n0 = chunk * cb, ncb = min(cb, nc - n0);
+  float2* twl = sm;       // [NX]
+  float2* X = twl + NX;   // [cb][os][nxp] inputs, then [cb][os][N2][AS], then [cb][os][NX] results
+  for (int i = tid; i < NX; i += nthr) twl[i] = tw[i];
+  const float2* ps = psfp + (size_t)y * nt;
+  for (int t = tid; t < nt; t += nthr) {
+    const int q = udiv(t, os), s = t - q * os;
+    const float2 p = ps[t];
+    for (int c = 0; c < ncb; ++c)
+      X[(c * os + s) * nxp + q] = cmulc(p, load_c<ST>(W, (((size_t)b * nc + n0 + c) * ny + y) * nt + t));
+  }
+  __syncthreads();
+  const int items1 = ncb * os * N2;  // <= blockDim.x
+  float2 v[N1];
+  int r1 = 0, i2 = 0;
+  const bool act1 = tid < items1;
+  if (act1) {
+    r1 = tid / N2;
+    i2 = tid - r1 * N2;
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) v[i1] = X[r1 * nxp + i2 + N2 * i1];
+  }
+  __syncthreads();
+  if (act1) {
+    rdft<N1>(v);
+    float2* dst = X + (r1 * N2 + i2) * AS;
+    dst[0] = v[0];
+    int m = i2;
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      dst[k1] = cmul(v[k1], twl[m]);
+      m += i2;
+      m = m >= NX ? m - NX : m;
+    }
+  }
+  __syncthreads();
+  const int items2 = ncb * os * N1;  // <= blockDim.x
+  float2 w[N2];
+  int r2 = 0, k1 = 0;
+  const bool act2 = tid < items2;
+  if (act2) {
+    r2 = tid / N1;
+    k1 = tid - r2 * N1;
+    const float2* src = X + r2 * N2 * AS + k1;
+#pragma unroll
+    for (int j = 0; j < N2; ++j) w[j] = src[j * AS];
+    rdft<N2>(w);
+  }
+  __syncthreads();
+  if (act2) {
+    // the inverse sub-transform is conj(w); keep twin * w, whose sum over s is
+    // the conjugate of the pre-twiddled sum
+    const int s = r2 - udiv(r2, os) * os;
+    float2* o = X + r2 * NX;
+    const float2* tws = twin + s * NX;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int x = k1 + N1 * k2;
+      o[x] = cmul(w[k2], tws[x]);
+    }
+  }
+  __syncthreads();
+  float2* pp = part + (((size_t)chunk * B + b) * ny + y) * NX;
+  for (int x = tid; x < NX; x += nthr) {
+    float2 acc = make_float2(0.f, 0.f);
+    for (int c = 0; c < ncb; ++c) {
+      float2 v2 = make_float2(0.f, 0.f);
+      for (int s = 0; s < os; ++s) v2 = cadd(v2, X[(c * os + s) * NX + x]);
+      acc = cadd(acc, cconj(cmul(v2, coils[((size_t)(n0 + c) * ny + y) * NX + x])));
+    }
+    pp[x] = acc;
   }
 }
 
@@ -474,9 +560,13 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
 // ---------------------------------------------------------------------------
 size_t two_pass_lds_fwd(int nx, int os, int cb) {
   const int n1 = split_n1(nx), n2 = nx / n1;
-  const int nxw = nx + ((n2 - nx % 32) % 32 + 32) % 32;
   const size_t a = (size_t)cb * os * n2 * (n1 + 1), o = (size_t)cb * os * nx;
-  return (size_t)nx + (size_t)os * nxw + (size_t)cb * nx + (a > o ? a : o);
+  return (size_t)nx + (size_t)cb * nx + (a > o ? a : o);
+}
+size_t two_pass_lds_adj(int nx, int os, int cb) {
+  const int n1 = split_n1(nx), n2 = nx / n1;
+  const size_t in = (size_t)nx + ((os - nx % 32) % 32 + 32) % 32, ex = (size_t)n2 * (n1 + 1);
+  return (size_t)nx + (size_t)cb * os * (in > ex ? in : ex);
 }
 // Coils per work-group of the two-pass forward form (0 = not applicable):
 // every second-pass item needs its own thread (at most 256) and the LDS must
@@ -488,7 +578,7 @@ int two_pass_coils(int nx, int os, int nc, int* threads) {
     const int items = cb * os * std::max(n1, n2);
     if (items > 256) continue;
     if (two_pass_lds_fwd(nx, os, cb) * 8 > 65536) continue;
-    *threads = std::max(64, (items + 63) / 64 * 64);
+    *threads = 256;  // the load, scatter and output phases take every thread (measured faster than items)
     return cb;
   }
   return 0;
@@ -548,6 +638,14 @@ struct ReadoutAdj {
   struct L {
     static int run(const Plan& pl) {
       StageScope sc(pl, GPJC_STAGE_READOUT_ADJ);
+      if (pl.f2_adj) {
+        const size_t lds = two_pass_lds_adj(NX, pl.os, pl.f2_cb) * sizeof(float2);
+        dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
+        hipLaunchKernelGGL((k_readout_adj2<NX, ST>), grid, dim3(pl.f2_threads), lds, pl.stream, (const void*)pl.W,
+                           pl.coils, pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, pl.f2_cb, pl.B);
+        GPJC_HIP(hipGetLastError());
+        return GPJC_OK;
+      }
       const size_t lds = (size_t)(NX + 2 * pl.f1h_cb * pl.os * fline(NX)) * sizeof(float2);
       dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
       hipLaunchKernelGGL((k_readout_adj<NX, ST>), grid, dim3(256), lds, pl.stream, (const void*)pl.W, pl.coils,

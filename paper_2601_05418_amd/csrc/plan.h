@@ -51,7 +51,8 @@ struct Plan {
   // launch configuration
   int f1_rows = 1;          // image rows per readout-forward workgroup
   int f2_cb = 0;            // coils per work-group of the two-pass readout forward (0 = Stockham form)
-  int f2_threads = 256;     // threads per work-group of the two-pass readout forward
+  int f2_threads = 256;     // threads per work-group of the two-pass readout forms
+  bool f2_adj = false;      // the adjoint uses the two-pass form too (one coil group per work-group)
   int f1h_cb = 1;           // coils transformed together in the readout adjoint
   int f1h_nchunk = 1;       // coil chunks (partial images) in the readout adjoint
   int f1h_cpc = 1;          // coils per chunk
@@ -180,6 +181,7 @@ int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
 
 // Sizing of the two-pass readout forms (operator.hip).
 size_t two_pass_lds_fwd(int nx, int os, int cb);
+size_t two_pass_lds_adj(int nx, int os, int cb);
 int two_pass_coils(int nx, int os, int nc, int* threads);
 
 // Lengths the FFT kernels are instantiated for.
