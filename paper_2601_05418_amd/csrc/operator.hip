@@ -491,6 +491,113 @@ __global__ __launch_bounds__(256) void k_pe_normal(const float2* __restrict__ Zp
   }
 }
 
+// Two-pass form of the normal y-stage for NY = N1 N2, L lines per
+// work-group (256 threads).  All threads first sum the k-split partials of
+// the lines into LDS (coalesced along y).  Per line, the forward transform's
+// first pass (N1-point DFTs of stride-N2 subsequences, twiddled), one
+// exchange, its second pass (N2-point DFTs) -- which leaves each thread the
+// spectrum subsequence ky = k1 + N1 k2 -- then mask / NY and conjugation, and,
+// in the same registers, the first pass of the second transform taken the
+// other way round (N2-point DFTs over k2, twiddled), one more exchange, and
+// N1-point DFTs giving y = m2 + N2 n1.
+template <int NY>
+struct PeNormal2Geo {
+  static constexpr int N1 = Split<NY>::N1, N2 = Split<NY>::N2, AS = N1 + 1;
+  static constexpr int L = 64 / (N1 > N2 ? N1 : N2) > 0 ? 64 / (N1 > N2 ? N1 : N2) : 1;  // lines per work-group
+  static constexpr int NYP = NY + 1;
+};
+
+template <int NY, Store ST>
+__global__ __launch_bounds__(256) void k_pe_normal2(const float2* __restrict__ Zp, int ksplit, size_t zstride,
+                                                    void* __restrict__ Zt, const float* __restrict__ maskf, int nlines,
+                                                    int K, int kp, const float2* __restrict__ tw) {
+  using Gm = PeNormal2Geo<NY>;
+  constexpr int N1 = Gm::N1, N2 = Gm::N2, AS = Gm::AS, L = Gm::L, NYP = Gm::NYP;
+  __shared__ float2 twl[NY];
+  __shared__ float2 Zs[L * NYP];
+  __shared__ float2 E[L * N2 * AS];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
+  const int l0 = blockIdx.x * L;
+  const int nl = min(L, nlines - l0);
+  for (int i = tid; i < nl * NY; i += 256) {
+    const int ln = i / NY, y = i - ln * NY;
+    const size_t g = (size_t)l0 * NY + i;
+    float2 a = Zp[g];
+    for (int ks = 1; ks < ksplit; ++ks) a = cadd(a, Zp[ks * zstride + g]);
+    Zs[ln * NYP + y] = (y & 1) ? make_float2(-a.x, -a.y) : a;
+  }
+  __syncthreads();
+  if (tid < nl * N2) {  // forward, first pass: item (line, i2)
+    const int ln = tid / N2, i2 = tid - ln * N2;
+    float2 v[N1];
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) v[i1] = Zs[ln * NYP + i2 + N2 * i1];
+    rdft<N1>(v);
+    float2* dst = E + (ln * N2 + i2) * AS;
+    dst[0] = v[0];
+    int m = i2;
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      dst[k1] = cmul(v[k1], twl[m]);
+      m += i2;
+      m = m >= NY ? m - NY : m;
+    }
+  }
+  __syncthreads();
+  // forward second pass, mask, and the second transform's first pass: item (line, k1)
+  float2 w[N2];
+  int ln2 = 0, k1 = 0;
+  const bool act2 = tid < nl * N1;
+  if (act2) {
+    ln2 = tid / N1;
+    k1 = tid - ln2 * N1;
+    const float2* src = E + ln2 * N2 * AS + k1;
+#pragma unroll
+    for (int i2 = 0; i2 < N2; ++i2) w[i2] = src[i2 * AS];
+    rdft<N2>(w);  // w[k2] = F[k1 + N1 k2]
+    const float inv = 1.0f / (float)NY;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) w[k2] = cconj(cscale(w[k2], maskf[k1 + N1 * k2] * inv));
+    rdft<N2>(w);  // over k2: w[m2] = sum_k2 g[k1 + N1 k2] w_N2^{k2 m2}
+  }
+  __syncthreads();
+  if (act2) {
+    float2* dst = E + ln2 * N2 * AS + k1;
+    int m = 0;
+#pragma unroll
+    for (int m2 = 0; m2 < N2; ++m2) {
+      dst[m2 * AS] = cmul(w[m2], twl[m]);  // twiddle w_NY^{k1 m2}
+      m += k1;
+      m = m >= NY ? m - NY : m;
+    }
+  }
+  __syncthreads();
+  if (tid < nl * N2) {  // second transform, last pass: item (line, m2)
+    const int ln = tid / N2, m2 = tid - ln * N2;
+    float2 v[N1];
+    const float2* src = E + (ln * N2 + m2) * AS;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = src[n1];
+    rdft<N1>(v);  // v[n1] = G[m2 + N2 n1]
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int y = m2 + N2 * n1;
+      float2 r = cconj(v[n1]);
+      if (y & 1) r = make_float2(-r.x, -r.y);
+      Zs[ln * NYP + y] = r;
+    }
+  }
+  __syncthreads();
+  // transposed store, k fastest within each (b, p)
+  for (int i = tid; i < nl * NY; i += 256) {
+    const int y = i / nl, ln = i - y * nl;
+    const int l = l0 + ln;
+    const int bp = l / K, k = l - bp * K;
+    store_c<ST>(Zt, ((size_t)bp * NY + y) * kp + k, Zs[ln * NYP + y]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // F3 on uncompressed columns W[(b,n)][y][t] (stride nt).  Work-group: one
 // (b, n) and `tb` consecutive t.
@@ -699,6 +806,14 @@ struct PeNormal {
     static int run(const Plan& pl) {
       StageScope sc(pl, GPJC_STAGE_PE_NORMAL);
       const int nlines = pl.B * pl.np * pl.K;
+      if constexpr (Split<NY>::N1 > 1 && Split<NY>::N2 > 1 && Split<NY>::N2 <= 32) {
+        constexpr int lines = PeNormal2Geo<NY>::L;
+        const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
+        hipLaunchKernelGGL((k_pe_normal2<NY, ST>), dim3((nlines + lines - 1) / lines), dim3(256), 0, pl.stream, pl.Zp,
+                           pl.cfg(ST).ksplit, zs, zt_for(pl, ST), pl.maskf, nlines, pl.K, pl.Kp, pl.tw_y);
+        GPJC_HIP(hipGetLastError());
+        return GPJC_OK;
+      }
       const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
       const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
       hipLaunchKernelGGL((k_pe_normal<NY, ST>), dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds,
