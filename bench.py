@@ -38,9 +38,9 @@ PEAKS = {"hbm": 8.0e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
 # sources each kernel is built from when the counters were taken.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "highfield_op_hbm_traffic.md")
 STAGE_SOURCES = {
-    "readout_fwd": ("operator.hip", "fft.h", "devutil.h"),
-    "readout_adj": ("operator.hip", "fft.h", "devutil.h"),
-    "pe_normal": ("operator.hip", "fft.h", "devutil.h"),
+    "readout_fwd": ("operator.hip", "fft.h", "fft2.h", "devutil.h"),
+    "readout_adj": ("operator.hip", "fft.h", "fft2.h", "devutil.h"),
+    "pe_normal": ("operator.hip", "fft.h", "fft2.h", "devutil.h"),
     "group_compress": ("gemm.hip", "devutil.h"),
     "group_expand": ("gemm.hip", "devutil.h"),
 }
