@@ -568,13 +568,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
 // MFMA spans 32 rows per load instruction, so register-direct loads touch 32
 // cache lines each; here the work-group loads k-tiles of 32 elements (one
 // 128-byte line per row) cooperatively, eight lanes per row, into LDS, and
-// the waves read their MFMA fragments from there.  The next k-tile is
+// the waves read their MFMA fragments from there.  The next PF k-tiles are
 // prefetched into registers while the current one is multiplied.  Row
 // stride 36 floats (144 bytes, an odd multiple of 16): the 16-byte fragment
 // reads of one pass fall on distinct bank groups.  Needs 2P a multiple of 32
 // (a k-tile never crosses a coil) and the k-split chunk a multiple of 32.
 // ---------------------------------------------------------------------------
-template <int WM, int WN, int MT, int NT>
+template <int WM, int WN, int MT, int NT, int PF>
 __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   using G = Geo<Store::F32>;
   constexpr int T = 32, KT = 32, LS = KT + 4;
@@ -623,12 +623,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
     vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)n * cstride + jj + 4 * c16) * 4) : kOOB;
   }
   const uint32_t wrap = (uint32_t)((cstride - (size_t)(twoP - KT)) * 4);
-  floatx4 pa[AR], pb[BR];
-  auto fetch = [&]() {
+  floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
+  auto fetch = [&](floatx4(&xa)[AR], floatx4(&xb)[BR]) {
 #pragma unroll
-    for (int r = 0; r < AR; ++r) pa[r] = bload(rA, va[r]);
+    for (int r = 0; r < AR; ++r) xa[r] = bload(rA, va[r]);
 #pragma unroll
-    for (int r = 0; r < BR; ++r) pb[r] = bload(rB, vb[r]);
+    for (int r = 0; r < BR; ++r) xb[r] = bload(rB, vb[r]);
     jj += KT;
     uint32_t inc = KT * 4;
     if (jj == twoP) {
@@ -647,19 +647,25 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
     for (int c = 0; c < NT; ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[m][c][r] = 0.f;
-  if (nst > 0) fetch();
-  for (int st = 0; st < nst; ++st) {
-    __syncthreads();  // the previous k-tile has been read
 #pragma unroll
-    for (int r = 0; r < AR; ++r)
-      *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[r];
+  for (int f = 0; f < PF; ++f)
+    if (f < nst) fetch(pa[f], pb[f]);
+  for (int st0 = 0; st0 < nst; st0 += PF) {
 #pragma unroll
-    for (int r = 0; r < BR; ++r)
-      *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[r];
-    __syncthreads();
-    if (st + 1 < nst) fetch();
+    for (int f = 0; f < PF; ++f) {
+      const int st = st0 + f;
+      if (st >= nst) break;
+      __syncthreads();  // the previous k-tile has been read
 #pragma unroll
-    for (int j = 0; j < KT / 8; ++j) {
+      for (int r = 0; r < AR; ++r)
+        *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[f][r];
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+        *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[f][r];
+      __syncthreads();
+      if (st + PF < nst) fetch(pa[f], pb[f]);
+#pragma unroll
+      for (int j = 0; j < KT / 8; ++j) {
       floatx4 fa[MT], fb[NT];
 #pragma unroll
       for (int m = 0; m < MT; ++m)
@@ -668,11 +674,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
       for (int c = 0; c < NT; ++c)
         fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 8 * j + 4 * lh);
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+          for (int m = 0; m < MT; ++m)
 #pragma unroll
-          for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+      }
     }
   }
   float2* out = a.out + ks * a.split_stride + ((size_t)b * a.np + p) * a.K * a.N;
@@ -694,7 +701,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 // operands (Z^T rows and rows of the real-form bank) are contiguous along the
 // contraction, which has 2 Kp (a multiple of 32) elements.  The output tile
 // is staged through the same LDS to write whole W row segments.
-template <int WM, int WN, int MT, int NT>
+template <int WM, int WN, int MT, int NT, int PF>
 __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
   using G = Geo<Store::F32>;
   constexpr int T = 32, KT = 32, LS = KT + 4;
@@ -736,12 +743,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
     const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
     vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.KD + 4 * c16) * 4) : kOOB;
   }
-  floatx4 pa[AR], pb[BR];
-  auto fetch = [&]() {
+  floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
+  auto fetch = [&](floatx4(&xa)[AR], floatx4(&xb)[BR]) {
 #pragma unroll
-    for (int r = 0; r < AR; ++r) pa[r] = bload(rA, va[r]);
+    for (int r = 0; r < AR; ++r) xa[r] = bload(rA, va[r]);
 #pragma unroll
-    for (int r = 0; r < BR; ++r) pb[r] = bload(rB, vb[r]);
+    for (int r = 0; r < BR; ++r) xb[r] = bload(rB, vb[r]);
 #pragma unroll
     for (int r = 0; r < AR; ++r) va[r] += KT * 4;
 #pragma unroll
@@ -754,19 +761,25 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
     for (int c = 0; c < NT; ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[m][c][r] = 0.f;
-  fetch();
-  for (int st = 0; st < nst; ++st) {
-    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < AR; ++r)
-      *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[r];
+  for (int f = 0; f < PF; ++f)
+    if (f < nst) fetch(pa[f], pb[f]);
+  for (int st0 = 0; st0 < nst; st0 += PF) {
 #pragma unroll
-    for (int r = 0; r < BR; ++r)
-      *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[r];
-    __syncthreads();
-    if (st + 1 < nst) fetch();
+    for (int f = 0; f < PF; ++f) {
+      const int st = st0 + f;
+      if (st >= nst) break;
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < KT / 8; ++j) {
+      for (int r = 0; r < AR; ++r)
+        *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[f][r];
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+        *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[f][r];
+      __syncthreads();
+      if (st + PF < nst) fetch(pa[f], pb[f]);
+#pragma unroll
+      for (int j = 0; j < KT / 8; ++j) {
       floatx4 fa[MT], fb[NT];
 #pragma unroll
       for (int m = 0; m < MT; ++m)
@@ -775,11 +788,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
       for (int c = 0; c < NT; ++c)
         fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 8 * j + 4 * lh);
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+          for (int m = 0; m < MT; ++m)
 #pragma unroll
-          for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+      }
     }
   }
   __syncthreads();  // the operand tiles are dead; the LDS now stages the output tile
@@ -862,10 +876,11 @@ constexpr Shape kCompress16[kNumShapes] = {{2, 1, 4, 4, 3}, {2, 1, 4, 4, 4}, {2,
                                            {4, 1, 2, 4, 4}, {2, 2, 2, 2, 3}, {1, 4, 2, 2, 3}, {2, 1, 4, 2, 5}};
 constexpr Shape kExpand16[kNumShapes] = {{1, 2, 4, 4, 4}, {1, 2, 4, 4, 3}, {1, 4, 2, 4, 3}, {2, 2, 4, 2, 3},
                                          {1, 4, 2, 2, 3}, {1, 4, 2, 4, 5}, {2, 2, 2, 4, 3}, {1, 4, 1, 4, 3}};
-constexpr Shape kCompressLds[kNumShapes] = {{4, 1, 1, 1, 0}, {4, 1, 1, 2, 0}, {2, 2, 2, 1, 0}, {2, 1, 2, 1, 0},
-                                            {4, 2, 1, 1, 0}, {2, 2, 1, 2, 0}, {2, 1, 1, 1, 0}, {1, 4, 1, 1, 0}};
-constexpr Shape kExpandLds[kNumShapes] = {{1, 4, 1, 1, 0}, {1, 4, 1, 2, 0}, {2, 2, 1, 1, 0}, {1, 2, 1, 1, 0},
-                                          {2, 4, 1, 1, 0}, {1, 2, 1, 2, 0}, {1, 2, 1, 4, 0}, {2, 2, 1, 2, 0}};
+// (depth = k-tiles of register prefetch for the LDS-staged forms)
+constexpr Shape kCompressLds[kNumShapes] = {{4, 1, 1, 1, 1}, {4, 1, 1, 1, 2}, {4, 1, 1, 2, 1}, {2, 2, 2, 1, 1},
+                                            {2, 1, 2, 1, 1}, {4, 2, 1, 1, 1}, {2, 1, 1, 1, 1}, {1, 4, 1, 1, 1}};
+constexpr Shape kExpandLds[kNumShapes] = {{1, 4, 1, 1, 1}, {1, 4, 1, 1, 2}, {2, 2, 1, 1, 1}, {1, 4, 1, 2, 1},
+                                          {2, 4, 1, 1, 1}, {1, 2, 1, 2, 1}, {1, 2, 1, 1, 1}, {2, 2, 1, 2, 1}};
 constexpr Shape kCompressGeneral = {4, 1, 2, 2, 3};
 constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
 
@@ -893,7 +908,7 @@ void launch_compress_v(hipStream_t s, const CompressArgs& a) {
   if (compress_staged(a, ST)) {
     constexpr Shape S = kCompressLds[V];
     const dim3 grid(tiles(a.N, S.wn * S.nt * 32) * tiles(a.M, S.wm * S.mt * 32) * rest);
-    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
   } else if (compress_uniform(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kCompress32[V] : kCompress16[V];
     constexpr int T = Geo<ST>::T;
@@ -911,7 +926,7 @@ void launch_expand_v(hipStream_t s, const ExpandArgs& a) {
   if (ST == Store::F32 && a.KD % 32 == 0 && expand_uniform(a, ST)) {
     constexpr Shape S = kExpandLds[V];
     const dim3 grid(tiles(a.N, S.wn * S.nt * 32) * tiles(a.M, S.wm * S.mt * 32) * rest);
-    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
   } else if (expand_uniform(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kExpand32[V] : kExpand16[V];
     constexpr int T = Geo<ST>::T;
