@@ -78,6 +78,11 @@ __host__ __device__ inline void rr_pair(int n, int s, int i, int* p, int* q) {
 constexpr int kBlk = 16;     // Jacobi block
 constexpr int kPair = 32;    // pair problem size
 constexpr int kLd = 33;      // LDS row stride of 32 x 32 tiles
+// Inner sweeps per pair problem and round.  The pair problem need not be
+// diagonalised to rounding: the outer sweeps revisit every coupling, and two
+// inner sweeps gave the fewest total operations on Ns = 1024 (the outer sweep
+// count stays at 10-11 from 1 to 15 inner sweeps).
+constexpr int kInnerSweeps = 2;
 
 // ---------------------------------------------------------------------------
 // Whitening factor: T = Q^{-1}, Psi = Q Q^H, one work-group, global scratch.
@@ -180,7 +185,7 @@ constexpr int kGR = 16;   // pixels per chunk
 
 typedef double dx4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gram(const double2* __restrict__ cw, const double* __restrict__ wc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_gram(const double2* __restrict__ cw, const double* __restrict__ wc,
                                               const float2* __restrict__ psf, const double2* __restrict__ dtab,
                                               const double* __restrict__ qinv, const int* __restrict__ t0s,
                                               double2* __restrict__ H, int P, int nx, int ny, int nt, int ns,
@@ -204,23 +209,57 @@ __global__ __launch_bounds__(256) void k_gram(const double2* __restrict__ cw, co
       ci[i][j] = dx4{0.0, 0.0, 0.0, 0.0};
     }
   const double* qg = qinv + (size_t)g * ny;
+  // Each thread synthesises pixel rr = tid % kGR of every chunk for the rows
+  // a = tid / kGR + 16 q (q < 4) of both sides: the row-dependent factors
+  // (coil map base, sample j) are fixed for the whole pixel loop.
+  static_assert(kGR == 16 && kGT == 64, "synthesis mapping assumes 16 pixels x 64 rows per chunk");
+  const int rr = tid & (kGR - 1), arow = tid >> 4;
+  const double2* cwrow[2][4];
+  int jrow[2][4];
+  bool vrow[2][4];
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = (sd ? tb : ta) * kGT + arow + 16 * q;
+      vrow[sd][q] = idx < ns;
+      const int n = vrow[sd][q] ? idx / P : 0;
+      jrow[sd][q] = vrow[sd][q] ? idx - n * P : 0;
+      cwrow[sd][q] = cw + (size_t)n * npix;
+    }
+  // pixel r = r0 + rr, as (iy, ix), advanced by kGR per chunk
+  int iy = rr / nx, ix = rr - (rr / nx) * nx;
   for (int r0 = 0; r0 < npix; r0 += kGR) {
-    for (int e = tid; e < 2 * kGT * kGR; e += 256) {
-      const int side = e / (kGT * kGR);
-      const int rem = e - side * kGT * kGR;
-      const int a = rem / kGR, rr = rem - a * kGR;
-      const int idx = (side ? tb : ta) * kGT + a;
-      const int r = r0 + rr;
-      double2 v = make_double2(0.0, 0.0);
-      if (idx < ns && r < npix) {
-        const int n = idx / P, j = idx - n * P;
-        const int iy = r / nx, ix = r - iy * nx;
-        const float2 pf = psf[(size_t)iy * nt + t0 + j];
-        v = zmul(zmul(cw[(size_t)n * npix + r], make_double2(pf.x, pf.y)), dtab[j * nx + ix]);
-        if (side == 0) v = zscale(v, wc[r] * qg[iy]);
+    const int r = r0 + rr;
+    if (r < npix) {
+      const float2* prow = psf + (size_t)iy * nt + t0;
+      const double2* drow = dtab + ix;
+      const double wq = wc[r] * qg[iy];
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double2 v = make_double2(0.0, 0.0);
+          if (vrow[sd][q]) {
+            const int j = jrow[sd][q];
+            const float2 pf = prow[j];
+            v = zmul(zmul(cwrow[sd][q][r], make_double2(pf.x, pf.y)), drow[(size_t)j * nx]);
+            if (sd == 0) v = zscale(v, wq);
+          }
+          if (sd) eB[arow + 16 * q][rr] = v;
+          else eA[arow + 16 * q][rr] = v;
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        eA[arow + 16 * q][rr] = make_double2(0.0, 0.0);
+        eB[arow + 16 * q][rr] = make_double2(0.0, 0.0);
       }
-      if (side) eB[a][rr] = v;
-      else eA[a][rr] = v;
+    }
+    ix += kGR;
+    while (ix >= nx) {
+      ix -= nx;
+      ++iy;
     }
     __syncthreads();
 #pragma unroll
@@ -306,7 +345,7 @@ __global__ __launch_bounds__(256) void k_jac_solve(const double2* __restrict__ H
   }
   __syncthreads();
   const int bi = tid / (kPair / 2), bj = tid % (kPair / 2);  // 2 x 2 block of M owned in a step
-  for (int sweep = 0; sweep < 15; ++sweep) {
+  for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < kPair * kPair; e += 256) {
       const int a = e / kPair, b = e % kPair;
@@ -413,23 +452,51 @@ __global__ __launch_bounds__(256) void k_jac_solve(const double2* __restrict__ H
   if (tid == 0) rot[g * (nb / 2) + pr] = rotated;
 }
 
-// One 16 x 16 block of a complex 32 x 32 x 32 product from LDS tiles on the
-// FP64 16x16x4 MFMA: C[16 bi + ., 16 bj + .] = sum_k op(A)[., k] B[k, .] with
-// op(A) = A, or A^H when AH.  The complex product takes four real products
-// (re = ar br - ai bi, im = ar bi + ai br).  Operand lanes: A[l % 16][l / 16],
-// B[l / 16][l % 16]; result lane l, register r: C[4 r + l / 16][l % 16].
-template <bool AH>
-__device__ inline void ztile_mma(const double2 (*A)[kLd], const double2 (*B)[kLd], int bi, int bj, dx4& cr,
-                                 dx4& ci) {
+// One 16 x 16 block of a complex 32 x 32 x 32 product on the FP64 16x16x4
+// MFMA.  The complex product takes four real products (re = ar br - ai bi,
+// im = ar bi + ai br).  Operand lanes: A[l % 16][l / 16], B[l / 16][l % 16];
+// result lane l, register r: C[4 r + l / 16][l % 16].
+//
+// Register fragments of a 32 x 32 row-major tile T for k-steps k0 = 0, 4, ..:
+//   as B operand of column block bj:        frag[s] = T[4 s + l / 16][16 bj + l % 16]
+//   as A operand of (T^H), row block bi:    frag[s] = conj(T[4 s + l / 16][16 bi + l % 16])
+// Both read the same elements; the conjugation is applied at use.
+
+__device__ inline void zfrag_load(const double2* __restrict__ T, int blk, double2 (&f)[kPair / 4]) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < kPair / 4; ++s) f[s] = T[(4 * s + (l >> 4)) * kPair + 16 * blk + (l & 15)];
+}
+
+// C = X[16 bi + ., :] * B, B given as fragments of column block bj; X in LDS.
+__device__ inline void zmma_lds_frag(const double2 (*X)[kLd], const double2 (&fb)[kPair / 4], int bi, dx4& cr,
+                                     dx4& ci) {
   const int l = threadIdx.x & 63;
   const int li = l & 15, lk = l >> 4;
   cr = dx4{0.0, 0.0, 0.0, 0.0};
   ci = dx4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k0 = 0; k0 < kPair; k0 += 4) {
-    double2 a = AH ? A[k0 + lk][16 * bi + li] : A[16 * bi + li][k0 + lk];
-    if (AH) a.y = -a.y;
-    const double2 b = B[k0 + lk][16 * bj + li];
+  for (int s = 0; s < kPair / 4; ++s) {
+    const double2 a = X[16 * bi + li][4 * s + lk];
+    const double2 b = fb[s];
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+  }
+}
+
+// C = V^H[16 bi + ., :] * X[:, 16 bj + .], V^H given as fragments of row block bi; X in LDS.
+__device__ inline void zmma_fragh_lds(const double2 (&fa)[kPair / 4], const double2 (*X)[kLd], int bj, dx4& cr,
+                                      dx4& ci) {
+  const int l = threadIdx.x & 63;
+  const int li = l & 15, lk = l >> 4;
+  cr = dx4{0.0, 0.0, 0.0, 0.0};
+  ci = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < kPair / 4; ++s) {
+    const double2 a = make_double2(fa[s].x, -fa[s].y);
+    const double2 b = X[4 * s + lk][16 * bj + li];
     cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
     cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
     ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
@@ -445,8 +512,10 @@ __device__ inline void ztile_store(double2 (*C)[kLd], int bi, int bj, const dx4&
 
 // H <- Q^H H Q on the tile of pair a (rows) x pair b (cols), a <= b; the
 // mirrored tile (b, a) is written as the conjugate transpose.  Each of the
-// four waves owns one 16 x 16 quarter of the tile.
-__global__ __launch_bounds__(256) void k_jac_apply_h(double2* __restrict__ H, const double2* __restrict__ Vall,
+// four waves owns one 16 x 16 quarter of the tile; the rotation blocks are
+// read from L2 straight into MFMA operand registers, so only the H tile
+// occupies LDS.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_jac_apply_h(double2* __restrict__ H, const double2* __restrict__ Vall,
                                                      const int* __restrict__ rot, const int* __restrict__ active,
                                                      int nsp, int nb, int round) {
   const int g = blockIdx.y;
@@ -460,29 +529,26 @@ __global__ __launch_bounds__(256) void k_jac_apply_h(double2* __restrict__ H, co
   rr_pair(nb, round, a, &Ia, &Ja);
   rr_pair(nb, round, b, &Ib, &Jb);
   __shared__ double2 X[kPair][kLd];
-  __shared__ double2 Va[kPair][kLd];
-  __shared__ double2 Vb[kPair][kLd];
   const int tid = threadIdx.x;
+  const int w = tid >> 6, bi = w >> 1, bj = w & 1;
   double2* Hg = H + (size_t)g * nsp * nsp;
-  const double2* Vga = Vall + ((size_t)g * npair + a) * kPair * kPair;
-  const double2* Vgb = Vall + ((size_t)g * npair + b) * kPair * kPair;
+  double2 fa[kPair / 4], fb[kPair / 4];
+  if (rb) zfrag_load(Vall + ((size_t)g * npair + b) * kPair * kPair, bj, fb);
+  if (ra) zfrag_load(Vall + ((size_t)g * npair + a) * kPair * kPair, bi, fa);
   for (int e = tid; e < kPair * kPair; e += 256) {
     const int i = e / kPair, j = e % kPair;
     X[i][j] = Hg[(size_t)pair_index(Ia, Ja, i) * nsp + pair_index(Ib, Jb, j)];
-    if (ra) Va[i][j] = Vga[e];
-    if (rb) Vb[i][j] = Vgb[e];
   }
   __syncthreads();
-  const int w = tid >> 6, bi = w >> 1, bj = w & 1;
   dx4 cr, ci;
   if (rb) {  // X <- X V_b
-    ztile_mma<false>(X, Vb, bi, bj, cr, ci);
+    zmma_lds_frag(X, fb, bi, cr, ci);
     __syncthreads();
     ztile_store(X, bi, bj, cr, ci);
     __syncthreads();
   }
   if (ra) {  // X <- V_a^H X
-    ztile_mma<true>(Va, X, bi, bj, cr, ci);
+    zmma_fragh_lds(fa, X, bj, cr, ci);
     __syncthreads();
     ztile_store(X, bi, bj, cr, ci);
     __syncthreads();
@@ -507,12 +573,12 @@ __global__ __launch_bounds__(256) void k_jac_apply_u(double2* __restrict__ U, co
   int Ib, Jb;
   rr_pair(nb, round, b, &Ib, &Jb);
   __shared__ double2 X[kPair][kLd];
-  __shared__ double2 Vb[kPair][kLd];
   const int tid = threadIdx.x;
-  double2* Ug = U + (size_t)g * nsp * nsp;
-  const double2* Vgb = Vall + ((size_t)g * npair + b) * kPair * kPair;
-  for (int e = tid; e < kPair * kPair; e += 256) Vb[e / kPair][e % kPair] = Vgb[e];
   const int w = tid >> 6, bi = w >> 1, bj = w & 1, l = tid & 63;
+  double2* Ug = U + (size_t)g * nsp * nsp;
+  double2 fb[kPair / 4];
+  zfrag_load(Vall + ((size_t)g * npair + b) * kPair * kPair, bj, fb);
+  const int col = pair_index(Ib, Jb, 16 * bj + (l & 15));
   const int rend = min(nsp, (int)(blockIdx.x + 1) * kURows);
   for (int r0 = blockIdx.x * kURows; r0 < rend; r0 += kPair) {
     for (int e = tid; e < kPair * kPair; e += 256) {
@@ -521,8 +587,7 @@ __global__ __launch_bounds__(256) void k_jac_apply_u(double2* __restrict__ U, co
     }
     __syncthreads();
     dx4 cr, ci;
-    ztile_mma<false>(X, Vb, bi, bj, cr, ci);
-    const int col = pair_index(Ib, Jb, 16 * bj + (l & 15));
+    zmma_lds_frag(X, fb, bi, cr, ci);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       Ug[(size_t)(r0 + 16 * bi + 4 * r + (l >> 4)) * nsp + col] = make_double2(cr[r], ci[r]);
