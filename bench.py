@@ -314,18 +314,30 @@ def main():
     log(f"lambda {lam:.4e}, L {lip:.4e}")
 
     x = torch.empty((1, g.ny, g.nx), dtype=torch.complex64, device=dev)
+    # Untimed pass with every stage launch bracketed by HIP events: the
+    # per-stage breakdown, and the dominant kernel.  Event pairs between
+    # launches cost a few microseconds each, so the timed steps bracket only
+    # the dominant kernel.
+    plan.stage_timing(True)
+    plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec=args.prec, out=x)
+    torch.cuda.synchronize()
+    stages = plan.stage_times()
+    plan.stage_timing(False)
+    per_stage = {k: {"ms_per_launch": (v[0] / v[1] if v[1] else 0.0), "launches": v[1], "ms_total": v[0]}
+                 for k, v in stages.items() if v[1]}
+    dom = max(per_stage, key=lambda k: per_stage[k]["ms_total"])
     for i in range(args.warmup):
         plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec=args.prec, out=x)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup}")
-    plan.stage_timing(True)
+    plan.stage_timing(True, stages=[dom])
     torch.cuda.synchronize()
     t = time.perf_counter()
     for i in range(args.steps):
         plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec=args.prec, out=x)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    stages = plan.stage_times()
+    live = plan.stage_times()[dom]
     plan.stage_timing(False)
     ms_per_step = 1e3 * dt / args.steps
     value = ITERS * args.steps / dt
@@ -343,11 +355,8 @@ def main():
     torch.cuda.synchronize()
     op_rate = nop / (time.perf_counter() - t)
 
-    per_stage = {k: {"ms_per_launch": (v[0] / v[1] if v[1] else 0.0), "launches": v[1], "ms_total": v[0]}
-                 for k, v in stages.items() if v[1]}
-    dom = max(per_stage, key=lambda k: per_stage[k]["ms_total"])
     bound, work, kind = stage_work(g, dom, args.prec)
-    avg_s = per_stage[dom]["ms_per_launch"] / 1e3
+    avg_s = live[0] / live[1] / 1e3  # measured over the timed steps
     if bound == "mfma":
         peak = PEAKS[args.prec]
         roof = {"bound": "mfma", "achieved": work / avg_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
@@ -361,6 +370,7 @@ def main():
     roof["kernel"] = dom
     roof["work_per_launch"] = work
     roof["work_unit"] = kind
+    roof["timed_launches"] = live[1]
 
     result = {
         "metric": METRIC,
@@ -387,6 +397,8 @@ def main():
         "calibrate_s": t_cal,
         "compress_s": t_comp,
         "stages": per_stage,
+        "stages_note": "one untimed FISTA step with every launch bracketed by HIP events (the events add gaps); "
+                       "the timed steps bracket only the roofline kernel",
         "roofline": roof,
         "cpu_baseline": None,
     }

@@ -200,6 +200,11 @@ enum {
   GPJC_STAGE_COUNT
 };
 int gpjc_stage_timing(gpjc_plan* plan, int enable);
+/* As gpjc_stage_timing, but only the stages whose bit (1 << stage id) is set
+ * in stage_mask are bracketed; 0 disables timing.  Each event pair adds a few
+ * microseconds between launches, so a throughput measurement times only the
+ * stage it reports.  GPJC_E_INVAL for bits at or above GPJC_STAGE_COUNT. */
+int gpjc_stage_timing_select(gpjc_plan* plan, unsigned stage_mask);
 int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches);
 
 /* Work-group tile shape of the two group contractions and the contraction

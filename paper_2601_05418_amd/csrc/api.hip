@@ -462,8 +462,14 @@ int gpjc_wavelet_absmax(gpjc_plan* plan, const gpjc_c64* d_img, int haar_levels,
 }
 
 int gpjc_stage_timing(gpjc_plan* plan, int enable) {
+  return gpjc_stage_timing_select(plan, enable ? (1u << GPJC_STAGE_COUNT) - 1u : 0u);
+}
+
+int gpjc_stage_timing_select(gpjc_plan* plan, unsigned stage_mask) {
   GPJC_TRY(check_plan(plan));
+  if (stage_mask >> GPJC_STAGE_COUNT) return fail(GPJC_E_INVAL, "stage mask names an unknown stage");
   Timing& t = plan->timing;
+  const bool enable = stage_mask != 0;
   if (enable) {
     if (t.ev.empty()) {
       const int cap = 16384;
@@ -473,7 +479,8 @@ int gpjc_stage_timing(gpjc_plan* plan, int enable) {
     }
     t.used = 0;
   }
-  t.on = enable != 0;
+  t.on = enable;
+  t.mask = stage_mask;
   return GPJC_OK;
 }
 

@@ -33,6 +33,7 @@ enum class Store { F32 = 0, BF16 = 1, F16 = 2 };
 // HIP-event timing of stage launches (enabled on request).
 struct Timing {
   bool on = false;
+  unsigned mask = 0;  // bit s set: stage s is timed
   int used = 0;
   std::vector<hipEvent_t> ev;  // 2 per launch
   std::vector<int> stage;
@@ -115,7 +116,7 @@ struct StageScope {
   int slot = -1;
   StageScope(const Plan& p, int st) : pl(p) {
     Timing& t = p.timing;
-    if (t.on && t.used < (int)t.stage.size()) {
+    if (t.on && ((t.mask >> st) & 1u) && t.used < (int)t.stage.size()) {
       slot = t.used++;
       t.stage[slot] = st;
       (void)hipEventRecord(t.ev[2 * slot], p.stream);

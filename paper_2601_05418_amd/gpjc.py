@@ -70,6 +70,7 @@ _SIGS = {
     "gpjc_power_iteration": (_I, [_VP, _I, _VP, _I, _VP]),
     "gpjc_wavelet_absmax": (_I, [_VP, _VP, _I, _VP]),
     "gpjc_stage_timing": (_I, [_VP, _I]),
+    "gpjc_stage_timing_select": (_I, [_VP, ctypes.c_uint]),
     "gpjc_stage_times": (_I, [_VP, _VP, _VP]),
     "gpjc_set_gemm_config": (_I, [_VP, _I, _I, _I, _I]),
     "gpjc_get_gemm_config": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
@@ -299,8 +300,16 @@ class Plan:
         _check(self.lib.gpjc_wavelet_absmax(self.handle, self._in(img), int(levels), ctypes.byref(out)))
         return out.value
 
-    def stage_timing(self, enable=True):
-        _check(self.lib.gpjc_stage_timing(self.handle, int(bool(enable))))
+    def stage_timing(self, enable=True, stages=None):
+        """Bracket stage launches with HIP events: all stages, or only the
+        named ones (names from STAGES) when `stages` is given."""
+        if stages is None:
+            _check(self.lib.gpjc_stage_timing(self.handle, int(bool(enable))))
+            return
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+        _check(self.lib.gpjc_stage_timing_select(self.handle, mask if enable else 0))
 
     def stage_times(self):
         ms = (ctypes.c_double * len(STAGES))()

@@ -87,6 +87,7 @@ def test_null_plan_calls():
     assert lib.gpjc_forward(None, 0, FAKE, FAKE) == gpjc.GPJC_E_INVAL
     assert lib.gpjc_recon_cg(None, 0, FAKE, FAKE, 5, 0, None) == gpjc.GPJC_E_INVAL
     assert lib.gpjc_plan_destroy(None) == gpjc.GPJC_OK
+    assert lib.gpjc_stage_timing_select(None, 1) == gpjc.GPJC_E_INVAL
 
 
 def test_batch_and_autotune_argument_errors():
