@@ -355,6 +355,45 @@ def main():
     torch.cuda.synchronize()
     op_rate = nop / (time.perf_counter() - t)
 
+    def op_rate_of(pl, prec, n=100):
+        for _ in range(5):
+            pl.normal(x, prec=prec, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            pl.normal(x, prec=prec, out=out)
+        torch.cuda.synchronize()
+        return n / (time.perf_counter() - t0)
+
+    # the same operator with 16-bit operands (FP32 accumulation), and the
+    # uncompressed FP32 operator on the same slice
+    variants = {args.prec: op_rate}
+    for pr in ("fp32", "bf16", "fp16"):
+        if pr != args.prec:
+            variants[pr] = op_rate_of(plan, pr)
+    unc = gpjc.Plan.from_slice(sl, compressed=False)
+    variants["uncompressed_fp32"] = op_rate_of(unc, "fp32")
+    log("E'^H E' per s: " + ", ".join(f"{k} {v:.0f}" for k, v in variants.items()))
+    # the same FISTA-50 reconstruction with the plain (uncompressed) FP32
+    # operator on the acquired k-space: the reference the compression is
+    # measured against
+    b_u = unc.adjoint(ksp)
+    lam_u = 1e-3 * unc.wavelet_absmax(b_u, LEVELS)
+    lip_u = unc.power_iteration(x0, 50) * 1.01
+    x_u = torch.empty_like(x)
+    for _ in range(max(1, args.warmup)):
+        unc.recon_fista(ksp, ITERS, lam_u, lip_u, LEVELS, out=x_u)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        unc.recon_fista(ksp, ITERS, lam_u, lip_u, LEVELS, out=x_u)
+    torch.cuda.synchronize()
+    dt_u = (time.perf_counter() - t) / args.steps
+    plain = {"s_per_slice": dt_u, "apps_per_s": ITERS / dt_u, "op_apps_per_s": variants["uncompressed_fp32"],
+             "speedup_of_compressed": dt_u / (ms_per_step / 1e3)}
+    unc.close()
+    log(f"plain FP32 FISTA-{ITERS}: {dt_u * 1e3:.3f} ms per slice")
+
     bound, work, kind = stage_work(g, dom, args.prec)
     avg_s = live[0] / live[1] / 1e3  # measured over the timed steps
     if bound == "mfma":
@@ -394,6 +433,8 @@ def main():
         },
         "s_per_slice": ms_per_step / 1e3,
         "op_apps_per_s": op_rate,
+        "op_apps_per_s_by_variant": variants,
+        "plain_fp32": plain,
         "calibrate_s": t_cal,
         "compress_s": t_comp,
         "stages": per_stage,

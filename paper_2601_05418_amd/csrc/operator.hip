@@ -670,6 +670,92 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
 }
 
 // ---------------------------------------------------------------------------
+// F_yᴴ M F_y on uncompressed columns, in place, two-pass register form (as
+// k_pe_normal2).  Work-group: one (b, n) and L consecutive t; lane ln = tid %
+// L owns column t0 + ln, so every global access is an L-sample row segment.
+// The first pass reads its stride-N2 inputs straight from W and the last pass
+// writes straight back; only the two exchanges go through LDS, laid out with
+// the column index fastest.
+// ---------------------------------------------------------------------------
+template <int NY>
+struct PeCols2Geo {
+  static constexpr int N1 = Split<NY>::N1, N2 = Split<NY>::N2;
+  static constexpr int L = 256 / (N1 > N2 ? N1 : N2);  // columns per work-group
+};
+
+template <int NY>
+__global__ __launch_bounds__(256) void k_pe_cols_normal2(float2* __restrict__ W, const float* __restrict__ maskf,
+                                                         int nt, const float2* __restrict__ tw) {
+  using Gm = PeCols2Geo<NY>;
+  constexpr int N1 = Gm::N1, N2 = Gm::N2, L = Gm::L;
+  __shared__ float2 twl[NY];
+  __shared__ float2 E[N1 * N2 * L];  // element (i2, k1) of column ln at (i2 N1 + k1) L + ln
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
+  const int t0 = blockIdx.x * L;
+  const int ln = tid % L, it = tid / L;
+  const bool colok = t0 + ln < nt;
+  float2* col = W + (size_t)blockIdx.y * NY * nt + t0 + ln;  // sample y of this column at col[y nt]
+  float2 v[N1];
+  if (it < N2) {  // forward, first pass: item (ln, i2 = it)
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) {
+      const int y = it + N2 * i1;
+      const float2 a = colok ? col[(size_t)y * nt] : make_float2(0.f, 0.f);
+      v[i1] = (y & 1) ? make_float2(-a.x, -a.y) : a;
+    }
+  }
+  __syncthreads();  // twiddle table
+  if (it < N2) {
+    rdft<N1>(v);
+    E[(it * N1) * L + ln] = v[0];
+    int m = it;
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      E[(it * N1 + k1) * L + ln] = cmul(v[k1], twl[m]);
+      m += it;
+      m = m >= NY ? m - NY : m;
+    }
+  }
+  __syncthreads();
+  // forward second pass, mask, and the second transform's first pass: item (ln, k1 = it)
+  float2 w[N2];
+  const bool act2 = it < N1;
+  if (act2) {
+#pragma unroll
+    for (int i2 = 0; i2 < N2; ++i2) w[i2] = E[(i2 * N1 + it) * L + ln];
+    rdft<N2>(w);  // w[k2] = F[k1 + N1 k2]
+    const float inv = 1.0f / (float)NY;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) w[k2] = cconj(cscale(w[k2], maskf[it + N1 * k2] * inv));
+    rdft<N2>(w);
+  }
+  __syncthreads();
+  if (act2) {
+    int m = 0;
+#pragma unroll
+    for (int m2 = 0; m2 < N2; ++m2) {
+      E[(m2 * N1 + it) * L + ln] = cmul(w[m2], twl[m]);  // twiddle w_NY^{k1 m2}
+      m += it;
+      m = m >= NY ? m - NY : m;
+    }
+  }
+  __syncthreads();
+  if (it < N2 && colok) {  // second transform, last pass: item (ln, m2 = it)
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = E[(it * N1 + n1) * L + ln];
+    rdft<N1>(v);  // v[n1] = G[m2 + N2 n1]
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int y = it + N2 * n1;
+      float2 r = cconj(v[n1]);
+      if (y & 1) r = make_float2(-r.x, -r.y);
+      col[(size_t)y * nt] = r;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side sizing of the two-pass readout forms (complex elements of LDS).
 // ---------------------------------------------------------------------------
 size_t two_pass_lds_fwd(int nx, int os, int cb) {
@@ -838,6 +924,15 @@ struct PeCols {
   struct L {
     static int run(const Plan& pl, int mode, const float2* in_s, float2* out_s) {
       StageScope sc(pl, GPJC_STAGE_PE_COLS);
+      if constexpr (ST == Store::F32 && Split<NY>::N1 > 1 && Split<NY>::N2 > 1 && Split<NY>::N2 <= 32) {
+        if (mode == 2) {
+          constexpr int L = PeCols2Geo<NY>::L;
+          hipLaunchKernelGGL((k_pe_cols_normal2<NY>), dim3((pl.nt + L - 1) / L, pl.B * pl.nc), dim3(256), 0,
+                             pl.stream, pl.W, pl.maskf, pl.nt, pl.tw_y);
+          GPJC_HIP(hipGetLastError());
+          return GPJC_OK;
+        }
+      }
       const int tb = pl.f3_tb;
       const size_t lds = (size_t)(NY + 2 * tb * fline(NY)) * sizeof(float2);
       dim3 grid((pl.nt + tb - 1) / tb, pl.B * pl.nc);

@@ -94,6 +94,16 @@ def test_uncompressed(gpu_lib, case):
     check(host(plan.normal(dev(x)))[0], ops["nrm_full"](x[0]))
 
 
+def test_uncompressed_normal_ragged_column_block(gpu_lib):
+    """Ny = 16 splits as 8 x 2, so the column-FFT kernel takes 32 readout
+    samples per work-group; Nt = 3 x 16 = 48 leaves a half-filled last block."""
+    sl = H.rounded_slice(synth.tiny_slice(0, nx=16, ny=16, nc=3, os_=3, patch_len=4, k=6))
+    plan = gpjc.Plan.from_slice(sl, compressed=False)
+    ops = H.oracle_ops(sl, None)
+    x = H.round64(H.crandn(np.random.default_rng(8), (1, 16, 16)))
+    check(host(plan.normal(dev(x)))[0], ops["nrm_full"](x[0]))
+
+
 @pytest.mark.parametrize("case", ["small", "rect"])
 def test_adjoint_identity(gpu_lib, case):
     sl, a, plan = make(case)
@@ -130,6 +140,16 @@ def test_highfield_full_size(gpu_lib):
     check(host(plan.forward(dev(x)))[0], ops["fwd"](x[0]))
     y = H.round64(H.crandn(np.random.default_rng(8), plan.data_shape()))
     check(host(plan.adjoint(dev(y)))[0], ops["adj"](y[0]))
+
+
+def test_highfield_uncompressed_normal_full_size(gpu_lib):
+    """The plain operator's normal form at full size (column FFTs of
+    224 = 16 x 14 over 32 x 1344 columns), every element against the oracle."""
+    sl = H.rounded_slice(synth.highfield_slice(0))
+    plan = gpjc.Plan.from_slice(sl, compressed=False)
+    ops = H.oracle_ops(sl, None)
+    x = H.round64(sl.image)[None]
+    check(host(plan.normal(dev(x)))[0], ops["nrm_full"](x[0]))
 
 
 def test_state_and_argument_errors(gpu_lib):

@@ -109,3 +109,14 @@ def test_stage_timing_counts(gpu_lib):
     plan.stage_timing(False)
     assert t["readout_fwd"][1] == 4 and t["group_compress"][1] == 4 and t["readout_adj"][1] == 5
     assert t["solver"][1] == 4 and all(v[0] >= 0 for v in t.values())
+
+
+def test_stage_timing_select_times_only_named_stages(gpu_lib):
+    sl, plan, ops, y = setup("small")
+    plan.stage_timing(True, stages=["group_expand"])
+    plan.recon_fista(dev(y[None]), 4, 1e-3, 2.0, levels=3)
+    t = plan.stage_times()
+    plan.stage_timing(False)
+    assert t["group_expand"][1] == 5 and t["group_expand"][0] > 0
+    assert all(v[1] == 0 for k, v in t.items() if k != "group_expand")
+    assert plan.lib.gpjc_stage_timing_select(plan.handle, 1 << len(gpjc.STAGES)) == gpjc.GPJC_E_INVAL
