@@ -564,20 +564,25 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 compressing contraction staged through LDS.  The operand layout of an
-// MFMA spans 32 rows per load instruction, so register-direct loads touch 32
-// cache lines each; here the work-group loads k-tiles of 32 elements (one
-// 128-byte line per row) cooperatively, eight lanes per row, into LDS, and
-// the waves read their MFMA fragments from there.  The next PF k-tiles are
+// Compressing contraction staged through LDS.  The operand layout of an MFMA
+// spans 16 or 32 rows per load instruction, so register-direct loads touch
+// that many cache lines each; here the work-group loads k-tiles of one
+// 128-byte line per row (32 FP32 or 64 16-bit elements) cooperatively, eight
+// lanes per row, into LDS, and the waves read their MFMA fragments from
+// there (32x32x2 FP32, or 16x16x32 BF16 / FP16 with FP32 accumulation).  The next PF k-tiles are
 // prefetched into registers while the current one is multiplied.  Row
 // stride 36 floats (144 bytes, an odd multiple of 16): the 16-byte fragment
-// reads of one pass fall on distinct bank groups.  Needs 2P a multiple of 32
-// (a k-tile never crosses a coil) and the k-split chunk a multiple of 32.
+// reads of one pass fall on distinct bank groups.  Needs 2P a multiple of the
+// k-tile (a k-tile never crosses a coil) and the k-split chunk a multiple of it.
 // ---------------------------------------------------------------------------
-template <int WM, int WN, int MT, int NT, int PF>
+template <int WM, int WN, int MT, int NT, int PF, Store ST>
 __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
-  using G = Geo<Store::F32>;
-  constexpr int T = 32, KT = 32, LS = KT + 4;
+  using G = Geo<ST>;
+  using E = typename Mma<ST>::E;
+  constexpr int T = G::T, NR = G::NR, NE = G::NE;
+  constexpr int ES = (int)sizeof(E);
+  constexpr int KT = 128 / ES, LS = 36;  // k-tile elements per row; LDS row stride in floats
+  constexpr int JB = 128 / (G::KB * ES), JF = G::KB * ES / 4;  // MFMA blocks per k-tile, floats per block
   constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
   constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;  // 16-byte chunks per thread per k-tile
   static_assert(AR * NTHR == TM * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
@@ -586,7 +591,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   float* Bs = As + TM * LS;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 31, lh = lane >> 5;
+  const int li = lane % T, lh = lane / T;
   const int wm = wave / WN, wn = wave % WN;
   const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
   const int total = tiles_n * tiles_m * a.B * a.np * a.ksplit;
@@ -600,10 +605,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   const int twoP = 2 * a.P;
   const size_t cstride = (size_t)a.N * a.nt * 2;
 
-  const float* Ab = static_cast<const float*>(a.A) + (size_t)g * a.M * a.KD;
-  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)a.M * a.KD * 4));
-  const float* Bb = static_cast<const float*>(a.in) + (size_t)b * a.nc * cstride + (size_t)p * twoP;
-  const __amdgpu_buffer_rsrc_t rB = make_rsrc(Bb, (uint32_t)((a.nc * cstride - (size_t)p * twoP) * 4));
+  const E* Ab = static_cast<const E*>(a.A) + (size_t)g * a.M * a.KD;
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)a.M * a.KD * ES));
+  const E* Bb = static_cast<const E*>(a.in) + (size_t)b * a.nc * cstride + (size_t)p * twoP;
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(Bb, (uint32_t)((a.nc * cstride - (size_t)p * twoP) * ES));
 
   const int kbeg = ks * a.kchunk;
   const int kend = min(a.KD, kbeg + a.kchunk);
@@ -615,14 +620,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
   for (int r = 0; r < AR; ++r) {
     const int row = tm * TM + (tid >> 3) + r * (NTHR / 8);
-    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + kbeg + 4 * c16) * 4) : kOOB;
+    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + kbeg + (KT / 8) * c16) * ES) : kOOB;
   }
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
-    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)n * cstride + jj + 4 * c16) * 4) : kOOB;
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)n * cstride + jj + (KT / 8) * c16) * ES) : kOOB;
   }
-  const uint32_t wrap = (uint32_t)((cstride - (size_t)(twoP - KT)) * 4);
+  const uint32_t wrap = (uint32_t)((cstride - (size_t)(twoP - KT)) * ES);
   floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
   auto fetch = [&](floatx4(&xa)[AR], floatx4(&xb)[BR]) {
 #pragma unroll
@@ -630,13 +635,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
     for (int r = 0; r < BR; ++r) xb[r] = bload(rB, vb[r]);
     jj += KT;
-    uint32_t inc = KT * 4;
+    uint32_t inc = KT * ES;
     if (jj == twoP) {
       jj = 0;
       inc = wrap;
     }
 #pragma unroll
-    for (int r = 0; r < AR; ++r) va[r] += KT * 4;
+    for (int r = 0; r < AR; ++r) va[r] += KT * ES;
 #pragma unroll
     for (int r = 0; r < BR; ++r) vb[r] += inc;
   };
@@ -646,7 +651,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[m][c][r] = 0.f;
+      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
 #pragma unroll
   for (int f = 0; f < PF; ++f)
     if (f < nst) fetch(pa[f], pb[f]);
@@ -665,16 +670,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
       __syncthreads();
       if (st + PF < nst) fetch(pa[f], pb[f]);
 #pragma unroll
-      for (int j = 0; j < KT / 8; ++j) {
+      for (int j = 0; j < JB; ++j) {
       floatx4 fa[MT], fb[NT];
 #pragma unroll
       for (int m = 0; m < MT; ++m)
-        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + 8 * j + 4 * lh);
+        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + JF * j + 4 * lh);
 #pragma unroll
       for (int c = 0; c < NT; ++c)
-        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 8 * j + 4 * lh);
+        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < NE; ++e)
 #pragma unroll
           for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -690,21 +695,25 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
     for (int c = 0; c < NT; ++c) {
       const int col = col0 + T * c + li;
 #pragma unroll
-      for (int r = 0; r < 16; r += 2) {
+      for (int r = 0; r < NR; r += 2) {
         const int row = row0 + T * m + G::row_of(r, lh);
         if (col < a.N && row < a.M) out[(size_t)(row >> 1) * a.N + col] = make_float2(acc[m][c][r], acc[m][c][r + 1]);
       }
     }
 }
 
-// FP32 expanding contraction staged through LDS, as k_compress_lds: both
+// Expanding contraction staged through LDS, as k_compress_lds: both
 // operands (Z^T rows and rows of the real-form bank) are contiguous along the
-// contraction, which has 2 Kp (a multiple of 32) elements.  The output tile
+// contraction, which has 2 Kp elements (a multiple of the k-tile).  The output tile
 // is staged through the same LDS to write whole W row segments.
-template <int WM, int WN, int MT, int NT, int PF>
+template <int WM, int WN, int MT, int NT, int PF, Store ST>
 __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
-  using G = Geo<Store::F32>;
-  constexpr int T = 32, KT = 32, LS = KT + 4;
+  using G = Geo<ST>;
+  using E = typename Mma<ST>::E;
+  constexpr int T = G::T, NR = G::NR, NE = G::NE;
+  constexpr int ES = (int)sizeof(E);
+  constexpr int KT = 128 / ES, LS = 36;
+  constexpr int JB = 128 / (G::KB * ES), JF = G::KB * ES / 4;
   constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
   constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;
   static_assert(AR * NTHR == TM * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
@@ -715,7 +724,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
   float* Bs = As + TM * LS;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 31, lh = lane >> 5;
+  const int li = lane % T, lh = lane / T;
   const int wm = wave / WN, wn = wave % WN;
   const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
   const int total = tiles_n * tiles_m * a.B * a.np;
@@ -726,22 +735,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
   const int b = bp / a.np, p = bp - b * a.np;
   const int g = a.pgroup[p];
 
-  const __amdgpu_buffer_rsrc_t rA = make_rsrc(static_cast<const float*>(a.Zt) + (size_t)bp * a.M * a.KD,
-                                              (uint32_t)((size_t)a.M * a.KD * 4));
-  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const float*>(a.AH) + (size_t)g * a.N * a.KD,
-                                              (uint32_t)((size_t)a.N * a.KD * 4));
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(static_cast<const E*>(a.Zt) + (size_t)bp * a.M * a.KD,
+                                              (uint32_t)((size_t)a.M * a.KD * ES));
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const E*>(a.AH) + (size_t)g * a.N * a.KD,
+                                              (uint32_t)((size_t)a.N * a.KD * ES));
   const int nst = a.KD / KT;
   const int c16 = tid & 7;
   uint32_t va[AR], vb[BR];
 #pragma unroll
   for (int r = 0; r < AR; ++r) {
     const int row = tm * TM + (tid >> 3) + r * (NTHR / 8);
-    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + 4 * c16) * 4) : kOOB;
+    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + (KT / 8) * c16) * ES) : kOOB;
   }
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
-    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.KD + 4 * c16) * 4) : kOOB;
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.KD + (KT / 8) * c16) * ES) : kOOB;
   }
   floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
   auto fetch = [&](floatx4(&xa)[AR], floatx4(&xb)[BR]) {
@@ -750,9 +759,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
     for (int r = 0; r < BR; ++r) xb[r] = bload(rB, vb[r]);
 #pragma unroll
-    for (int r = 0; r < AR; ++r) va[r] += KT * 4;
+    for (int r = 0; r < AR; ++r) va[r] += KT * ES;
 #pragma unroll
-    for (int r = 0; r < BR; ++r) vb[r] += KT * 4;
+    for (int r = 0; r < BR; ++r) vb[r] += KT * ES;
   };
   typename G::Acc acc[MT][NT];
 #pragma unroll
@@ -760,7 +769,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[m][c][r] = 0.f;
+      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
 #pragma unroll
   for (int f = 0; f < PF; ++f)
     if (f < nst) fetch(pa[f], pb[f]);
@@ -779,16 +788,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
       __syncthreads();
       if (st + PF < nst) fetch(pa[f], pb[f]);
 #pragma unroll
-      for (int j = 0; j < KT / 8; ++j) {
+      for (int j = 0; j < JB; ++j) {
       floatx4 fa[MT], fb[NT];
 #pragma unroll
       for (int m = 0; m < MT; ++m)
-        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + 8 * j + 4 * lh);
+        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + JF * j + 4 * lh);
 #pragma unroll
       for (int c = 0; c < NT; ++c)
-        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 8 * j + 4 * lh);
+        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < NE; ++e)
 #pragma unroll
           for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -803,7 +812,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
+      for (int r = 0; r < NR; ++r)
         tile[(wm * MT * T + T * m + G::row_of(r, lh)) * LDT + wn * NT * T + T * c + li] = acc[m][c][r];
   __syncthreads();
   const int twoP = 2 * a.P;
@@ -815,7 +824,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
     const int n = col / twoP, jj = col - n * twoP;
     const size_t fi = (((size_t)b * a.nc + n) * a.M + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
     const float* src = tile + rl * LDT + cl;
-    *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(a.W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
+    if constexpr (ST == Store::F32) {
+      *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(a.W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
+    } else {
+      uint2 v;
+      v.x = to_bits16<ST>(src[0]) | (to_bits16<ST>(src[1]) << 16);
+      v.y = to_bits16<ST>(src[2]) | (to_bits16<ST>(src[3]) << 16);
+      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.W) + fi) = v;
+    }
   }
 }
 
@@ -881,6 +897,11 @@ constexpr Shape kCompressLds[kNumShapes] = {{4, 1, 1, 1, 1}, {4, 1, 1, 1, 2}, {4
                                             {2, 1, 2, 1, 1}, {4, 2, 1, 1, 1}, {2, 1, 1, 1, 1}, {1, 4, 1, 1, 1}};
 constexpr Shape kExpandLds[kNumShapes] = {{1, 4, 1, 1, 1}, {1, 4, 1, 1, 2}, {2, 2, 1, 1, 1}, {1, 4, 1, 2, 1},
                                           {2, 4, 1, 1, 1}, {1, 2, 1, 2, 1}, {1, 2, 1, 1, 1}, {2, 2, 1, 2, 1}};
+// 16-bit LDS-staged forms (16 x 16 MFMA tiles)
+constexpr Shape kCompressLds16[kNumShapes] = {{4, 1, 2, 4, 1}, {2, 2, 4, 2, 1}, {2, 1, 4, 2, 1}, {4, 1, 2, 2, 1},
+                                              {2, 1, 4, 4, 1}, {4, 2, 2, 2, 1}, {1, 4, 8, 2, 1}, {4, 1, 2, 2, 2}};
+constexpr Shape kExpandLds16[kNumShapes] = {{2, 2, 2, 2, 1}, {1, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 4, 2, 2, 1},
+                                            {1, 4, 2, 4, 1}, {1, 2, 2, 4, 1}, {1, 4, 2, 2, 2}, {2, 2, 2, 4, 1}};
 constexpr Shape kCompressGeneral = {4, 1, 2, 2, 3};
 constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
 
@@ -891,14 +912,20 @@ bool compress_uniform(const CompressArgs& a, Store st) {
   return (2 * a.P) % kb == 0 && a.kchunk % kb == 0 && (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB &&
          (size_t)a.M * a.KD * esz < kOOB;
 }
+// k-tile elements of the LDS-staged forms: one 128-byte line per row
+int staged_ktile(Store st) { return st == Store::F32 ? 32 : 64; }
 bool compress_staged(const CompressArgs& a, Store st) {
-  return st == Store::F32 && (2 * a.P) % 32 == 0 && a.kchunk % 32 == 0 && compress_uniform(a, st);
+  const int kt = staged_ktile(st);
+  return (2 * a.P) % kt == 0 && a.kchunk % kt == 0 && compress_uniform(a, st);
 }
+bool expand_staged(const ExpandArgs& a, Store st);
 bool expand_uniform(const ExpandArgs& a, Store st) {
   const int kb = st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB;
   const size_t esz = st == Store::F32 ? 4 : 2;
   return a.KD % kb == 0 && (size_t)a.M * a.KD * esz < kOOB && (size_t)a.N * a.KD * esz < kOOB;
 }
+
+bool expand_staged(const ExpandArgs& a, Store st) { return a.KD % staged_ktile(st) == 0 && expand_uniform(a, st); }
 
 int tiles(int n, int t) { return (n + t - 1) / t; }
 
@@ -906,9 +933,10 @@ template <int V, Store ST>
 void launch_compress_v(hipStream_t s, const CompressArgs& a) {
   const int rest = a.B * a.np * a.ksplit;
   if (compress_staged(a, ST)) {
-    constexpr Shape S = kCompressLds[V];
-    const dim3 grid(tiles(a.N, S.wn * S.nt * 32) * tiles(a.M, S.wm * S.mt * 32) * rest);
-    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    constexpr Shape S = ST == Store::F32 ? kCompressLds[V] : kCompressLds16[V];
+    constexpr int T = Geo<ST>::T;
+    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
+    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
   } else if (compress_uniform(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kCompress32[V] : kCompress16[V];
     constexpr int T = Geo<ST>::T;
@@ -923,10 +951,11 @@ void launch_compress_v(hipStream_t s, const CompressArgs& a) {
 template <int V, Store ST>
 void launch_expand_v(hipStream_t s, const ExpandArgs& a) {
   const int rest = a.B * a.np;
-  if (ST == Store::F32 && a.KD % 32 == 0 && expand_uniform(a, ST)) {
-    constexpr Shape S = kExpandLds[V];
-    const dim3 grid(tiles(a.N, S.wn * S.nt * 32) * tiles(a.M, S.wm * S.mt * 32) * rest);
-    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+  if (expand_staged(a, ST)) {
+    constexpr Shape S = ST == Store::F32 ? kExpandLds[V] : kExpandLds16[V];
+    constexpr int T = Geo<ST>::T;
+    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
+    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
   } else if (expand_uniform(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kExpand32[V] : kExpand16[V];
     constexpr int T = Geo<ST>::T;
@@ -999,7 +1028,8 @@ int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* ou
   a.K = pl.K;
   a.B = pl.B;
   a.ksplit = ksplit;
-  const int kb = 32;  // the staged FP32 form takes 32-element k-tiles, the general forms 16 or 32
+  // the staged forms take k-tiles of 32 (FP32) or 64 (16-bit) elements, the others blocks of 16 or 32
+  const int kb = st != Store::F32 && (2 * pl.P) % 64 == 0 ? 64 : 32;
   a.kchunk = ((a.KD + ksplit - 1) / ksplit + kb - 1) / kb * kb;
   a.split_stride = (size_t)pl.B * pl.np * pl.K * ncol;
   switch (st) {
@@ -1017,18 +1047,20 @@ int gemm_compress_variants() { return kNumShapes; }
 int gemm_expand_variants() { return kNumShapes; }
 
 // Defaults: shape 0 of each class (shape 7 for the FP32 compressing contraction
-// when 2K < 64 rows), and a split giving about 1536 (FP32) or 768 (16-bit)
-// work-groups.
+// when 2K < 64 rows), and a split giving about 1536 (FP32) or 640 / 768
+// (16-bit, staged / register-direct) work-groups.
 void default_gemm_config(Plan& pl) {
   for (int c = 0; c < 2; ++c) {
     const Store st = c == 0 ? Store::F32 : Store::BF16;
     Plan::GemmCfg& g = pl.cfg(st);
     g.cvar = (c == 0 && 2 * pl.K < 64) ? 7 : 0;
     g.evar = 0;
-    const Shape S = c == 0 ? ((2 * pl.P) % 32 == 0 ? kCompressLds[g.cvar] : kCompress32[g.cvar]) : kCompress16[g.cvar];
+    const Shape S = c == 0 ? ((2 * pl.P) % 32 == 0 ? kCompressLds[g.cvar] : kCompress32[g.cvar])
+                           : ((2 * pl.P) % 64 == 0 ? kCompressLds16[g.cvar] : kCompress16[g.cvar]);
     const int T = c == 0 ? 32 : 16;
     const long t = (long)tiles(pl.ny, S.wn * S.nt * T) * tiles(2 * pl.K, S.wm * S.mt * T) * pl.B * pl.np;
-    const long target = c == 0 ? 1536 : 768;  // work-groups: measured best on the 224 x 224, 32-coil slice
+    // work-groups: measured best on the 224 x 224, 32-coil slice
+    const long target = c == 0 ? 1536 : (2 * pl.P) % 64 == 0 ? 640 : 768;
     int ks = (int)std::max<long>(1, (target + t - 1) / t);
     ks = std::min(std::min(ks, std::max(1, 2 * pl.ns / 128)), kMaxKsplit);
     g.ksplit = ks;

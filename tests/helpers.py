@@ -39,10 +39,19 @@ def periodic_slice(seed=0):
     return dataclasses.replace(sl, geom=g)
 
 
+def wide_slice(seed=0):
+    """96 x 80, 4 coils, os 2 (192 samples), 6 patches of 32, K = 20: 2P = 64
+    is a whole k-tile of the 16-bit LDS-staged contractions (and two of the
+    FP32 ones), with ragged 2K = 40 and Ny = 80."""
+    return synth._make_rect(seed, nx=96, ny=80, nc=4, os_=2, patch_len=32, k=20, accel=3, acs=6,
+                            cycles=2, phase_max=2.0)
+
+
 CASES = {
     "small": lambda: synth.small_slice(0),
     "rect": lambda: rect_slice(0),
     "periodic": lambda: periodic_slice(0),
+    "wide": lambda: wide_slice(0),
 }
 
 
