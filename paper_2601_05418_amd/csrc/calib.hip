@@ -189,21 +189,21 @@ __global__ void k_calib_tables(const float2* __restrict__ psf, const int* __rest
 // Gram, separated form (see the header).
 // k_gram_q: Q[(n nc + m)][iy][dd] = sum_ix wc cw_n conj(cw_m) ph[dd][ix].
 // Work-group: one row iy, one coil n and a chunk of kQO * 256 outputs (m, dd);
-// pixels are staged kQX at a time in LDS (all coils' maps, the weighted map of
-// coil n, the phase rows).
+// pixels are staged qx at a time in LDS (all coils' maps, the weighted map of
+// coil n, the phase rows), qx chosen by the host to fit the LDS budget.
 // ---------------------------------------------------------------------------
-constexpr int kQX = 16;  // pixels per LDS chunk
-constexpr int kQO = 8;   // outputs per thread
+constexpr int kQO = 8;            // outputs per thread
+constexpr size_t kGramLds = 65536;  // LDS budget of the two Gram kernels (bytes)
 
 __global__ __launch_bounds__(256) void k_gram_q(const double2* __restrict__ cw, const double* __restrict__ wc,
                                                 const double2* __restrict__ ph, double2* __restrict__ Q, int nc,
-                                                int nx, int ny, int nd) {
+                                                int nx, int ny, int nd, int qx) {
   const int iy = blockIdx.x, n = blockIdx.y;
   const int npix = nx * ny;
   extern __shared__ double2 smq[];
-  double2* cwm = smq;               // [nc][kQX]
-  double2* an = cwm + nc * kQX;     // [kQX]  wc * cw_n
-  double2* phs = an + kQX;          // [nd][kQX]
+  double2* cwm = smq;              // [nc][qx]
+  double2* an = cwm + nc * qx;     // [qx]  wc * cw_n
+  double2* phs = an + qx;          // [nd][qx]
   const int tid = threadIdx.x;
   const int nout = nc * nd;
   int om[kQO], od[kQO];
@@ -218,16 +218,16 @@ __global__ __launch_bounds__(256) void k_gram_q(const double2* __restrict__ cw, 
     acc[q] = make_double2(0.0, 0.0);
   }
   const size_t rowpix = (size_t)iy * nx;
-  for (int x0 = 0; x0 < nx; x0 += kQX) {
-    const int nxc = min(kQX, nx - x0);
-    for (int i = tid; i < nc * kQX; i += 256) {
-      const int m = i / kQX, x = i - m * kQX;
+  for (int x0 = 0; x0 < nx; x0 += qx) {
+    const int nxc = min(qx, nx - x0);
+    for (int i = tid; i < nc * qx; i += 256) {
+      const int m = i / qx, x = i - m * qx;
       cwm[i] = x < nxc ? cw[(size_t)m * npix + rowpix + x0 + x] : make_double2(0.0, 0.0);
     }
-    for (int x = tid; x < kQX; x += 256)
+    for (int x = tid; x < qx; x += 256)
       an[x] = x < nxc ? zscale(cw[(size_t)n * npix + rowpix + x0 + x], wc[rowpix + x0 + x]) : make_double2(0.0, 0.0);
-    for (int i = tid; i < nd * kQX; i += 256) {
-      const int dd = i / kQX, x = i - dd * kQX;
+    for (int i = tid; i < nd * qx; i += 256) {
+      const int dd = i / qx, x = i - dd * qx;
       phs[i] = x < nxc ? ph[(size_t)dd * nx + x0 + x] : make_double2(0.0, 0.0);
     }
     __syncthreads();
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_gram_q(const double2* __restrict__ cw, 
       const double2 a = an[x];
 #pragma unroll
       for (int q = 0; q < kQO; ++q)
-        if (ok[q]) acc[q] = zadd(acc[q], zmul(zmulc(a, cwm[om[q] * kQX + x]), phs[od[q] * kQX + x]));
+        if (ok[q]) acc[q] = zadd(acc[q], zmul(zmulc(a, cwm[om[q] * qx + x]), phs[od[q] * qx + x]));
     }
     __syncthreads();
   }
@@ -246,23 +246,22 @@ __global__ __launch_bounds__(256) void k_gram_q(const double2* __restrict__ cw, 
 
 // k_gram_assemble: the block (n, m), m >= n, of P_g; the block (m, n) is its
 // conjugate transpose.  Work-group: one coil pair, one group and a tile of
-// 4 * 256 outputs (j, k); rows iy are staged kAY at a time in LDS (the
+// 4 * 256 outputs (j, k); rows iy are staged ay at a time in LDS (the
 // q-weighted PSF samples of the patch, the plain ones, and Q_nm).
-constexpr int kAY = 16;  // rows per LDS chunk
-constexpr int kAO = 4;   // outputs per thread
+constexpr int kAO = 4;  // outputs per thread
 
 __global__ __launch_bounds__(256) void k_gram_assemble(const double2* __restrict__ Q, const float2* __restrict__ psf,
                                                        const double* __restrict__ qinv, const int* __restrict__ t0s,
                                                        double2* __restrict__ H, int nc, int P, int ny, int nt, int nsp,
-                                                       int ntile) {
+                                                       int ntile, int ay) {
   const int n = blockIdx.x, m = blockIdx.y;
   if (m < n) return;
   const int g = blockIdx.z / ntile, tile = blockIdx.z - g * ntile;
   const int nd = 2 * P - 1, t0 = t0s[g];
   extern __shared__ double2 sma[];
-  double2* pj = sma;                // [kAY][P]  q_g(iy) psf[iy][t0 + j]
-  double2* pk = pj + kAY * P;       // [kAY][P]  psf[iy][t0 + k]
-  double2* qs = pk + kAY * P;       // [kAY][nd] Q_nm(iy, .)
+  double2* pj = sma;             // [ay][P]  q_g(iy) psf[iy][t0 + j]
+  double2* pk = pj + ay * P;     // [ay][P]  psf[iy][t0 + k]
+  double2* qs = pk + ay * P;     // [ay][nd] Q_nm(iy, .)
   const int tid = threadIdx.x;
   int oj[kAO], ok_[kAO];
   bool ok[kAO];
@@ -277,9 +276,9 @@ __global__ __launch_bounds__(256) void k_gram_assemble(const double2* __restrict
   }
   const double2* Qnm = Q + ((size_t)n * nc + m) * ny * nd;
   const double* qg = qinv + (size_t)g * ny;
-  for (int y0 = 0; y0 < ny; y0 += kAY) {
-    const int nyc = min(kAY, ny - y0);
-    for (int i = tid; i < kAY * P; i += 256) {
+  for (int y0 = 0; y0 < ny; y0 += ay) {
+    const int nyc = min(ay, ny - y0);
+    for (int i = tid; i < ay * P; i += 256) {
       const int r = i / P, j = i - r * P;
       double2 a = make_double2(0.0, 0.0), b = a;
       if (r < nyc) {
@@ -290,7 +289,7 @@ __global__ __launch_bounds__(256) void k_gram_assemble(const double2* __restrict
       pj[i] = a;
       pk[i] = b;
     }
-    for (int i = tid; i < kAY * nd; i += 256) {
+    for (int i = tid; i < ay * nd; i += 256) {
       const int r = i / nd, dd = i - r * nd;
       qs[i] = r < nyc ? Qnm[(size_t)(y0 + r) * nd + dd] : make_double2(0.0, 0.0);
     }
@@ -782,17 +781,18 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
   {
     const int nout = pl.nc * nd;
     const dim3 gq(pl.ny, pl.nc, (nout + kQO * 256 - 1) / (kQO * 256));
-    const size_t lq = sizeof(double2) * (size_t)(pl.nc + 1 + nd) * kQX;
-    const size_t la_need = sizeof(double2) * (size_t)(2 * P + nd) * kAY;
-    if (lq > 65536 || la_need > 65536)
-      return fail(GPJC_E_UNSUPPORTED, "calibration: coils + 2 x patch length, or 4 x patch length, above 256");
-    hipLaunchKernelGGL(k_gram_q, gq, dim3(256), lq, st, cw, wc, ph, Qg, pl.nc, pl.nx, pl.ny, nd);
+    // pixels / rows per LDS chunk: 16, fewer when the staged rows would not fit
+    const size_t qrow = sizeof(double2) * (size_t)(pl.nc + 1 + nd), arow = sizeof(double2) * (size_t)(2 * P + nd);
+    const int qx = (int)std::min<size_t>(16, kGramLds / qrow), ay = (int)std::min<size_t>(16, kGramLds / arow);
+    if (qx < 1 || ay < 1) return fail(GPJC_E_UNSUPPORTED, "calibration: coil count or patch length too large");
+    const size_t lq = qrow * qx;
+    hipLaunchKernelGGL(k_gram_q, gq, dim3(256), lq, st, cw, wc, ph, Qg, pl.nc, pl.nx, pl.ny, nd, qx);
     GPJC_HIP(hipGetLastError());
     const int ntile = (P * P + kAO * 256 - 1) / (kAO * 256);
     const dim3 ga(pl.nc, pl.nc, G * ntile);
-    const size_t la = sizeof(double2) * (size_t)(2 * P + nd) * kAY;
+    const size_t la = arow * ay;
     hipLaunchKernelGGL(k_gram_assemble, ga, dim3(256), la, st, Qg, pl.psf, qinv, t0s, H, pl.nc, P, pl.ny, pl.nt, nsp,
-                       ntile);
+                       ntile, ay);
     GPJC_HIP(hipGetLastError());
   }
 

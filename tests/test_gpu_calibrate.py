@@ -130,3 +130,13 @@ def test_calibrate_ns512_decayed_couplings(gpu_lib):
     plan, eig, bank, a_ref, lam_ref, groups = calibrate_both(sl, groups=[0, 3, 7])
     assert np.allclose(eig.sum(axis=1), 64 * 64, rtol=1e-11)
     check_bank(eig, bank, a_ref, lam_ref, sl.geom.k)
+
+
+def test_calibrate_long_patches(gpu_lib):
+    """P = 96 (Ns = 192): the separated Gram stages fewer than 16 rows per LDS
+    chunk (10 here, 32 rows leave a ragged last chunk), and 2P - 1 = 191
+    phase offsets."""
+    sl = H.rounded_slice(synth._make_rect(0, nx=48, ny=32, nc=2, os_=4, patch_len=96, k=8, accel=2, acs=4,
+                                          cycles=2, phase_max=2.0))
+    plan, eig, bank, a_ref, lam_ref, _ = calibrate_both(sl)
+    check_bank(eig, bank, a_ref, lam_ref, sl.geom.k)
