@@ -573,7 +573,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
 // prefetched into registers while the current one is multiplied.  Row
 // stride 36 floats (144 bytes, an odd multiple of 16): the 16-byte fragment
 // reads of one pass fall on distinct bank groups.  Needs 2P a multiple of the
-// k-tile (a k-tile never crosses a coil) and the k-split chunk a multiple of it.
+// 16-byte chunk (a chunk never crosses a coil) and the k-split chunk a
+// multiple of the k-tile.
 // ---------------------------------------------------------------------------
 template <int WM, int WN, int MT, int NT, int PF, Store ST>
 __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
@@ -612,33 +613,40 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 
   const int kbeg = ks * a.kchunk;
   const int kend = min(a.KD, kbeg + a.kchunk);
-  const int nst = max(0, (kend - kbeg) / KT);
-  int n = kbeg / twoP;
-  int jj = kbeg - n * twoP;
-  const int c16 = tid & 7;  // 16-byte chunk of a row handled by this thread
+  const int nst = max(0, (kend - kbeg + KT - 1) / KT);
+  // This thread's 16-byte chunk along the contraction: element kk of the
+  // (coil, in-patch sample) index, i.e. coil nn, sample jj.  A chunk never
+  // straddles a coil (2P is a multiple of the chunk); k-tiles may, so the
+  // coil advance is per thread.  Chunks at or past kend read zeros.
+  const int c16 = tid & 7;
+  int kk = kbeg + (KT / 8) * c16;
+  int jj = kk % twoP;
+  const int nn = kk / twoP;
   uint32_t va[AR], vb[BR];
 #pragma unroll
   for (int r = 0; r < AR; ++r) {
     const int row = tm * TM + (tid >> 3) + r * (NTHR / 8);
-    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + kbeg + (KT / 8) * c16) * ES) : kOOB;
+    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + kk) * ES) : kOOB;
   }
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
-    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)n * cstride + jj + (KT / 8) * c16) * ES) : kOOB;
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)nn * cstride + jj) * ES) : kOOB;
   }
-  const uint32_t wrap = (uint32_t)((cstride - (size_t)(twoP - KT)) * ES);
+  const uint32_t wrap = (uint32_t)((cstride - (size_t)twoP) * ES);  // end of a coil's patch -> next coil's
   floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
   auto fetch = [&](floatx4(&xa)[AR], floatx4(&xb)[BR]) {
+    const bool in = kk < kend;
 #pragma unroll
-    for (int r = 0; r < AR; ++r) xa[r] = bload(rA, va[r]);
+    for (int r = 0; r < AR; ++r) xa[r] = bload(rA, in ? va[r] : kOOB);
 #pragma unroll
-    for (int r = 0; r < BR; ++r) xb[r] = bload(rB, vb[r]);
+    for (int r = 0; r < BR; ++r) xb[r] = bload(rB, in ? vb[r] : kOOB);
+    kk += KT;
     jj += KT;
     uint32_t inc = KT * ES;
-    if (jj == twoP) {
-      jj = 0;
-      inc = wrap;
+    while (jj >= twoP) {
+      jj -= twoP;
+      inc += wrap;
     }
 #pragma unroll
     for (int r = 0; r < AR; ++r) va[r] += KT * ES;
@@ -915,8 +923,9 @@ bool compress_uniform(const CompressArgs& a, Store st) {
 // k-tile elements of the LDS-staged forms: one 128-byte line per row
 int staged_ktile(Store st) { return st == Store::F32 ? 32 : 64; }
 bool compress_staged(const CompressArgs& a, Store st) {
-  const int kt = staged_ktile(st);
-  return (2 * a.P) % kt == 0 && a.kchunk % kt == 0 && compress_uniform(a, st);
+  const size_t esz = st == Store::F32 ? 4 : 2;
+  return (2 * a.P) % (int)(16 / esz) == 0 && a.kchunk % staged_ktile(st) == 0 &&
+         (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB && (size_t)a.M * a.KD * esz < kOOB;
 }
 bool expand_staged(const ExpandArgs& a, Store st);
 bool expand_uniform(const ExpandArgs& a, Store st) {
@@ -1028,8 +1037,8 @@ int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* ou
   a.K = pl.K;
   a.B = pl.B;
   a.ksplit = ksplit;
-  // the staged forms take k-tiles of 32 (FP32) or 64 (16-bit) elements, the others blocks of 16 or 32
-  const int kb = st != Store::F32 && (2 * pl.P) % 64 == 0 ? 64 : 32;
+  // the staged forms take k-tiles of 32 (FP32) or 64 (16-bit) elements
+  const int kb = st == Store::F32 ? 32 : 64;
   a.kchunk = ((a.KD + ksplit - 1) / ksplit + kb - 1) / kb * kb;
   a.split_stride = (size_t)pl.B * pl.np * pl.K * ncol;
   switch (st) {
@@ -1047,20 +1056,19 @@ int gemm_compress_variants() { return kNumShapes; }
 int gemm_expand_variants() { return kNumShapes; }
 
 // Defaults: shape 0 of each class (shape 7 for the FP32 compressing contraction
-// when 2K < 64 rows), and a split giving about 1536 (FP32) or 640 / 768
-// (16-bit, staged / register-direct) work-groups.
+// when 2K < 64 rows), and a split giving about 1536 (FP32) or 640 (16-bit)
+// work-groups.
 void default_gemm_config(Plan& pl) {
   for (int c = 0; c < 2; ++c) {
     const Store st = c == 0 ? Store::F32 : Store::BF16;
     Plan::GemmCfg& g = pl.cfg(st);
     g.cvar = (c == 0 && 2 * pl.K < 64) ? 7 : 0;
     g.evar = 0;
-    const Shape S = c == 0 ? ((2 * pl.P) % 32 == 0 ? kCompressLds[g.cvar] : kCompress32[g.cvar])
-                           : ((2 * pl.P) % 64 == 0 ? kCompressLds16[g.cvar] : kCompress16[g.cvar]);
+    const Shape S = c == 0 ? kCompressLds[g.cvar] : kCompressLds16[g.cvar];  // the staged forms take every even P
     const int T = c == 0 ? 32 : 16;
     const long t = (long)tiles(pl.ny, S.wn * S.nt * T) * tiles(2 * pl.K, S.wm * S.mt * T) * pl.B * pl.np;
     // work-groups: measured best on the 224 x 224, 32-coil slice
-    const long target = c == 0 ? 1536 : (2 * pl.P) % 64 == 0 ? 640 : 768;
+    const long target = c == 0 ? 1536 : 640;
     int ks = (int)std::max<long>(1, (target + t - 1) / t);
     ks = std::min(std::min(ks, std::max(1, 2 * pl.ns / 128)), kMaxKsplit);
     g.ksplit = ks;
