@@ -9,15 +9,20 @@
 // are read in their natural interleaved layouts and the contraction index kk
 // is contiguous in memory for both.
 //
-// FP32 (v_mfma_f32_16x16x4_f32): in a block of 16 kk, lane (i, q)
-// (i = lane % 16, q = lane / 16) holds kk = kb + 4q .. kb + 4q + 3 of row i
-// as one float4 and feeds element e to the e-th MFMA; the four MFMAs
-// together cover the 16 kk.
-// BF16 / FP16 (v_mfma_f32_16x16x32_{bf16,f16}): in a block of 32 kk, lane
-// (i, q) holds kk = kb + 8q .. kb + 8q + 7 of row i (16 bytes), one MFMA per
-// block, FP32 accumulation.
-// Either way one 16-byte load per lane and operand tile feeds a block, and
-// loads run a few blocks (the ring depth less one) ahead of the MFMAs.
+// Three families of kernels, chosen per launch:
+// - LDS-staged (k_compress_lds, k_expand_lds): the work-group loads k-tiles of
+//   one 128-byte line per row cooperatively into LDS and the waves read their
+//   MFMA fragments from there; 32x32x2 FP32, or 16x16x32 BF16 / FP16 with FP32
+//   accumulation.  Every geometry of the compressing contraction, and the
+//   expanding one when 2 Kp is a whole number of k-tiles.
+// - Buffer-addressed register-direct (k_expand_u): each lane loads its own
+//   operand fragments, 16 bytes per lane and block, a few blocks ahead.
+// - General (k_compress, k_expand): per-lane addressing with masks, for
+//   operands of 2 GiB or more.  In a block of 16 kk (FP32,
+//   v_mfma_f32_16x16x4_f32) lane (i, q) (i = lane % 16, q = lane / 16) holds
+//   kk = kb + 4q .. kb + 4q + 3 of row i and feeds element e to the e-th MFMA;
+//   in a block of 32 kk (16-bit, v_mfma_f32_16x16x32_*) it holds 8 elements and
+//   feeds one MFMA.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -342,119 +347,6 @@ struct Geo<Store::F32> {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], c, 0, 0, 0);
   }
 };
-
-template <int WM, int WN, int MT, int NT, Store ST, int DEPTH>
-__global__ __launch_bounds__(64 * WM * WN) void k_compress_u(CompressArgs a) {
-  using G = Geo<ST>;
-  using E = typename Mma<ST>::E;
-  constexpr int T = G::T, KB = G::KB, LW = G::LW, NE = G::NE, NR = G::NR;
-  constexpr uint32_t BB = KB * sizeof(E);
-  constexpr int TM = WM * MT * T, TN = WN * NT * T;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane % T, lh = lane / T;
-  const int wm = wave / WN, wn = wave % WN;
-  const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
-  const int total = tiles_n * tiles_m * a.B * a.np * a.ksplit;
-  const int logical = xcd_logical(blockIdx.x, total);
-  const int tn = logical % tiles_n;
-  const int rest = logical / tiles_n;
-  const int tm = rest % tiles_m, z = rest / tiles_m;
-  const int ks = z % a.ksplit, bp = z / a.ksplit;
-  const int b = bp / a.np, p = bp - b * a.np;
-  const int g = a.pgroup[p];
-  const int row0 = tm * TM + wm * MT * T, col0 = tn * TN + wn * NT * T;
-  const int twoP = 2 * a.P;
-  const size_t cstride = (size_t)a.N * a.nt * 2;  // elements between coils
-
-  const E* Ab = static_cast<const E*>(a.A) + (size_t)g * a.M * a.KD;
-  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)a.M * a.KD * sizeof(E)));
-  const E* Bb = static_cast<const E*>(a.in) + (size_t)b * a.nc * cstride + (size_t)p * twoP;
-  const __amdgpu_buffer_rsrc_t rB = make_rsrc(Bb, (uint32_t)((a.nc * cstride - (size_t)p * twoP) * sizeof(E)));
-
-  const int kbeg = ks * a.kchunk;
-  const int kend = min(a.KD, kbeg + a.kchunk);
-  const int nblk = (kend - kbeg) / KB;
-  int n = kbeg / twoP;  // uniform coil and in-patch position of the block
-  int jj = kbeg - n * twoP;
-  uint32_t va[MT], vb[NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int r = row0 + T * m + li;
-    va[m] = r < a.M ? (uint32_t)(((size_t)r * a.KD + kbeg + LW * lh) * sizeof(E)) : kOOB;
-  }
-#pragma unroll
-  for (int c = 0; c < NT; ++c) {
-    const int cc = col0 + T * c + li;
-    vb[c] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)n * cstride + jj + LW * lh) * sizeof(E)) : kOOB;
-  }
-  if (nblk <= 0) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) va[m] |= kOOB;
-#pragma unroll
-    for (int c = 0; c < NT; ++c) vb[c] |= kOOB;
-  }
-  const uint32_t wrap = (uint32_t)((cstride - (size_t)(twoP - KB)) * sizeof(E));
-  int loaded = 0;
-  auto load = [&](floatx4(&xa)[MT], floatx4(&xb)[NT]) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) xa[m] = bload(rA, va[m]);
-#pragma unroll
-    for (int c = 0; c < NT; ++c) xb[c] = bload(rB, vb[c]);
-    jj += KB;
-    uint32_t inc = BB;
-    if (jj == twoP) {
-      jj = 0;
-      inc = wrap;
-    }
-#pragma unroll
-    for (int m = 0; m < MT; ++m) va[m] += BB;
-#pragma unroll
-    for (int c = 0; c < NT; ++c) vb[c] += inc;
-    if (++loaded == nblk) {
-#pragma unroll
-      for (int m = 0; m < MT; ++m) va[m] |= kOOB;
-#pragma unroll
-      for (int c = 0; c < NT; ++c) vb[c] |= kOOB;
-    }
-  };
-  typename G::Acc acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int c = 0; c < NT; ++c)
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
-  floatx4 ra[DEPTH][MT], rb[DEPTH][NT];
-#pragma unroll
-  for (int s = 0; s < DEPTH - 1; ++s) load(ra[s], rb[s]);
-  for (int kb = 0; kb < nblk; kb += DEPTH) {
-#pragma unroll
-    for (int s = 0; s < DEPTH; ++s) {
-      load(ra[(s + DEPTH - 1) % DEPTH], rb[(s + DEPTH - 1) % DEPTH]);
-      if (kb + s < nblk) {  // uniform: the last round may hold fewer than DEPTH blocks
-#pragma unroll
-        for (int e = 0; e < NE; ++e)
-#pragma unroll
-          for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(ra[s][m], rb[s][c], e, acc[m][c]);
-      }
-    }
-  }
-  // rows pair up as (k, re), (k, im); row_of(r, h) is even for even r
-  float2* out = a.out + ks * a.split_stride + ((size_t)b * a.np + p) * a.K * a.N;
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int c = 0; c < NT; ++c) {
-      const int col = col0 + T * c + li;
-#pragma unroll
-      for (int r = 0; r < NR; r += 2) {
-        const int row = row0 + T * m + G::row_of(r, lh);
-        if (col < a.N && row < a.M) out[(size_t)(row >> 1) * a.N + col] = make_float2(acc[m][c][r], acc[m][c][r + 1]);
-      }
-    }
-}
 
 template <int WM, int WN, int MT, int NT, Store ST, int DEPTH>
 __global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
@@ -884,28 +776,23 @@ __global__ void k_expand_bank(const double2* __restrict__ A, BankOut o, int G, i
 }
 
 // Tile-shape tables: waves WM x WN per work-group, wave tile MT x NT MFMA
-// tiles (32 x 32 for the FP32 buffer-addressed forms, 16 x 16 for the 16-bit
-// ones), register-ring depth.  Index 0 is the default of its class.  The
-// general forms (geometries the buffer-addressed ones do not cover) use one
-// fixed shape.
+// tiles, depth.  kCompressLds / kExpandLds: LDS-staged FP32 (32 x 32 tiles,
+// depth = k-tiles of register prefetch); the *16 tables: LDS-staged 16-bit
+// (16 x 16 tiles); kExpand32 / kExpand16: the buffer-addressed register-direct
+// expanding forms (depth = register ring).  Index 0 is the default of its
+// class.  The general forms (operands of 2 GiB or more) use one fixed shape.
 struct Shape {
   int wm, wn, mt, nt, depth;
 };
 constexpr int kNumShapes = 8;
-constexpr Shape kCompress32[kNumShapes] = {{2, 1, 2, 2, 3}, {1, 1, 4, 1, 3}, {2, 1, 2, 1, 3}, {1, 2, 4, 1, 3},
-                                           {2, 2, 2, 1, 3}, {1, 1, 4, 1, 5}, {2, 1, 2, 2, 4}, {1, 4, 1, 1, 3}};
 constexpr Shape kExpand32[kNumShapes] = {{1, 2, 1, 4, 3}, {1, 4, 1, 2, 3}, {1, 2, 2, 2, 3}, {1, 1, 1, 4, 3},
                                          {2, 2, 1, 2, 3}, {1, 2, 1, 4, 4}, {1, 4, 1, 1, 3}, {1, 2, 2, 2, 4}};
-constexpr Shape kCompress16[kNumShapes] = {{2, 1, 4, 4, 3}, {2, 1, 4, 4, 4}, {2, 1, 4, 2, 3}, {4, 1, 2, 2, 3},
-                                           {4, 1, 2, 4, 4}, {2, 2, 2, 2, 3}, {1, 4, 2, 2, 3}, {2, 1, 4, 2, 5}};
 constexpr Shape kExpand16[kNumShapes] = {{1, 2, 4, 4, 4}, {1, 2, 4, 4, 3}, {1, 4, 2, 4, 3}, {2, 2, 4, 2, 3},
                                          {1, 4, 2, 2, 3}, {1, 4, 2, 4, 5}, {2, 2, 2, 4, 3}, {1, 4, 1, 4, 3}};
-// (depth = k-tiles of register prefetch for the LDS-staged forms)
 constexpr Shape kCompressLds[kNumShapes] = {{4, 1, 1, 1, 1}, {4, 1, 1, 1, 2}, {4, 1, 1, 2, 1}, {2, 2, 2, 1, 1},
                                             {2, 1, 2, 1, 1}, {4, 2, 1, 1, 1}, {2, 1, 1, 1, 1}, {1, 4, 1, 1, 1}};
 constexpr Shape kExpandLds[kNumShapes] = {{1, 4, 1, 1, 1}, {1, 4, 1, 1, 2}, {2, 2, 1, 1, 1}, {1, 4, 1, 2, 1},
                                           {2, 4, 1, 1, 1}, {1, 2, 1, 2, 1}, {1, 2, 1, 1, 1}, {2, 2, 1, 2, 1}};
-// 16-bit LDS-staged forms (16 x 16 MFMA tiles)
 constexpr Shape kCompressLds16[kNumShapes] = {{4, 1, 2, 4, 1}, {2, 2, 4, 2, 1}, {2, 1, 4, 2, 1}, {4, 1, 2, 2, 1},
                                               {2, 1, 4, 4, 1}, {4, 2, 2, 2, 1}, {1, 4, 8, 2, 1}, {4, 1, 2, 2, 2}};
 constexpr Shape kExpandLds16[kNumShapes] = {{2, 2, 2, 2, 1}, {1, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 4, 2, 2, 1},
@@ -913,21 +800,14 @@ constexpr Shape kExpandLds16[kNumShapes] = {{2, 2, 2, 2, 1}, {1, 2, 2, 2, 1}, {1
 constexpr Shape kCompressGeneral = {4, 1, 2, 2, 3};
 constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
 
-// Whether the buffer-addressed forms apply (see above).
-bool compress_uniform(const CompressArgs& a, Store st) {
-  const int kb = st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB;
-  const size_t esz = st == Store::F32 ? 4 : 2;
-  return (2 * a.P) % kb == 0 && a.kchunk % kb == 0 && (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB &&
-         (size_t)a.M * a.KD * esz < kOOB;
-}
-// k-tile elements of the LDS-staged forms: one 128-byte line per row
+// Whether the LDS-staged and buffer-addressed forms apply.  The staged forms
+// take k-tiles of one 128-byte line per row.
 int staged_ktile(Store st) { return st == Store::F32 ? 32 : 64; }
 bool compress_staged(const CompressArgs& a, Store st) {
   const size_t esz = st == Store::F32 ? 4 : 2;
   return (2 * a.P) % (int)(16 / esz) == 0 && a.kchunk % staged_ktile(st) == 0 &&
          (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB && (size_t)a.M * a.KD * esz < kOOB;
 }
-bool expand_staged(const ExpandArgs& a, Store st);
 bool expand_uniform(const ExpandArgs& a, Store st) {
   const int kb = st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB;
   const size_t esz = st == Store::F32 ? 4 : 2;
@@ -946,11 +826,6 @@ void launch_compress_v(hipStream_t s, const CompressArgs& a) {
     constexpr int T = Geo<ST>::T;
     const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
     hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
-  } else if (compress_uniform(a, ST)) {
-    constexpr Shape S = ST == Store::F32 ? kCompress32[V] : kCompress16[V];
-    constexpr int T = Geo<ST>::T;
-    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
-    hipLaunchKernelGGL((k_compress_u<S.wm, S.wn, S.mt, S.nt, ST, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
   } else {
     constexpr Shape S = kCompressGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
