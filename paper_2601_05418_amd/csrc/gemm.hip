@@ -794,7 +794,7 @@ constexpr Shape kCompressLds[kNumShapes] = {{4, 1, 1, 1, 1}, {4, 1, 1, 1, 2}, {4
 constexpr Shape kExpandLds[kNumShapes] = {{1, 4, 1, 1, 1}, {1, 4, 1, 1, 2}, {2, 2, 1, 1, 1}, {1, 4, 1, 2, 1},
                                           {2, 4, 1, 1, 1}, {1, 2, 1, 2, 1}, {1, 2, 1, 1, 1}, {2, 2, 1, 2, 1}};
 constexpr Shape kCompressLds16[kNumShapes] = {{4, 1, 2, 4, 1}, {2, 2, 4, 2, 1}, {2, 1, 4, 2, 1}, {4, 1, 2, 2, 1},
-                                              {2, 1, 4, 4, 1}, {4, 2, 2, 2, 1}, {1, 4, 8, 2, 1}, {4, 1, 2, 2, 2}};
+                                              {2, 1, 4, 4, 1}, {4, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 2, 2, 2, 1}};
 constexpr Shape kExpandLds16[kNumShapes] = {{2, 2, 2, 2, 1}, {1, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 4, 2, 2, 1},
                                             {1, 4, 2, 4, 1}, {1, 2, 2, 4, 1}, {1, 4, 2, 2, 2}, {2, 2, 2, 4, 1}};
 constexpr Shape kCompressGeneral = {4, 1, 2, 2, 3};
@@ -930,14 +930,23 @@ int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* ou
 int gemm_compress_variants() { return kNumShapes; }
 int gemm_expand_variants() { return kNumShapes; }
 
-// Defaults: shape 0 of each class (shape 7 for the FP32 compressing contraction
-// when 2K < 64 rows), and a split giving about 1536 (FP32) or 640 (16-bit)
-// work-groups.
+// Defaults: for the compressing contraction the work-group shape with the
+// tallest row tile (128, 64 or 32 of the 2K rows) that pads at most 1/8 of its
+// rows, for the expanding one shape 0; and a split giving about 1536 (FP32) or
+// 640 (16-bit) work-groups.
+int compress_shape_for_rows(int rows, bool f32) {
+  const int order[3] = {0, f32 ? 6 : 7, f32 ? 7 : 6}, tile[3] = {128, 64, 32};
+  for (int i = 0; i < 3; ++i) {
+    const int padded = (rows + tile[i] - 1) / tile[i] * tile[i];
+    if (8 * (padded - rows) <= padded) return order[i];
+  }
+  return order[2];
+}
 void default_gemm_config(Plan& pl) {
   for (int c = 0; c < 2; ++c) {
     const Store st = c == 0 ? Store::F32 : Store::BF16;
     Plan::GemmCfg& g = pl.cfg(st);
-    g.cvar = (c == 0 && 2 * pl.K < 64) ? 7 : 0;
+    g.cvar = compress_shape_for_rows(2 * pl.K, c == 0);
     g.evar = 0;
     const Shape S = c == 0 ? kCompressLds[g.cvar] : kCompressLds16[g.cvar];  // the staged forms take every even P
     const int T = c == 0 ? 32 : 16;
