@@ -74,6 +74,8 @@ static int validate_geom(const gpjc_geom* g) {
   int ms = 0;
   for (int i = 0; i < g->ny; ++i) ms += g->mask[i] != 0;
   if (ms == 0) return fail(GPJC_E_INVAL, "mask selects no phase-encode line");
+  if ((long)g->os * g->nx > (1L << 20) || (long)g->nc * g->ny * g->nx > (1L << 30))
+    return fail(GPJC_E_INVAL, "os * nx or nc * ny * nx out of range");
   if (g->compressed) {
     const int nt = g->os * g->nx;
     if (g->patch_len < 1 || nt % g->patch_len)
