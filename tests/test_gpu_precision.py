@@ -48,13 +48,13 @@ def make(case):
     return sl, a, plan
 
 
-def check(name, out, ref, model, prec, bound=True):
+def check(name, out, ref, model, prec, bound=True, ratio=0.2):
     e, m = H.rel_l2(out, ref), H.rel_l2(out, model)
     print(f"{name} {prec}: rel_l2 vs FP64 {e:.3e}, vs rounding model {m:.3e}", flush=True)
     if bound:
         assert e <= BOUND[prec]
     assert m <= MODEL[prec]
-    assert m <= 0.2 * e  # the model explains the error
+    assert m <= ratio * e  # the model explains the error
 
 
 # The per-application bounds are the targets for the C1-shaped precision
@@ -139,3 +139,24 @@ def test_refined_cg_reaches_least_squares_solution(gpu_lib, prec):
     assert er <= H.NRMSE_RECON
     if prec == "bf16":
         assert en > 3 * H.NRMSE_RECON  # without refreshes the BF16 operator error remains
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_highfield_reduced_precision_full_size(gpu_lib, prec):
+    """224 x 224, 32 coils, 1344 samples, 42 groups, K = 64: the 16-bit
+    normal operator in the launch configuration the benchmark uses, against
+    the rounding model and the FP64 oracle (random orthonormal bank).  At this
+    size the FP32 stages' own rounding (about 1e-6 relative after the 1344-point
+    readout transforms and 2048-term contractions) moves about 2e-3 of the
+    FP16 entries across a rounding boundary, so the GPU sits about 2-3e-5 from
+    the FP16 model, 0.2-0.25 of the raw error; the model must still explain
+    70% of it."""
+    sl = H.rounded_slice(synth.highfield_slice(0))
+    g = sl.geom
+    a = H.random_bank(g, seed=7)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    mod = H.rounded_ops(sl, a, prec)
+    x = H.round64(sl.image)
+    check("normal", host(plan.normal(dev(x[None]), prec=prec))[0], ops["nrm"](x), mod["nrm"](x), prec, ratio=0.3)
