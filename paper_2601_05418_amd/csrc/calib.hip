@@ -201,9 +201,10 @@ __global__ __launch_bounds__(256) void k_gram_q(const double2* __restrict__ cw, 
   const int iy = blockIdx.x, n = blockIdx.y;
   const int npix = nx * ny;
   extern __shared__ double2 smq[];
-  double2* cwm = smq;              // [nc][qx]
-  double2* an = cwm + nc * qx;     // [qx]  wc * cw_n
-  double2* phs = an + qx;          // [nd][qx]
+  const int qs = qx + 1;           // LDS row stride: an odd number of 16-byte slots, so rows fall on distinct banks
+  double2* cwm = smq;              // [nc][qs]
+  double2* an = cwm + nc * qs;     // [qx]  wc * cw_n
+  double2* phs = an + qx;          // [nd][qs]
   const int tid = threadIdx.x;
   const int nout = nc * nd;
   int om[kQO], od[kQO];
@@ -222,20 +223,20 @@ __global__ __launch_bounds__(256) void k_gram_q(const double2* __restrict__ cw, 
     const int nxc = min(qx, nx - x0);
     for (int i = tid; i < nc * qx; i += 256) {
       const int m = i / qx, x = i - m * qx;
-      cwm[i] = x < nxc ? cw[(size_t)m * npix + rowpix + x0 + x] : make_double2(0.0, 0.0);
+      cwm[m * qs + x] = x < nxc ? cw[(size_t)m * npix + rowpix + x0 + x] : make_double2(0.0, 0.0);
     }
     for (int x = tid; x < qx; x += 256)
       an[x] = x < nxc ? zscale(cw[(size_t)n * npix + rowpix + x0 + x], wc[rowpix + x0 + x]) : make_double2(0.0, 0.0);
     for (int i = tid; i < nd * qx; i += 256) {
       const int dd = i / qx, x = i - dd * qx;
-      phs[i] = x < nxc ? ph[(size_t)dd * nx + x0 + x] : make_double2(0.0, 0.0);
+      phs[dd * qs + x] = x < nxc ? ph[(size_t)dd * nx + x0 + x] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     for (int x = 0; x < nxc; ++x) {
       const double2 a = an[x];
 #pragma unroll
       for (int q = 0; q < kQO; ++q)
-        if (ok[q]) acc[q] = zadd(acc[q], zmul(zmulc(a, cwm[om[q] * qx + x]), phs[od[q] * qx + x]));
+        if (ok[q]) acc[q] = zadd(acc[q], zmul(zmulc(a, cwm[om[q] * qs + x]), phs[od[q] * qs + x]));
     }
     __syncthreads();
   }
@@ -782,10 +783,11 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
     const int nout = pl.nc * nd;
     const dim3 gq(pl.ny, pl.nc, (nout + kQO * 256 - 1) / (kQO * 256));
     // pixels / rows per LDS chunk: 16, fewer when the staged rows would not fit
+    // LDS of k_gram_q: (nc + nd) rows of qx + 1 slots and one row of qx
     const size_t qrow = sizeof(double2) * (size_t)(pl.nc + 1 + nd), arow = sizeof(double2) * (size_t)(2 * P + nd);
-    const int qx = (int)std::min<size_t>(16, kGramLds / qrow), ay = (int)std::min<size_t>(16, kGramLds / arow);
+    const int qx = (int)std::min<size_t>(16, kGramLds / qrow - 1), ay = (int)std::min<size_t>(16, kGramLds / arow);
     if (qx < 1 || ay < 1) return fail(GPJC_E_UNSUPPORTED, "calibration: coil count or patch length too large");
-    const size_t lq = qrow * qx;
+    const size_t lq = qrow * (qx + 1);
     hipLaunchKernelGGL(k_gram_q, gq, dim3(256), lq, st, cw, wc, ph, Qg, pl.nc, pl.nx, pl.ny, nd, qx);
     GPJC_HIP(hipGetLastError());
     const int ntile = (P * P + kAO * 256 - 1) / (kAO * 256);
