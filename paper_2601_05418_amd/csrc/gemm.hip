@@ -4,17 +4,25 @@
 //   compress  Z_p[k][y]          = sum_{n,j} A_g[k][n][j] W[n][y][p P + j]
 //   expand    W[n][y][p P + j]   = sum_k conj(A_g[k][n][j]) Z_p[k][y]
 //
-// A complex product is one real product of the expanded matrix
-// [[Ar, -Ai], [Ai, Ar]] with interleaved (re, im) columns, so both operands
-// are read in their natural interleaved layouts and the contraction index kk
-// is contiguous in memory for both.
+// Both operands are read in their natural interleaved (re, im) layouts, so
+// the contraction index kk is contiguous in memory for both.  The bank is
+// stored in expanded real form, rows [Ar, -Ai] and [Ai, Ar] interleaved per
+// complex row (compressing) and [Ar, Ai], [-Ai, Ar] per complex column
+// (expanding).  Two ways of forming the complex product:
+// - expanded: one real product with the expanded bank, four real
+//   multiplications per complex one (16-bit types, register-direct and
+//   general forms);
+// - three-multiplication (FP32 LDS-staged forms): only the first expanded
+//   row of each pair is read, conj(A) (compressing) or A (expanding), and
+//   three real products t1, t2, t3 are combined at the end (block_mma).
 //
 // Three families of kernels, chosen per launch:
 // - LDS-staged (k_compress_lds, k_expand_lds): the work-group loads k-tiles of
 //   one 128-byte line per row cooperatively into LDS and the waves read their
-//   MFMA fragments from there; 32x32x2 FP32, or 16x16x32 BF16 / FP16 with FP32
-//   accumulation.  Every geometry of the compressing contraction, and the
-//   expanding one when 2 Kp is a whole number of k-tiles.
+//   MFMA fragments from there; 32x32x2 FP32 in the three-multiplication form,
+//   or 16x16x32 BF16 / FP16 with FP32 accumulation.  Every geometry of the
+//   compressing contraction, and the expanding one when 2 Kp is a whole
+//   number of k-tiles.
 // - Buffer-addressed register-direct (k_expand_u): each lane loads its own
 //   operand fragments, 16 bytes per lane and block, a few blocks ahead.
 // - General (k_compress, k_expand): per-lane addressing with masks, for
@@ -468,13 +476,56 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
 // 16-byte chunk (a chunk never crosses a coil) and the k-split chunk a
 // multiple of the k-tile.
 // ---------------------------------------------------------------------------
+// One MFMA block of a wave's k-tile product: row fragments fa[MT] and
+// column fragments fb[NT] into acc.  In FP32 each fragment holds two
+// interleaved complex elements and the block is the three-multiplication
+// complex product conj(X) Y, X being the bank operand (the rows when XR):
+//   t1 += Xr Yr,  t2 += Xi Yi,  t3 += (Xr - Xi)(Yr + Yi),
+// from which re = t1 + t2 and im = t3 - t1 + t2.  It takes three real
+// products where the expanded 2 x 2 block form takes four.  The 16-bit types
+// take the expanded form, one MFMA per block.
+template <Store ST, bool XR, int MT, int NT, int NA>
+__device__ inline void block_mma(const floatx4 (&fa)[MT], const floatx4 (&fb)[NT],
+                                 typename Geo<ST>::Acc (&acc)[NA][MT][NT]) {
+  if constexpr (ST == Store::F32) {
+    static_assert(NA == 3, "three accumulators per tile");
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float sa[MT], sb[NT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) sa[m] = XR ? fa[m][2 * h] - fa[m][2 * h + 1] : fa[m][2 * h] + fa[m][2 * h + 1];
+#pragma unroll
+      for (int c = 0; c < NT; ++c) sb[c] = XR ? fb[c][2 * h] + fb[c][2 * h + 1] : fb[c][2 * h] - fb[c][2 * h + 1];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+          acc[0][m][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][2 * h], fb[c][2 * h], acc[0][m][c], 0, 0, 0);
+          acc[1][m][c] =
+              __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][2 * h + 1], fb[c][2 * h + 1], acc[1][m][c], 0, 0, 0);
+          acc[2][m][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[m], sb[c], acc[2][m][c], 0, 0, 0);
+        }
+    }
+  } else {
+    static_assert(NA == 1, "one accumulator per tile");
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int c = 0; c < NT; ++c) acc[0][m][c] = Geo<ST>::step(fa[m], fb[c], 0, acc[0][m][c]);
+  }
+}
+
 template <int WM, int WN, int MT, int NT, int PF, Store ST>
 __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   using G = Geo<ST>;
   using E = typename Mma<ST>::E;
-  constexpr int T = G::T, NR = G::NR, NE = G::NE;
+  constexpr int T = G::T, NR = G::NR;
   constexpr int ES = (int)sizeof(E);
   constexpr int KT = 128 / ES, LS = 36;  // k-tile elements per row; LDS row stride in floats
+  // FP32 takes the three-multiplication form: a.M counts complex rows k, and
+  // row k is bank row 2k, conj(A_g[k]) interleaved.
+  constexpr bool C3 = ST == Store::F32;
+  constexpr int RS = C3 ? 2 : 1, NA = C3 ? 3 : 1;  // bank rows per kernel row; accumulators per tile
   constexpr int JB = 128 / (G::KB * ES), JF = G::KB * ES / 4;  // MFMA blocks per k-tile, floats per block
   constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
   constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;  // 16-byte chunks per thread per k-tile
@@ -498,8 +549,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   const int twoP = 2 * a.P;
   const size_t cstride = (size_t)a.N * a.nt * 2;
 
-  const E* Ab = static_cast<const E*>(a.A) + (size_t)g * a.M * a.KD;
-  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)a.M * a.KD * ES));
+  const E* Ab = static_cast<const E*>(a.A) + (size_t)g * RS * a.M * a.KD;
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)RS * a.M * a.KD * ES));
   const E* Bb = static_cast<const E*>(a.in) + (size_t)b * a.nc * cstride + (size_t)p * twoP;
   const __amdgpu_buffer_rsrc_t rB = make_rsrc(Bb, (uint32_t)((a.nc * cstride - (size_t)p * twoP) * ES));
 
@@ -518,7 +569,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
   for (int r = 0; r < AR; ++r) {
     const int row = tm * TM + (tid >> 3) + r * (NTHR / 8);
-    va[r] = row < a.M ? (uint32_t)(((size_t)row * a.KD + kk) * ES) : kOOB;
+    va[r] = row < a.M ? (uint32_t)(((size_t)row * RS * a.KD + kk) * ES) : kOOB;
   }
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
@@ -545,13 +596,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
     for (int r = 0; r < BR; ++r) vb[r] += inc;
   };
-  typename G::Acc acc[MT][NT];
+  typename G::Acc acc[NA][MT][NT];
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
+  for (int q = 0; q < NA; ++q)
 #pragma unroll
-    for (int c = 0; c < NT; ++c)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
+      for (int c = 0; c < NT; ++c)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[q][m][c][r] = 0.f;
 #pragma unroll
   for (int f = 0; f < PF; ++f)
     if (f < nst) fetch(pa[f], pb[f]);
@@ -578,12 +631,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
       for (int c = 0; c < NT; ++c)
         fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
-#pragma unroll
-        for (int e = 0; e < NE; ++e)
-#pragma unroll
-          for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+        block_mma<ST, true>(fa, fb, acc);
       }
     }
   }
@@ -594,10 +642,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
       const int col = col0 + T * c + li;
+      if constexpr (C3) {
 #pragma unroll
-      for (int r = 0; r < NR; r += 2) {
-        const int row = row0 + T * m + G::row_of(r, lh);
-        if (col < a.N && row < a.M) out[(size_t)(row >> 1) * a.N + col] = make_float2(acc[m][c][r], acc[m][c][r + 1]);
+        for (int r = 0; r < NR; ++r) {
+          const int row = row0 + T * m + G::row_of(r, lh);
+          const float t1 = acc[0][m][c][r], t2 = acc[1][m][c][r], t3 = acc[2][m][c][r];
+          if (col < a.N && row < a.M) out[(size_t)row * a.N + col] = make_float2(t1 + t2, t3 - t1 + t2);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; r += 2) {
+          const int row = row0 + T * m + G::row_of(r, lh);
+          if (col < a.N && row < a.M)
+            out[(size_t)(row >> 1) * a.N + col] = make_float2(acc[0][m][c][r], acc[0][m][c][r + 1]);
+        }
       }
     }
 }
@@ -610,14 +668,18 @@ template <int WM, int WN, int MT, int NT, int PF, Store ST>
 __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
   using G = Geo<ST>;
   using E = typename Mma<ST>::E;
-  constexpr int T = G::T, NR = G::NR, NE = G::NE;
+  constexpr int T = G::T, NR = G::NR;
   constexpr int ES = (int)sizeof(E);
   constexpr int KT = 128 / ES, LS = 36;
+  // FP32 takes the three-multiplication form: a.N counts complex columns
+  // (n, j), and column i is bank row 2i, A_g[:, i] interleaved.
+  constexpr bool C3 = ST == Store::F32;
+  constexpr int RS = C3 ? 2 : 1, NA = C3 ? 3 : 1, CF = C3 ? 2 : 1;  // CF: output floats per column
   constexpr int JB = 128 / (G::KB * ES), JF = G::KB * ES / 4;
   constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
   constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;
   static_assert(AR * NTHR == TM * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
-  constexpr int LDT = TN + 4;
+  constexpr int LDT = CF * TN + 4;
   constexpr int SM = ((TM + TN) * LS > TM * LDT ? (TM + TN) * LS : TM * LDT);
   __shared__ floatx4 smem[SM / 4];
   float* As = reinterpret_cast<float*>(smem);
@@ -637,8 +699,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 
   const __amdgpu_buffer_rsrc_t rA = make_rsrc(static_cast<const E*>(a.Zt) + (size_t)bp * a.M * a.KD,
                                               (uint32_t)((size_t)a.M * a.KD * ES));
-  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const E*>(a.AH) + (size_t)g * a.N * a.KD,
-                                              (uint32_t)((size_t)a.N * a.KD * ES));
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const E*>(a.AH) + (size_t)g * RS * a.N * a.KD,
+                                              (uint32_t)((size_t)RS * a.N * a.KD * ES));
   const int nst = a.KD / KT;
   const int c16 = tid & 7;
   uint32_t va[AR], vb[BR];
@@ -650,7 +712,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
-    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.KD + (KT / 8) * c16) * ES) : kOOB;
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * RS * a.KD + (KT / 8) * c16) * ES) : kOOB;
   }
   floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
   auto fetch = [&](floatx4(&xa)[AR], floatx4(&xb)[BR]) {
@@ -663,13 +725,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
     for (int r = 0; r < BR; ++r) vb[r] += KT * ES;
   };
-  typename G::Acc acc[MT][NT];
+  typename G::Acc acc[NA][MT][NT];
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
+  for (int q = 0; q < NA; ++q)
 #pragma unroll
-    for (int c = 0; c < NT; ++c)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
+      for (int c = 0; c < NT; ++c)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[q][m][c][r] = 0.f;
 #pragma unroll
   for (int f = 0; f < PF; ++f)
     if (f < nst) fetch(pa[f], pb[f]);
@@ -696,12 +760,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
       for (int c = 0; c < NT; ++c)
         fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
-#pragma unroll
-        for (int e = 0; e < NE; ++e)
-#pragma unroll
-          for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(fa[m], fb[c], e, acc[m][c]);
+        block_mma<ST, false>(fa, fb, acc);
       }
     }
   }
@@ -712,15 +771,23 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        tile[(wm * MT * T + T * m + G::row_of(r, lh)) * LDT + wn * NT * T + T * c + li] = acc[m][c][r];
+      for (int r = 0; r < NR; ++r) {
+        float* t = tile + (wm * MT * T + T * m + G::row_of(r, lh)) * LDT + CF * (wn * NT * T + T * c + li);
+        if constexpr (C3) {
+          const float t1 = acc[0][m][c][r], t2 = acc[1][m][c][r], t3 = acc[2][m][c][r];
+          *reinterpret_cast<float2*>(t) = make_float2(t1 + t2, t3 - t1 + t2);
+        } else {
+          *t = acc[0][m][c][r];
+        }
+      }
   __syncthreads();
   const int twoP = 2 * a.P;
-  const int rbase = tm * TM, cbase = tn * TN;
-  for (int e = tid; e < TM * (TN / 4); e += NTHR) {
-    const int rl = e / (TN / 4), cl = (e - rl * (TN / 4)) * 4;
+  constexpr int TF = CF * TN;  // output tile width in floats
+  const int rbase = tm * TM, cbase = CF * tn * TN, ncolf = CF * a.N;
+  for (int e = tid; e < TM * (TF / 4); e += NTHR) {
+    const int rl = e / (TF / 4), cl = (e - rl * (TF / 4)) * 4;
     const int y = rbase + rl, col = cbase + cl;
-    if (y >= a.M || col >= a.N) continue;
+    if (y >= a.M || col >= ncolf) continue;
     const int n = col / twoP, jj = col - n * twoP;
     const size_t fi = (((size_t)b * a.nc + n) * a.M + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
     const float* src = tile + rl * LDT + cl;
@@ -776,8 +843,8 @@ __global__ void k_expand_bank(const double2* __restrict__ A, BankOut o, int G, i
 }
 
 // Tile-shape tables: waves WM x WN per work-group, wave tile MT x NT MFMA
-// tiles, depth.  kCompressLds / kExpandLds: LDS-staged FP32 (32 x 32 tiles,
-// depth = k-tiles of register prefetch); the *16 tables: LDS-staged 16-bit
+// tiles, depth.  kCompressLds / kExpandLds: LDS-staged FP32 (32 x 32 tiles
+// of complex rows / columns, depth = k-tiles of register prefetch); the *16 tables: LDS-staged 16-bit
 // (16 x 16 tiles); kExpand32 / kExpand16: the buffer-addressed register-direct
 // expanding forms (depth = register ring).  Index 0 is the default of its
 // class.  The general forms (operands of 2 GiB or more) use one fixed shape.
@@ -789,10 +856,10 @@ constexpr Shape kExpand32[kNumShapes] = {{1, 2, 1, 4, 3}, {1, 4, 1, 2, 3}, {1, 2
                                          {2, 2, 1, 2, 3}, {1, 2, 1, 4, 4}, {1, 4, 1, 1, 3}, {1, 2, 2, 2, 4}};
 constexpr Shape kExpand16[kNumShapes] = {{1, 2, 4, 4, 4}, {1, 2, 4, 4, 3}, {1, 4, 2, 4, 3}, {2, 2, 4, 2, 3},
                                          {1, 4, 2, 2, 3}, {1, 4, 2, 4, 5}, {2, 2, 2, 4, 3}, {1, 4, 1, 4, 3}};
-constexpr Shape kCompressLds[kNumShapes] = {{4, 1, 1, 1, 1}, {4, 1, 1, 1, 2}, {4, 1, 1, 2, 1}, {2, 2, 2, 1, 1},
-                                            {2, 1, 2, 1, 1}, {4, 2, 1, 1, 1}, {2, 1, 1, 1, 1}, {1, 4, 1, 1, 1}};
-constexpr Shape kExpandLds[kNumShapes] = {{1, 4, 1, 1, 1}, {1, 4, 1, 1, 2}, {2, 2, 1, 1, 1}, {1, 4, 1, 2, 1},
-                                          {2, 4, 1, 1, 1}, {1, 2, 1, 2, 1}, {1, 2, 1, 1, 1}, {2, 2, 1, 2, 1}};
+constexpr Shape kCompressLds[kNumShapes] = {{2, 2, 1, 1, 1}, {2, 1, 1, 1, 2}, {2, 1, 1, 1, 1}, {2, 1, 1, 2, 1},
+                                            {4, 1, 1, 1, 1}, {2, 4, 1, 1, 1}, {1, 2, 1, 1, 1}, {1, 4, 1, 1, 1}};
+constexpr Shape kExpandLds[kNumShapes] = {{1, 2, 1, 1, 1}, {1, 4, 1, 1, 1}, {1, 2, 1, 1, 2}, {2, 2, 1, 1, 1},
+                                          {1, 1, 1, 1, 1}, {1, 2, 1, 2, 1}, {2, 1, 1, 1, 1}, {1, 4, 1, 1, 2}};
 constexpr Shape kCompressLds16[kNumShapes] = {{4, 1, 2, 4, 1}, {2, 2, 4, 2, 1}, {2, 1, 4, 2, 1}, {4, 1, 2, 2, 1},
                                               {2, 1, 4, 4, 1}, {4, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 2, 2, 2, 1}};
 constexpr Shape kExpandLds16[kNumShapes] = {{2, 2, 2, 2, 1}, {1, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 4, 2, 2, 1},
@@ -824,8 +891,10 @@ void launch_compress_v(hipStream_t s, const CompressArgs& a) {
   if (compress_staged(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kCompressLds[V] : kCompressLds16[V];
     constexpr int T = Geo<ST>::T;
-    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
-    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    CompressArgs c = a;
+    if (ST == Store::F32) c.M = a.K;  // complex rows of the three-multiplication form
+    const dim3 grid(tiles(c.N, S.wn * S.nt * T) * tiles(c.M, S.wm * S.mt * T) * rest);
+    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, c);
   } else {
     constexpr Shape S = kCompressGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
@@ -838,8 +907,10 @@ void launch_expand_v(hipStream_t s, const ExpandArgs& a) {
   if (expand_staged(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kExpandLds[V] : kExpandLds16[V];
     constexpr int T = Geo<ST>::T;
-    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
-    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    ExpandArgs e = a;
+    if (ST == Store::F32) e.N = a.N / 2;  // complex columns of the three-multiplication form
+    const dim3 grid(tiles(e.N, S.wn * S.nt * T) * tiles(e.M, S.wm * S.mt * T) * rest);
+    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, e);
   } else if (expand_uniform(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kExpand32[V] : kExpand16[V];
     constexpr int T = Geo<ST>::T;
@@ -931,28 +1002,31 @@ int gemm_compress_variants() { return kNumShapes; }
 int gemm_expand_variants() { return kNumShapes; }
 
 // Defaults: for the compressing contraction the work-group shape with the
-// tallest row tile (128, 64 or 32 of the 2K rows) that pads at most 1/8 of its
-// rows, for the expanding one shape 0; and a split giving about 1536 (FP32) or
-// 640 (16-bit) work-groups.
+// tallest row tile that pads at most 1/8 of its rows (FP32: 64 or 32 of the K
+// complex rows; 16-bit: 128, 64 or 32 of the 2K real rows), else the shortest;
+// for the expanding one shape 0; and a split giving about 1008 (FP32) or 640
+// (16-bit) work-groups.
 int compress_shape_for_rows(int rows, bool f32) {
-  const int order[3] = {0, f32 ? 6 : 7, f32 ? 7 : 6}, tile[3] = {128, 64, 32};
-  for (int i = 0; i < 3; ++i) {
+  const int n = f32 ? 2 : 3;
+  const int order[3] = {0, 7, 6}, tile[3] = {f32 ? 64 : 128, f32 ? 32 : 64, 32};
+  for (int i = 0; i < n; ++i) {
     const int padded = (rows + tile[i] - 1) / tile[i] * tile[i];
     if (8 * (padded - rows) <= padded) return order[i];
   }
-  return order[2];
+  return order[n - 1];
 }
 void default_gemm_config(Plan& pl) {
   for (int c = 0; c < 2; ++c) {
     const Store st = c == 0 ? Store::F32 : Store::BF16;
     Plan::GemmCfg& g = pl.cfg(st);
-    g.cvar = compress_shape_for_rows(2 * pl.K, c == 0);
+    const int rows = c == 0 ? pl.K : 2 * pl.K;  // complex rows in FP32, real rows in 16-bit
+    g.cvar = compress_shape_for_rows(rows, c == 0);
     g.evar = 0;
     const Shape S = c == 0 ? kCompressLds[g.cvar] : kCompressLds16[g.cvar];  // the staged forms take every even P
     const int T = c == 0 ? 32 : 16;
-    const long t = (long)tiles(pl.ny, S.wn * S.nt * T) * tiles(2 * pl.K, S.wm * S.mt * T) * pl.B * pl.np;
+    const long t = (long)tiles(pl.ny, S.wn * S.nt * T) * tiles(rows, S.wm * S.mt * T) * pl.B * pl.np;
     // work-groups: measured best on the 224 x 224, 32-coil slice
-    const long target = c == 0 ? 1536 : 640;
+    const long target = c == 0 ? 1008 : 640;
     int ks = (int)std::max<long>(1, (target + t - 1) / t);
     ks = std::min(std::min(ks, std::max(1, 2 * pl.ns / 128)), kMaxKsplit);
     g.ksplit = ks;
