@@ -204,6 +204,7 @@ __global__ __launch_bounds__(256) void k_readout_adj(const void* __restrict__ W,
 // read through the L1 cache, shared by all work-groups of a CU.
 // ---------------------------------------------------------------------------
 __device__ inline int udiv(int a, int b) { return (int)(((float)a + 0.5f) / (float)b); }  // a < 2^16, b small
+constexpr int kPsfRegs = 8;  // readout samples per thread held in registers by k_readout_fwd2 / _adj2
 
 template <int NX, Store ST>
 __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__ img, const float2* __restrict__ coils,
@@ -246,6 +247,13 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
     }
   }
   __syncthreads();
+  // The PSF samples of the output phase are loaded here, behind the second
+  // pass.  Loads and stores retire in issue order, so a load issued between
+  // the output stores could only be waited for together with them.
+  const float2* ps = psfp + (size_t)y * nt;
+  float2 pv[kPsfRegs];
+#pragma unroll
+  for (int k = 0; k < kPsfRegs; ++k) pv[k] = ps[min(tid + k * nthr, nt - 1)];  // past the end: dropped
   const int items2 = ncb * os * N1;
   const bool act = tid < items2;
   float2 w[N2];
@@ -266,8 +274,16 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
     for (int k2 = 0; k2 < N2; ++k2) o[(k1 + N1 * k2) * os] = w[k2];
   }
   __syncthreads();
-  const float2* ps = psfp + (size_t)y * nt;
-  for (int t = tid; t < nt; t += nthr) {
+  for (int c = 0; c < ncb; ++c) {
+    const size_t row = (((size_t)b * nc + n0 + c) * ny + y) * nt;
+    const float2* ar = A + c * nt;
+#pragma unroll
+    for (int k = 0; k < kPsfRegs; ++k) {
+      const int t = tid + k * nthr;
+      if (t < nt) store_c<ST>(W, row + t, cmul(pv[k], ar[t]));
+    }
+  }
+  for (int t = tid + kPsfRegs * nthr; t < nt; t += nthr) {
     const float2 p = ps[t];
     for (int c = 0; c < ncb; ++c)
       store_c<ST>(W, (((size_t)b * nc + n0 + c) * ny + y) * nt + t, cmul(p, A[c * nt + t]));
@@ -298,7 +314,28 @@ __global__ __launch_bounds__(256) void k_readout_adj2(const void* __restrict__ W
   float2* X = twl + NX;   // [cb][os][nxp] inputs, then [cb][os][N2][AS], then [cb][os][NX] results
   for (int i = tid; i < NX; i += nthr) twl[i] = tw[i];
   const float2* ps = psfp + (size_t)y * nt;
-  for (int t = tid; t < nt; t += nthr) {
+  // kPsfRegs samples per thread and coil are loaded before any is used, so
+  // that many loads are in flight instead of one sample's.  Samples past the
+  // row end load the last sample (no branch around a load) and are dropped.
+  float2 pv[kPsfRegs];
+  int xo[kPsfRegs];  // LDS slot (s, q) of sample t, without the coil offset
+#pragma unroll
+  for (int k = 0; k < kPsfRegs; ++k) {
+    const int t = tid + k * nthr;
+    const int q = udiv(t, os), s = t - q * os;
+    pv[k] = ps[min(t, nt - 1)];
+    xo[k] = s * nxp + q;
+  }
+  for (int c = 0; c < ncb; ++c) {
+    const size_t row = (((size_t)b * nc + n0 + c) * ny + y) * nt;
+    float2 wv[kPsfRegs];
+#pragma unroll
+    for (int k = 0; k < kPsfRegs; ++k) wv[k] = load_c<ST>(W, row + min(tid + k * nthr, nt - 1));
+#pragma unroll
+    for (int k = 0; k < kPsfRegs; ++k)
+      if (tid + k * nthr < nt) X[c * os * nxp + xo[k]] = cmulc(pv[k], wv[k]);
+  }
+  for (int t = tid + kPsfRegs * nthr; t < nt; t += nthr) {
     const int q = udiv(t, os), s = t - q * os;
     const float2 p = ps[t];
     for (int c = 0; c < ncb; ++c)
@@ -390,6 +427,32 @@ template <int NY>
 __device__ inline float pe_post(int ky) {
   const float s = (((NY / 2) + ky) & 1) ? -1.f : 1.f;
   return s * (1.0f / sqrtf((float)NY));
+}
+
+// Sums over the k-split partials of elements i = tid + 256 it (it < IT) of
+// the nel consecutive elements at base, in partial order (the same values as
+// adding them one by one).  The loads of kSumBatch partials of all IT
+// elements are issued before any is added, so they are in flight together.
+constexpr int kSumBatch = 3;
+template <int IT>
+__device__ inline void sum_partials(float2 (&a)[IT], const float2* __restrict__ Zp, int ksplit, size_t zstride,
+                                    size_t base, int nel, int tid) {
+#pragma unroll
+  for (int it = 0; it < IT; ++it) a[it] = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < ksplit; k0 += kSumBatch) {
+    float2 v[kSumBatch][IT];
+#pragma unroll
+    for (int h = 0; h < kSumBatch; ++h)
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = min(tid + 256 * it, nel - 1);  // past the end: a valid element, dropped by the caller
+        v[h][it] = k0 + h < ksplit ? Zp[(size_t)(k0 + h) * zstride + base + i] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+    for (int h = 0; h < kSumBatch; ++h)
+#pragma unroll
+      for (int it = 0; it < IT; ++it) a[it] = cadd(a[it], v[h][it]);
+  }
 }
 
 template <int NY>
@@ -527,12 +590,18 @@ __global__ __launch_bounds__(256) void k_pe_normal2(const float2* __restrict__ Z
   for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
   const int l0 = blockIdx.x * L;
   const int nl = min(L, nlines - l0);
-  for (int i = tid; i < nl * NY; i += 256) {
-    const int ln = i / NY, y = i - ln * NY;
-    const size_t g = (size_t)l0 * NY + i;
-    float2 a = Zp[g];
-    for (int ks = 1; ks < ksplit; ++ks) a = cadd(a, Zp[ks * zstride + g]);
-    Zs[ln * NYP + y] = (y & 1) ? make_float2(-a.x, -a.y) : a;
+  {
+    constexpr int IT = (L * NY + 255) / 256;
+    float2 a[IT];
+    sum_partials<IT>(a, Zp, ksplit, zstride, (size_t)l0 * NY, nl * NY, tid);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = tid + 256 * it;
+      if (i < nl * NY) {
+        const int ln = i / NY, y = i - ln * NY;
+        Zs[ln * NYP + y] = (y & 1) ? make_float2(-a[it].x, -a[it].y) : a[it];
+      }
+    }
   }
   __syncthreads();
   if (tid < nl * N2) {  // forward, first pass: item (line, i2)
