@@ -49,6 +49,25 @@ __device__ inline float2 load_c(const void* base, size_t i) {
   }
 }
 
+// Sum over the nchunk partial images (stride n) at element i, in a fixed
+// order: partial 0, then groups of eight partials, each loaded together (a
+// group past nchunk reads partial nchunk - 1 and replaces it by zero, so no
+// load sits behind a branch) and added as a balanced tree.
+__device__ inline float2 sum_chunks(const float2* __restrict__ part, int nchunk, size_t n, size_t i) {
+  auto add = [](float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); };
+  float2 v = part[i];
+  for (int c = 1; c < nchunk; c += 8) {
+    float2 a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float2 x = part[(size_t)min(c + k, nchunk - 1) * n + i];
+      a[k] = c + k < nchunk ? x : make_float2(0.f, 0.f);
+    }
+    v = add(v, add(add(add(a[0], a[1]), add(a[2], a[3])), add(add(a[4], a[5]), add(a[6], a[7]))));
+  }
+  return v;
+}
+
 // Work-group id remapped so that consecutive logical tiles share one XCD
 // (work-groups are dealt round-robin over the 8 XCDs, each with its own L2).
 __device__ inline int xcd_logical(int linear, int total) {

@@ -405,18 +405,8 @@ __global__ __launch_bounds__(256) void k_readout_adj2(const void* __restrict__ W
 }
 
 __global__ void k_combine(const float2* __restrict__ part, int nchunk, size_t n, float2* __restrict__ out) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    float2 v = part[i];
-    int c = 1;
-    for (; c + 8 <= nchunk; c += 8) {  // eight loads in flight, fixed order
-      float2 a[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) a[k] = part[(size_t)(c + k) * n + i];
-      v = cadd(v, cadd(cadd(cadd(a[0], a[1]), cadd(a[2], a[3])), cadd(cadd(a[4], a[5]), cadd(a[6], a[7]))));
-    }
-    for (; c < nchunk; ++c) v = cadd(v, part[(size_t)c * n + i]);
-    out[i] = v;
-  }
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = sum_chunks(part, nchunk, n, i);
 }
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <vector>
 
+#include "devutil.h"
 #include "fft.h"
 #include "plan.h"
 
@@ -55,21 +56,6 @@ __device__ inline double sum_partials(const double* __restrict__ p, int nb, doub
   return r;
 }
 
-// Sum of the nchunk partial images at element i, in a fixed order; loads are
-// issued four at a time so that they are in flight together.
-__device__ inline float2 sum_part(const float2* __restrict__ part, int nchunk, size_t n, size_t i) {
-  float2 v = part[i];
-  int c = 1;
-  for (; c + 8 <= nchunk; c += 8) {
-    float2 a[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = part[(size_t)(c + k) * n + i];
-    v = cadd(v, cadd(cadd(cadd(a[0], a[1]), cadd(a[2], a[3])), cadd(cadd(a[4], a[5]), cadd(a[6], a[7]))));
-  }
-  for (; c < nchunk; ++c) v = cadd(v, part[(size_t)c * n + i]);
-  return v;
-}
-
 __global__ __launch_bounds__(256) void k_fill_zero(float2* __restrict__ v, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     v[i] = make_float2(0.f, 0.f);
@@ -103,7 +89,7 @@ __global__ __launch_bounds__(256) void k_cg_start(const float2* __restrict__ par
   __shared__ double sh[8];
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float2 v = csub(bvec[i], sum_part(part, nchunk, n, i));
+    const float2 v = csub(bvec[i], sum_chunks(part, nchunk, n, i));
     r[i] = v;
     p[i] = v;
     acc += (double)v.x * v.x + (double)v.y * v.y;
@@ -128,7 +114,7 @@ __global__ __launch_bounds__(256) void k_cg_q(const float2* __restrict__ part, i
   __shared__ double sh[8];
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float2 v = sum_part(part, nchunk, n, i);
+    const float2 v = sum_chunks(part, nchunk, n, i);
     q[i] = v;
     const float2 pv = p[i];
     acc += (double)pv.x * v.x + (double)pv.y * v.y;
@@ -288,7 +274,7 @@ __global__ __launch_bounds__(256) void k_gd_update(const float2* __restrict__ pa
                                                    float2* __restrict__ r_out, size_t n) {
   const float a = *alpha;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float2 r = csub(sum_part(part, nchunk, n, i), b[i]);
+    const float2 r = csub(sum_chunks(part, nchunk, n, i), b[i]);
     const float2 xv = x[i];
     x_out[i] = make_float2(fmaf(-a, r.x, xv.x), fmaf(-a, r.y, xv.y));
     if (r_out) r_out[i] = r;
@@ -303,7 +289,7 @@ __global__ __launch_bounds__(256) void k_gd_backward(const float2* __restrict__ 
   const float a = *alpha;
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float2 q = sum_part(part, nchunk, n, i);
+    const float2 q = sum_chunks(part, nchunk, n, i);
     const float2 gv = g[i];
     if (gx) gx[i] = make_float2(fmaf(-a, q.x, gv.x), fmaf(-a, q.y, gv.y));
     if (gb) gb[i] = make_float2(a * gv.x, a * gv.y);
@@ -485,7 +471,7 @@ __global__ __launch_bounds__(256) void k_fista_step(const float2* __restrict__ p
   const int ty = rem / tx_n, tx = rem - ty * tx_n;
   const size_t n = (size_t)B * nx * ny;
   const size_t idx = ((size_t)b * ny + ty * S + i) * nx + tx * S + j;
-  const float2 g = csub(sum_part(part, nchunk, n, idx), bvec[idx]);
+  const float2 g = csub(sum_chunks(part, nchunk, n, idx), bvec[idx]);
   const float2 yy = yv[idx];
   float2 c = make_float2(fmaf(-invL, g.x, yy.x), fmaf(-invL, g.y, yy.y));
   c = haar_lanes<LEV>(c, i, j, false);
@@ -568,7 +554,7 @@ __global__ __launch_bounds__(256) void k_power_q(const float2* __restrict__ part
   __shared__ double sh[8];
   double a1 = 0.0, a2 = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float2 w = sum_part(part, nchunk, n, i);
+    const float2 w = sum_chunks(part, nchunk, n, i);
     q[i] = w;
     const float2 a = v[i];
     a1 += (double)a.x * w.x + (double)a.y * w.y;
