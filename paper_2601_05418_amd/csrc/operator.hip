@@ -449,12 +449,19 @@ template <int NY>
 __device__ inline void load_z_lines(float2* A, const float2* __restrict__ Zp, int ksplit, size_t zstride, int l0,
                                     int nl, int tid) {
   constexpr int LS = fline(NY);
-  for (int i = tid; i < nl * NY; i += 256) {
-    const int li = i / NY, y = i - li * NY;
-    const size_t g = (size_t)l0 * NY + i;
-    float2 v = Zp[g];
-    for (int ks = 1; ks < ksplit; ++ks) v = cadd(v, Zp[ks * zstride + g]);
-    A[li * LS + fpad(y)] = (y & 1) ? make_float2(-v.x, -v.y) : v;
+  constexpr int IT = 4;  // elements per thread and round of loads
+  const int nel = nl * NY;
+  for (int i0 = 0; i0 < nel; i0 += IT * 256) {
+    float2 a[IT];
+    sum_partials<IT>(a, Zp, ksplit, zstride, (size_t)l0 * NY + i0, nel - i0, tid);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int i = i0 + tid + 256 * it;
+      if (i < nel) {
+        const int li = i / NY, y = i - li * NY;
+        A[li * LS + fpad(y)] = (y & 1) ? make_float2(-a[it].x, -a[it].y) : a[it];
+      }
+    }
   }
 }
 
