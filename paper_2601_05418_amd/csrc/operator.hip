@@ -205,6 +205,7 @@ __global__ __launch_bounds__(256) void k_readout_adj(const void* __restrict__ W,
 // ---------------------------------------------------------------------------
 __device__ inline int udiv(int a, int b) { return (int)(((float)a + 0.5f) / (float)b); }  // a < 2^16, b small
 constexpr int kPsfRegs = 8;  // readout samples per thread held in registers by k_readout_fwd2 / _adj2
+constexpr int kSetupRegs = 2;  // coil x image elements per thread and round of loads in k_readout_fwd2
 
 template <int NX, Store ST>
 __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__ img, const float2* __restrict__ coils,
@@ -221,11 +222,31 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
   float2* twl = sm;         // [NX]       exp(-2 pi i m / NX)
   float2* u = twl + NX;     // [cb][NX]   coil * image
   float2* A = u + cb * NX;  // [cb][os][N2][AS], then the output rows [cb][nt]
-  for (int i = tid; i < NX; i += nthr) twl[i] = tw[i];
   const float2* ip = img + ((size_t)b * ny + y) * NX;
-  for (int i = tid; i < ncb * NX; i += nthr) {
-    const int c = i / NX, x = i - c * NX;
-    u[i] = cmul(coils[((size_t)(n0 + c) * ny + y) * NX + x], ip[x]);
+  {
+    // The set-up loads (coil and image rows, twiddles) are issued before any
+    // is used: kSetupRegs elements per thread, clamped indices; a loop takes
+    // whatever a launch with few threads leaves over.
+    const int tot = ncb * NX;
+    float2 cv[kSetupRegs], iv[kSetupRegs];
+#pragma unroll
+    for (int k = 0; k < kSetupRegs; ++k) {
+      const int i = min(tid + k * nthr, tot - 1), c = i / NX, x = i - c * NX;
+      cv[k] = coils[((size_t)(n0 + c) * ny + y) * NX + x];
+      iv[k] = ip[x];
+    }
+    const float2 twv = tw[min(tid, NX - 1)];
+#pragma unroll
+    for (int k = 0; k < kSetupRegs; ++k) {
+      const int i = tid + k * nthr;
+      if (i < tot) u[i] = cmul(cv[k], iv[k]);
+    }
+    for (int i = tid + kSetupRegs * nthr; i < tot; i += nthr) {
+      const int c = i / NX, x = i - c * NX;
+      u[i] = cmul(coils[((size_t)(n0 + c) * ny + y) * NX + x], ip[x]);
+    }
+    if (tid < NX) twl[tid] = twv;
+    for (int i = tid + nthr; i < NX; i += nthr) twl[i] = tw[i];
   }
   __syncthreads();
   const int items1 = ncb * os * N2;
@@ -312,7 +333,7 @@ __global__ __launch_bounds__(256) void k_readout_adj2(const void* __restrict__ W
   const int n0 = chunk * cb, ncb = min(cb, nc - n0);
   float2* twl = sm;       // [NX]
   float2* X = twl + NX;   // [cb][os][nxp] inputs, then [cb][os][N2][AS], then [cb][os][NX] results
-  for (int i = tid; i < NX; i += nthr) twl[i] = tw[i];
+  const float2 twv = tw[min(tid, NX - 1)];  // stored below, behind the sample loads
   const float2* ps = psfp + (size_t)y * nt;
   // kPsfRegs samples per thread and coil are loaded before any is used, so
   // that many loads are in flight instead of one sample's.  Samples past the
@@ -341,6 +362,8 @@ __global__ __launch_bounds__(256) void k_readout_adj2(const void* __restrict__ W
     for (int c = 0; c < ncb; ++c)
       X[(c * os + s) * nxp + q] = cmulc(p, load_c<ST>(W, (((size_t)b * nc + n0 + c) * ny + y) * nt + t));
   }
+  if (tid < NX) twl[tid] = twv;
+  for (int i = tid + nthr; i < NX; i += nthr) twl[i] = tw[i];
   __syncthreads();
   const int items1 = ncb * os * N2;  // <= blockDim.x
   float2 v[N1];
