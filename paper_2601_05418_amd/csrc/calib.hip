@@ -500,38 +500,20 @@ __device__ inline void zmma_lds_frag(const double2 (*X)[kLd], const double2 (&fb
   }
 }
 
-// C = V^H[16 bi + ., :] * X[:, 16 bj + .], V^H given as fragments of row block bi; X in LDS.
-__device__ inline void zmma_fragh_lds(const double2 (&fa)[kPair / 4], const double2 (*X)[kLd], int bj, dx4& cr,
-                                      dx4& ci) {
-  const int l = threadIdx.x & 63;
-  const int li = l & 15, lk = l >> 4;
-  cr = dx4{0.0, 0.0, 0.0, 0.0};
-  ci = dx4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s = 0; s < kPair / 4; ++s) {
-    const double2 a = make_double2(fa[s].x, -fa[s].y);
-    const double2 b = X[4 * s + lk][16 * bj + li];
-    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
-  }
-}
-
-__device__ inline void ztile_store(double2 (*C)[kLd], int bi, int bj, const dx4& cr, const dx4& ci) {
-  const int l = threadIdx.x & 63;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) C[16 * bi + 4 * r + (l >> 4)][16 * bj + (l & 15)] = make_double2(cr[r], ci[r]);
-}
-
-// H <- Q^H H Q on the tile of pair a (rows) x pair b (cols), a <= b; the
-// mirrored tile (b, a) is written as the conjugate transpose.  Each of the
-// four waves owns one 16 x 16 quarter of the tile; the rotation blocks are
-// read from L2 straight into MFMA operand registers, so only the H tile
-// occupies LDS.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_jac_apply_h(double2* __restrict__ H, const double2* __restrict__ Vall,
-                                                     const int* __restrict__ rot, const int* __restrict__ active,
-                                                     int nsp, int nb, int round) {
+// H <- V_a^H H V_b on the tile of pair a (rows) x pair b (cols), a <= b, one
+// wave per tile with neither LDS nor barriers; the mirrored tile (b, a) is
+// written as the conjugate transpose.
+// - Y = X V_b, X the tile: per 16 x 16 block (q, bj), operand fragments of X
+//   are read from H directly, those of V_b from the rotation blocks.
+// - Z = V_a^H Y: the result registers of Y's blocks are already the B
+//   operand fragments of this product (register r of block q holds rows
+//   4 (4 q + r) + l / 16, i.e. k-step 4 q + r).
+// The wave reads the whole tile before it writes any of it, so the update
+// in place needs no synchronisation.  A side whose rotation is the identity
+// is skipped.
+__global__ __launch_bounds__(64) void k_jac_apply_h(double2* __restrict__ H, const double2* __restrict__ Vall,
+                                                    const int* __restrict__ rot, const int* __restrict__ active,
+                                                    int nsp, int nb, int round) {
   const int g = blockIdx.y;
   if (!active[g]) return;
   const int npair = nb / 2;
@@ -542,35 +524,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   int Ia, Ja, Ib, Jb;
   rr_pair(nb, round, a, &Ia, &Ja);
   rr_pair(nb, round, b, &Ib, &Jb);
-  __shared__ double2 X[kPair][kLd];
-  const int tid = threadIdx.x;
-  const int w = tid >> 6, bi = w >> 1, bj = w & 1;
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
   double2* Hg = H + (size_t)g * nsp * nsp;
-  double2 fa[kPair / 4], fb[kPair / 4];
-  if (rb) zfrag_load(Vall + ((size_t)g * npair + b) * kPair * kPair, bj, fb);
-  if (ra) zfrag_load(Vall + ((size_t)g * npair + a) * kPair * kPair, bi, fa);
-  for (int e = tid; e < kPair * kPair; e += 256) {
-    const int i = e / kPair, j = e % kPair;
-    X[i][j] = Hg[(size_t)pair_index(Ia, Ja, i) * nsp + pair_index(Ib, Jb, j)];
+  const double2* Va = Vall + ((size_t)g * npair + a) * kPair * kPair;
+  const double2* Vb = Vall + ((size_t)g * npair + b) * kPair * kPair;
+  dx4 yr[2][2], yi[2][2];  // Y block (q, bj): register r holds Y[16 q + 4 r + l / 16][16 bj + l % 16]
+  if (rb) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      double2 fb[kPair / 4];
+      zfrag_load(Vb, bj, fb);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const size_t row = (size_t)pair_index(Ia, Ja, 16 * q + li) * nsp;
+        dx4 cr = dx4{0.0, 0.0, 0.0, 0.0}, ci = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < kPair / 4; ++s) {
+          const double2 x = Hg[row + pair_index(Ib, Jb, 4 * s + lk)];
+          const double2 v = fb[s];
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, v.x, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-x.y, v.y, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, v.y, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, v.x, ci, 0, 0, 0);
+        }
+        yr[q][bj] = cr;
+        yi[q][bj] = ci;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double2 x = Hg[(size_t)pair_index(Ia, Ja, 16 * q + 4 * r + lk) * nsp + pair_index(Ib, Jb, 16 * bj + li)];
+          yr[q][bj][r] = x.x;
+          yi[q][bj][r] = x.y;
+        }
   }
-  __syncthreads();
-  dx4 cr, ci;
-  if (rb) {  // X <- X V_b
-    zmma_lds_frag(X, fb, bi, cr, ci);
-    __syncthreads();
-    ztile_store(X, bi, bj, cr, ci);
-    __syncthreads();
-  }
-  if (ra) {  // X <- V_a^H X
-    zmma_fragh_lds(fa, X, bj, cr, ci);
-    __syncthreads();
-    ztile_store(X, bi, bj, cr, ci);
-    __syncthreads();
-  }
-  for (int e = tid; e < kPair * kPair; e += 256) {
-    const int i = e / kPair, j = e % kPair;
-    Hg[(size_t)pair_index(Ia, Ja, i) * nsp + pair_index(Ib, Jb, j)] = X[i][j];
-    if (a != b) Hg[(size_t)pair_index(Ib, Jb, i) * nsp + pair_index(Ia, Ja, j)] = zconj(X[j][i]);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {  // row block of Z
+    double2 fa[kPair / 4];
+    if (ra) zfrag_load(Va, q, fa);
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      dx4 cr = yr[q][bj], ci = yi[q][bj];
+      if (ra) {
+        cr = dx4{0.0, 0.0, 0.0, 0.0};
+        ci = dx4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < kPair / 4; ++s) {
+          const double2 u = make_double2(fa[s].x, -fa[s].y);  // (V_a^H)[16 q + l % 16][4 s + l / 16]
+          const double yre = yr[s / 4][bj][s % 4], yim = yi[s / 4][bj][s % 4];
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(u.x, yre, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-u.y, yim, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(u.x, yim, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(u.y, yre, ci, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ra_i = pair_index(Ia, Ja, 16 * q + 4 * r + lk), cb_i = pair_index(Ib, Jb, 16 * bj + li);
+        Hg[(size_t)ra_i * nsp + cb_i] = make_double2(cr[r], ci[r]);
+        if (a != b) Hg[(size_t)cb_i * nsp + ra_i] = make_double2(cr[r], -ci[r]);
+      }
+    }
   }
 }
 
@@ -848,7 +867,7 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
     for (int round = 0; round < nb - 1; ++round) {
       hipLaunchKernelGGL(k_jac_solve, dim3(npair, G), dim3(256), 0, st, H, V, rot, active, thr2, nsp, nb, round,
                          1e-15);
-      hipLaunchKernelGGL(k_jac_apply_h, dim3(npair * npair, G), dim3(256), 0, st, H, V, rot, active, nsp, nb, round);
+      hipLaunchKernelGGL(k_jac_apply_h, dim3(npair * npair, G), dim3(64), 0, st, H, V, rot, active, nsp, nb, round);
       hipLaunchKernelGGL(k_jac_apply_u, dim3((nsp + kURows - 1) / kURows, npair, G), dim3(256), 0, st, U, V, rot,
                          active, nsp, nb, round);
     }
