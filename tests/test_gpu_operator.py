@@ -104,6 +104,26 @@ def test_uncompressed_normal_ragged_column_block(gpu_lib):
     check(host(plan.normal(dev(x)))[0], ops["nrm_full"](x[0]))
 
 
+@pytest.mark.parametrize("nx,ny,nc,os_,p", [(160, 16, 2, 16, 32), (512, 16, 4, 2, 16)])
+def test_long_readout_and_wide_rows(gpu_lib, nx, ny, nc, os_, p):
+    """Geometries that reach the readout kernels' remainder loops (their
+    work-groups have 256 threads): 160 x 16 = 2560 readout samples, more than
+    the 8 per thread held in registers, and four 512-pixel coil rows, more
+    than one round of 2 set-up loads per thread.  Forward, adjoint and normal
+    operator against the oracle (random orthonormal bank)."""
+    sl = H.rounded_slice(synth.tiny_slice(0, nx=nx, ny=ny, nc=nc, os_=os_, patch_len=p, k=8))
+    g = sl.geom
+    a = H.random_bank(g, seed=3)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(H.crandn(np.random.default_rng(4), (1, g.ny, g.nx)))
+    check(host(plan.forward(dev(x)))[0], ops["fwd"](x[0]))
+    y = H.round64(H.crandn(np.random.default_rng(5), plan.data_shape()))
+    check(host(plan.adjoint(dev(y)))[0], ops["adj"](y[0]))
+    check(host(plan.normal(dev(x)))[0], ops["nrm"](x[0]))
+
+
 @pytest.mark.parametrize("case", ["small", "rect"])
 def test_adjoint_identity(gpu_lib, case):
     sl, a, plan = make(case)
