@@ -85,7 +85,7 @@ struct CompressArgs {
   float2* out;      // [ksplit][B][np][K][N]
   const int* pgroup;
   const void* zeros;  // >= 16 zero bytes: the source of every masked-out load
-  int M, N, KD, nc, nt, P, np, K, B, ksplit, kchunk;
+  int M, N, KD, nc, nt, P, np, K, B, ksplit, kchunk;  // the FP32 staged form is launched with M = K
   size_t split_stride;
 };
 
@@ -208,7 +208,7 @@ struct ExpandArgs {
   void* W;          // [B][nc][ny][nt] complex (storage per Store)
   const int* pgroup;
   const void* zeros;
-  int M, N, KD, nc, nt, P, np, B;
+  int M, N, KD, nc, nt, P, np, B;  // the FP32 staged form is launched with N = ns
 };
 
 template <int WM, int WN, int MT, int NT, Store ST>

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
   {
     // The set-up loads (coil and image rows, twiddles) are issued before any
     // is used: kSetupRegs elements per thread, clamped indices; a loop takes
-    // whatever a launch with few threads leaves over.
+    // the rest of rows longer than that (cb NX > kSetupRegs blockDim).
     const int tot = ncb * NX;
     float2 cv[kSetupRegs], iv[kSetupRegs];
 #pragma unroll
