@@ -52,7 +52,8 @@ typedef struct { float re, im; } gpjc_c64;
 typedef struct { double re, im; } gpjc_c128;
 
 /* Arithmetic of the group contraction and PSF product inside the operator.
- * FP32: everything FP32 (FP32 MFMA).  BF16 / FP16 (compressed plans with
+ * FP32: everything FP32 (FP32 MFMA; the group contractions form each complex
+ * product from three real products).  BF16 / FP16 (compressed plans with
  * patch_len % 4 == 0, else GPJC_E_UNSUPPORTED): the operands of both group
  * contractions are rounded to BF16 / FP16 (round to nearest even) and
  * contracted on MFMA with FP32 accumulation -- the compression matrices, the
