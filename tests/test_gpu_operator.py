@@ -172,6 +172,36 @@ def test_highfield_uncompressed_normal_full_size(gpu_lib):
     check(host(plan.normal(dev(x)))[0], ops["nrm_full"](x[0]))
 
 
+def test_highfield_adjoint_identity_full_size(gpu_lib):
+    """<E' x, y> = <x, E'^H y> for the compressed FP32 operator at full size
+    (224 x 224, 32 coils, 42 groups, K = 64) in the benchmark's launch
+    configuration: a property of the pair that holds at any size."""
+    sl = H.rounded_slice(synth.highfield_slice(0))
+    a = H.random_bank(sl.geom, seed=11)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    rng = np.random.default_rng(12)
+    x = H.round64(H.crandn(rng, (1, sl.geom.ny, sl.geom.nx)))
+    y = H.round64(H.crandn(rng, plan.data_shape()))
+    lhs = np.vdot(host(plan.forward(dev(x))), y)
+    rhs = np.vdot(x, host(plan.adjoint(dev(y))))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_highfield_compress_full_size(gpu_lib):
+    """Compression of acquired data (Eq. 13) at full size: 68 sampled lines
+    give the contraction a ragged last column tile and no k-split.  Every
+    element against the oracle."""
+    sl = H.rounded_slice(synth.highfield_slice(0))
+    g = sl.geom
+    a = H.random_bank(g, seed=13)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    s_acq = H.round64(H.crandn(np.random.default_rng(14), (g.nc, g.ms, g.nt)))
+    out = host(plan.compress(dev(s_acq[None])))
+    check(out[0], oc.compress(s_acq, a, g.patch_group, g.patch_len))
+
+
 def test_state_and_argument_errors(gpu_lib):
     sl = H.rounded_slice(synth.small_slice(0))
     plan = gpjc.Plan.from_slice(sl)
