@@ -110,11 +110,17 @@ int gpjc_set_stream(gpjc_plan* plan, void* hip_stream);
  * K rows of U^H, times T (x) I_P with T = Q^{-1}, Psi = Q Q^H from
  * d_noise_cov [nc][nc] c64 (NULL = identity).  Outputs (optional):
  * h_eigvals [G][nc*P] descending, d_A_out [G][K][nc][P] c128.
- * Synchronises when h_eigvals is given.  Compressed plans only. */
+ * Synchronises.  Compressed plans only.  GPJC_E_NUMERIC if the Gram is not
+ * finite, the noise covariance is not positive definite, or the Jacobi
+ * sweeps do not reach off(H) <= 1e-13 ||H||_F within the sweep cap (40; the
+ * environment variable GPJC_JACOBI_SWEEP_CAP = 1..39 lowers it). */
 int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov,
                    double* h_eigvals, gpjc_c128* d_A_out);
 
-/* Install an externally computed bank d_A [G][K][nc][P] c128 (copied). */
+/* Install an externally computed bank d_A [G][K][nc][P] c128 (copied):
+ * the matrices A_g of Eq. 12 that Eqs. 13-14 apply, e.g. a bank exported by
+ * gpjc_calibrate (d_A_out) and reused, as the compression matrices are
+ * computed once and reused (Section 2.4).  d_A is 16-byte aligned. */
 int gpjc_set_compression(gpjc_plan* plan, const gpjc_c128* d_A);
 
 /* Eq. 13: d_ksp [B][nc][Ms][nt] c64 (acquired lines, ascending; 16-byte
@@ -162,12 +168,15 @@ int gpjc_gd_step(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x, con
 int gpjc_gd_step_backward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_g, const float* d_alpha,
                           const gpjc_c64* d_r, gpjc_c64* d_gx_out, gpjc_c64* d_gb_out, float* d_galpha_out);
 
-/* FISTA (Eq. 17 with the wavelet term, TV weight 0) on
+/* FISTA (Section 3.4, Eq. 17 with the wavelet term, TV weight 0) on
  * 1/2 ||E' x - y||^2 + lambda ||W x||_1, W the orthonormal separable Haar
  * transform with haar_levels levels (1..3, nx and ny divisible by
  * 2^levels; the final low-pass band is not penalised), step 1 / lipschitz,
  * x_0 = 0.  d_x [B][ny][nx] receives the last iterate.  h_obj [iters]
- * (optional) receives the objective after each iteration; synchronises. */
+ * (optional, iters <= 100001) receives the objective of each iterate x_k,
+ * accumulated in FP64 with a fixed reduction order; its data term applies
+ * E' in precision prec once more per iteration.  Synchronises at the end;
+ * GPJC_E_NUMERIC if the result holds NaN/Inf. */
 int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
                      double lambda, double lipschitz, int haar_levels, double* h_obj);
 

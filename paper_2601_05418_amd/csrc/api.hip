@@ -51,7 +51,7 @@ static int dalloc(T** p, size_t count) {
 static void free_plan(Plan* pl) {
   void* bufs[] = {pl->coils, pl->psf,  pl->psfp, pl->twin, pl->tw_x, pl->tw_y, pl->lines, pl->pgroup,
                   pl->maskf, pl->zeros, pl->A128, pl->Aexp, pl->AH,   pl->W,    pl->Zp,   pl->Zt,    pl->part,
-                  pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->red,  pl->hist,  pl->flag};
+                  pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->vd,   pl->red,  pl->hist,  pl->flag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int i = 0; i < 2; ++i) {
@@ -100,8 +100,6 @@ static int validate_geom(const gpjc_geom* g) {
 static int check_supported(const gpjc_geom* g) {
   if (!fft_size_supported(g->nx) || !fft_size_supported(g->ny))
     return fail(GPJC_E_UNSUPPORTED, "nx / ny must be one of the built FFT lengths");
-  if (g->compressed && (g->patch_len & 1))
-    return fail(GPJC_E_UNSUPPORTED, "odd patch_len is not built for the compressed operator");
   return GPJC_OK;
 }
 
@@ -201,6 +199,7 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
   GPJC_TRY(dalloc(&pl.vp, ni));
   GPJC_TRY(dalloc(&pl.vq, ni));
   GPJC_TRY(dalloc(&pl.vb, ni));
+  GPJC_TRY(dalloc(&pl.vd, pl.compressed ? (size_t)pl.B * pl.np * pl.K * pl.ms : (size_t)pl.B * pl.nc * pl.ms * pl.nt));
   GPJC_TRY(dalloc(&pl.red, 4096));
   pl.hist_cap = 100001;
   GPJC_TRY(dalloc(&pl.hist, (size_t)pl.hist_cap));
@@ -208,7 +207,10 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
   if (pl.compressed) {
     GPJC_TRY(dalloc(&pl.pgroup, (size_t)pl.np));
     GPJC_TRY(dalloc(&pl.A128, (size_t)pl.G * pl.K * pl.ns));
-    GPJC_TRY(dalloc(&pl.Aexp, (size_t)pl.G * 2 * pl.K * 2 * pl.ns));
+    // 16 floats of tail: with Ns odd, a contraction chunk at the end of the
+    // last row reads two floats past it (their data factor is zero)
+    GPJC_TRY(dalloc(&pl.Aexp, (size_t)pl.G * 2 * pl.K * 2 * pl.ns + 16));
+    GPJC_HIP(hipMemsetAsync(pl.Aexp + (size_t)pl.G * 2 * pl.K * 2 * pl.ns, 0, 16 * sizeof(float), stream));
     GPJC_TRY(dalloc(&pl.AH, (size_t)pl.G * 2 * pl.ns * 2 * pl.Kp));
     GPJC_TRY(dalloc(&pl.Zp, (size_t)kMaxKsplit * pl.B * pl.np * pl.K * pl.ny));
     GPJC_TRY(dalloc(&pl.Zt, (size_t)pl.B * pl.np * pl.ny * pl.Kp));
@@ -438,7 +440,7 @@ int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_
   if (haar_levels < 1 || haar_levels > 3) return fail(GPJC_E_UNSUPPORTED, "haar_levels must be 1, 2 or 3");
   const int t = 1 << haar_levels;
   if (plan->nx % t || plan->ny % t) return fail(GPJC_E_INVAL, "nx and ny must be divisible by 2^haar_levels");
-  if (h_obj) return fail(GPJC_E_UNSUPPORTED, "objective history is not built");
+  if (h_obj && iters > plan->hist_cap) return fail(GPJC_E_INVAL, "iters too large for the objective history");
   GPJC_TRY(check_bank(*plan));
   return finish(*plan, run_fista(*plan, st, reinterpret_cast<const float2*>(d_y), reinterpret_cast<float2*>(d_x),
                                  iters, lambda, lipschitz, haar_levels, h_obj));

@@ -820,7 +820,13 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
   const char* venv = std::getenv("GPJC_VERBOSE");
   const bool verbose = venv && venv[0] && venv[0] != '0';
   const double tol = 1e-13;
-  const int max_sweeps = 40;
+  // Sweep cap; GPJC_JACOBI_SWEEP_CAP (1..40) lowers it, so a caller can force
+  // the non-convergence status from the host.
+  int max_sweeps = 40;
+  if (const char* cap = std::getenv("GPJC_JACOBI_SWEEP_CAP")) {
+    const int c = std::atoi(cap);
+    if (c >= 1 && c < max_sweeps) max_sweeps = c;
+  }
   std::vector<double> hn((size_t)G * norm_blocks * 2);
   std::vector<int> act(G, 1);
   std::vector<double> th2(G, 0.0);

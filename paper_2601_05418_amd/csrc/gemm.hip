@@ -145,15 +145,31 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress(CompressArgs a) {
   // Masked-out operands are read from the zero buffer (the address is
   // selected, never the loaded value, so no load has to complete before
   // the MFMAs of the current block are issued).
+  // With P odd (FP32) a lane's four floats are two complex elements that may
+  // lie in two coils: the data operand is read as two 8-byte halves, the
+  // second at the next sample or the next coil's first one, or from the zero
+  // buffer at or past kend.
+  const bool odd = ST == Store::F32 && (twoP & 2);
   auto load = [&](floatx4(&xa)[MT], floatx4(&xb)[NT]) {
     const bool vk = kk < kend;
     const size_t kb_off = (size_t)n * coil_stride + jj;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
       xa[m] = *reinterpret_cast<const floatx4*>((va[m] && vk) ? arow[m] + kk : zeros);
+    if (odd) {
+      const bool vk1 = kk + 2 < kend;
+      const size_t kb1 = jj + 2 < twoP ? kb_off + 2 : kb_off + coil_stride - jj;
 #pragma unroll
-    for (int c = 0; c < NT; ++c)
-      xb[c] = *reinterpret_cast<const floatx4*>((vb[c] && vk) ? brow[c] + kb_off : zeros);
+      for (int c = 0; c < NT; ++c) {
+        const float2 h0 = *reinterpret_cast<const float2*>((vb[c] && vk) ? brow[c] + kb_off : zeros);
+        const float2 h1 = *reinterpret_cast<const float2*>((vb[c] && vk1) ? brow[c] + kb1 : zeros);
+        xb[c] = floatx4{h0.x, h0.y, h1.x, h1.y};
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        xb[c] = *reinterpret_cast<const floatx4*>((vb[c] && vk) ? brow[c] + kb_off : zeros);
+    }
   };
   // Ring of kDepth register buffers with compile-time indices: block s is
   // multiplied while blocks s+1 .. s+kDepth-1 are in flight.  Blocks past
@@ -200,6 +216,41 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress(CompressArgs a) {
         if (row + 2 < a.M) out[(size_t)((row >> 1) + 1) * a.N + col] = make_float2(acc[m][c][2], acc[m][c][3]);
       }
     }
+}
+
+// Writes four consecutive output floats src[0..3] of row y, starting at
+// float column col of the (n, j) index (two floats per complex column), to
+// W[b][n][y][p P + j].  With 2P a multiple of four they are one 16-byte
+// segment of one coil's patch.  With P odd (FP32 only) the two complex values
+// are stored one by one, each in its own coil, and a value at or past ncolf
+// (the floats of one row) is skipped.
+template <Store ST>
+__device__ inline void store_w_quad(void* W, const float* src, int b, int y, int col, int ncolf, int M, int nc,
+                                    int nt, int P, int p) {
+  const int twoP = 2 * P;
+  if constexpr (ST == Store::F32) {
+    if (twoP & 2) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = col + 2 * h;
+        if (c >= ncolf) break;
+        const int n = c / twoP, jj = c - n * twoP;
+        const size_t fi = (((size_t)b * nc + n) * M + y) * (size_t)nt * 2 + (size_t)p * twoP + jj;
+        *reinterpret_cast<float2*>(reinterpret_cast<float*>(W) + fi) = make_float2(src[2 * h], src[2 * h + 1]);
+      }
+      return;
+    }
+  }
+  const int n = col / twoP, jj = col - n * twoP;
+  const size_t fi = (((size_t)b * nc + n) * M + y) * (size_t)nt * 2 + (size_t)p * twoP + jj;
+  if constexpr (ST == Store::F32) {
+    *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
+  } else {
+    uint2 v;
+    v.x = to_bits16<ST>(src[0]) | (to_bits16<ST>(src[1]) << 16);
+    v.y = to_bits16<ST>(src[2]) | (to_bits16<ST>(src[3]) << 16);
+    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(W) + fi) = v;
+  }
 }
 
 struct ExpandArgs {
@@ -293,23 +344,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand(ExpandArgs a) {
       for (int r = 0; r < 4; ++r)
         tile[(wm * MT * 16 + 16 * m + 4 * lq + r) * LDT + wn * NT * 16 + 16 * c + li] = acc[m][c][r];
   __syncthreads();
-  const int twoP = 2 * a.P;
   const int rbase = tm * TM, cbase = tn * TN;
   for (int e = threadIdx.x; e < TM * (TN / 4); e += 64 * WM * WN) {
     const int rl = e / (TN / 4), cl = (e - rl * (TN / 4)) * 4;
     const int y = rbase + rl, col = cbase + cl;
     if (y >= a.M || col >= a.N) continue;
-    const int n = col / twoP, jj = col - n * twoP;
-    const size_t fi = (((size_t)b * a.nc + n) * a.M + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
-    const float* src = tile + rl * LDT + cl;
-    if constexpr (ST == Store::F32) {
-      *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(a.W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
-    } else {
-      uint2 v;
-      v.x = to_bits16<ST>(src[0]) | (to_bits16<ST>(src[1]) << 16);
-      v.y = to_bits16<ST>(src[2]) | (to_bits16<ST>(src[3]) << 16);
-      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.W) + fi) = v;
-    }
+    store_w_quad<ST>(a.W, tile + rl * LDT + cl, b, y, col, a.N, a.M, a.nc, a.nt, a.P, p);
   }
 }
 
@@ -331,6 +371,9 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t by
 }
 __device__ inline floatx4 bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+__device__ inline float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
 // MFMA geometry of the buffer-addressed forms: FP32 uses the 32 x 32 x 2
@@ -443,23 +486,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
       for (int r = 0; r < NR; ++r)
         tile[(wm * MT * T + T * m + G::row_of(r, lh)) * LDT + wn * NT * T + T * c + li] = acc[m][c][r];
   __syncthreads();
-  const int twoP = 2 * a.P;
   const int rbase = tm * TM, cbase = tn * TN;
   for (int e = threadIdx.x; e < TM * (TN / 4); e += 64 * WM * WN) {
     const int rl = e / (TN / 4), cl = (e - rl * (TN / 4)) * 4;
     const int y = rbase + rl, col = cbase + cl;
     if (y >= a.M || col >= a.N) continue;
-    const int n = col / twoP, jj = col - n * twoP;
-    const size_t fi = (((size_t)b * a.nc + n) * a.M + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
-    const float* src = tile + rl * LDT + cl;
-    if constexpr (ST == Store::F32) {
-      *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(a.W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
-    } else {
-      uint2 v;
-      v.x = to_bits16<ST>(src[0]) | (to_bits16<ST>(src[1]) << 16);
-      v.y = to_bits16<ST>(src[2]) | (to_bits16<ST>(src[3]) << 16);
-      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.W) + fi) = v;
-    }
+    store_w_quad<ST>(a.W, tile + rl * LDT + cl, b, y, col, a.N, a.M, a.nc, a.nt, a.P, p);
   }
 }
 
@@ -515,8 +547,9 @@ __device__ inline void block_mma(const floatx4 (&fa)[MT], const floatx4 (&fb)[NT
   }
 }
 
-template <int WM, int WN, int MT, int NT, int PF, Store ST>
+template <int WM, int WN, int MT, int NT, int PF, Store ST, bool ODD>
 __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
+  static_assert(!ODD || ST == Store::F32, "odd patch lengths are built for FP32 only");
   using G = Geo<ST>;
   using E = typename Mma<ST>::E;
   constexpr int T = G::T, NR = G::NR;
@@ -558,9 +591,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   const int kend = min(a.KD, kbeg + a.kchunk);
   const int nst = max(0, (kend - kbeg + KT - 1) / KT);
   // This thread's 16-byte chunk along the contraction: element kk of the
-  // (coil, in-patch sample) index, i.e. coil nn, sample jj.  A chunk never
-  // straddles a coil (2P is a multiple of the chunk); k-tiles may, so the
-  // coil advance is per thread.  Chunks at or past kend read zeros.
+  // (coil, in-patch sample) index, i.e. coil nn, sample jj.  With 2P a
+  // multiple of the chunk a chunk never straddles a coil; k-tiles may, so the
+  // coil advance is per thread.  Chunks at or past kend read zeros.  ODD (P
+  // odd, FP32): a chunk holds two complex elements that may lie in two
+  // coils, so the data operand is fetched as two 8-byte halves, the second
+  // at offset d1 from the first (the next sample, or the next coil's first
+  // one); a second half at or past kend reads zeros, and the bank's matching
+  // half then meets a zero factor.
   const int c16 = tid & 7;
   int kk = kbeg + (KT / 8) * c16;
   int jj = kk % twoP;
@@ -582,8 +620,19 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
     const bool in = kk < kend;
 #pragma unroll
     for (int r = 0; r < AR; ++r) xa[r] = bload(rA, in ? va[r] : kOOB);
+    if constexpr (ODD) {
+      const uint32_t d1 = (uint32_t)((jj + 2 < twoP ? (size_t)2 : cstride - (size_t)twoP + 2) * ES);
+      const bool in1 = kk + 2 < kend;
 #pragma unroll
-    for (int r = 0; r < BR; ++r) xb[r] = bload(rB, in ? vb[r] : kOOB);
+      for (int r = 0; r < BR; ++r) {
+        const float2 h0 = bload2(rB, in ? vb[r] : kOOB);
+        const float2 h1 = bload2(rB, in1 ? vb[r] + d1 : kOOB);
+        xb[r] = floatx4{h0.x, h0.y, h1.x, h1.y};
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < BR; ++r) xb[r] = bload(rB, in ? vb[r] : kOOB);
+    }
     kk += KT;
     jj += KT;
     uint32_t inc = KT * ES;
@@ -781,24 +830,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
         }
       }
   __syncthreads();
-  const int twoP = 2 * a.P;
   constexpr int TF = CF * TN;  // output tile width in floats
   const int rbase = tm * TM, cbase = CF * tn * TN, ncolf = CF * a.N;
   for (int e = tid; e < TM * (TF / 4); e += NTHR) {
     const int rl = e / (TF / 4), cl = (e - rl * (TF / 4)) * 4;
     const int y = rbase + rl, col = cbase + cl;
     if (y >= a.M || col >= ncolf) continue;
-    const int n = col / twoP, jj = col - n * twoP;
-    const size_t fi = (((size_t)b * a.nc + n) * a.M + y) * (size_t)a.nt * 2 + (size_t)p * twoP + jj;
-    const float* src = tile + rl * LDT + cl;
-    if constexpr (ST == Store::F32) {
-      *reinterpret_cast<floatx4*>(reinterpret_cast<float*>(a.W) + fi) = floatx4{src[0], src[1], src[2], src[3]};
-    } else {
-      uint2 v;
-      v.x = to_bits16<ST>(src[0]) | (to_bits16<ST>(src[1]) << 16);
-      v.y = to_bits16<ST>(src[2]) | (to_bits16<ST>(src[3]) << 16);
-      *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(a.W) + fi) = v;
-    }
+    store_w_quad<ST>(a.W, tile + rl * LDT + cl, b, y, col, ncolf, a.M, a.nc, a.nt, a.P, p);
   }
 }
 
@@ -872,7 +910,8 @@ constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
 int staged_ktile(Store st) { return st == Store::F32 ? 32 : 64; }
 bool compress_staged(const CompressArgs& a, Store st) {
   const size_t esz = st == Store::F32 ? 4 : 2;
-  return (2 * a.P) % (int)(16 / esz) == 0 && a.kchunk % staged_ktile(st) == 0 &&
+  // FP32 takes any P (odd P through the two-half data loads), 16-bit types 2P a multiple of 8
+  return (st == Store::F32 || (2 * a.P) % (int)(16 / esz) == 0) && a.kchunk % staged_ktile(st) == 0 &&
          (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB && (size_t)a.M * a.KD * esz < kOOB;
 }
 bool expand_uniform(const ExpandArgs& a, Store st) {
@@ -894,7 +933,15 @@ void launch_compress_v(hipStream_t s, const CompressArgs& a) {
     CompressArgs c = a;
     if (ST == Store::F32) c.M = a.K;  // complex rows of the three-multiplication form
     const dim3 grid(tiles(c.N, S.wn * S.nt * T) * tiles(c.M, S.wm * S.mt * T) * rest);
-    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, c);
+    if constexpr (ST == Store::F32) {
+      if (a.P & 1) {
+        hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, true>), grid, dim3(64 * S.wm * S.wn),
+                           0, s, c);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, false>), grid, dim3(64 * S.wm * S.wn), 0,
+                       s, c);
   } else {
     constexpr Shape S = kCompressGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);

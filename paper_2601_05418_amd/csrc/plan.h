@@ -99,6 +99,7 @@ struct Plan {
 
   // device: solver state
   float2 *vx = nullptr, *vr = nullptr, *vp = nullptr, *vq = nullptr, *vb = nullptr;
+  float2* vd = nullptr;     // one data vector (gpjc_forward's output layout): FISTA objective
   double* red = nullptr;    // reduction partials
   double* hist = nullptr;   // [hist_cap]
   int* flag = nullptr;      // numeric status flag

@@ -497,9 +497,97 @@ static int launch_fista_step(const Plan& pl, float invL, float thr, float mom) {
   return GPJC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// FISTA objective of an iterate x (Eq. 17 with the wavelet term, in the
+// 1/2 ||E' x - y||^2 + lambda ||W x||_1 form, final low-pass band not
+// penalised), accumulated in FP64 on the fixed reduction grid.
+// ---------------------------------------------------------------------------
+// partial sums of |d - y|^2 over the data vector
+__global__ __launch_bounds__(256) void k_resid2(const float2* __restrict__ d, const float2* __restrict__ y,
+                                                double* __restrict__ red, size_t n) {
+  __shared__ double sh[8];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float2 a = d[i], b = y[i];
+    const double re = (double)a.x - b.x, im = (double)a.y - b.y;
+    acc += re * re + im * im;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+// partial sums of |c| over the detail coefficients of W img (one 2^L x 2^L
+// tile per thread, tiles strided over the fixed grid)
+template <int LEV>
+__global__ __launch_bounds__(256) void k_wavelet_l1(const float2* __restrict__ img, int nx, int ny, int B,
+                                                    double* __restrict__ red) {
+  constexpr int S = 1 << LEV;
+  __shared__ double sh[8];
+  const int tx_n = nx / S, ty_n = ny / S;
+  const int ntiles = B * tx_n * ty_n;
+  double acc = 0.0;
+  for (int tile = blockIdx.x * blockDim.x + threadIdx.x; tile < ntiles; tile += gridDim.x * blockDim.x) {
+    const int b = tile / (tx_n * ty_n);
+    const int rem = tile - b * tx_n * ty_n;
+    const int ty = rem / tx_n, tx = rem - ty * tx_n;
+    float2 c[S][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) c[i][j] = img[((size_t)b * ny + ty * S + i) * nx + tx * S + j];
+    haar_tile<LEV>(c, false);
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+        if (i | j) acc += sqrt((double)c[i][j].x * c[i][j].x + (double)c[i][j].y * c[i][j].y);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+// *out = 1/2 sum(red_d) + lambda sum(red_w); single block
+__global__ void k_store_obj(const double* __restrict__ red_d, const double* __restrict__ red_w, int nb, double lambda,
+                            double* __restrict__ out) {
+  __shared__ double sh[8];
+  const double d = sum_partials(red_d, nb, sh);
+  const double w = sum_partials(red_w, nb, sh);
+  if (threadIdx.x == 0) *out = 0.5 * d + lambda * w;
+}
+
+__global__ __launch_bounds__(256) void k_norm2(const float2* __restrict__ v, double* __restrict__ red, size_t n);
+
+// *flag = 1 if the sum of the nb partials is not finite, else 0; single block
+__global__ void k_flag_nonfinite(const double* __restrict__ red, int nb, int* __restrict__ flag) {
+  __shared__ double sh[8];
+  const double s = sum_partials(red, nb, sh);
+  if (threadIdx.x == 0) *flag = isfinite(s) ? 0 : 1;
+}
+
+static size_t data_elems(const Plan& pl) {
+  return pl.compressed ? (size_t)pl.B * pl.np * pl.K * pl.ms : (size_t)pl.B * pl.nc * pl.ms * pl.nt;
+}
+
+// Objective of x = pl.vx into *out (device): forward application into pl.vd,
+// then the two reductions.
+static int fista_objective(const Plan& pl, Store st, const float2* y, int levels, double lambda, double* out) {
+  GPJC_TRY(op_forward(pl, st, pl.vx, pl.vd));
+  const int nb = kRedBlocks;
+  double* red_d = pl.red;
+  double* red_w = pl.red + nb;
+  hipLaunchKernelGGL(k_resid2, dim3(nb), dim3(256), 0, pl.stream, pl.vd, y, red_d, data_elems(pl));
+  switch (levels) {
+    case 1: hipLaunchKernelGGL(k_wavelet_l1<1>, dim3(nb), dim3(256), 0, pl.stream, pl.vx, pl.nx, pl.ny, pl.B, red_w); break;
+    case 2: hipLaunchKernelGGL(k_wavelet_l1<2>, dim3(nb), dim3(256), 0, pl.stream, pl.vx, pl.nx, pl.ny, pl.B, red_w); break;
+    default: hipLaunchKernelGGL(k_wavelet_l1<3>, dim3(nb), dim3(256), 0, pl.stream, pl.vx, pl.nx, pl.ny, pl.B, red_w); break;
+  }
+  hipLaunchKernelGGL(k_store_obj, dim3(1), dim3(256), 0, pl.stream, red_d, red_w, nb, lambda, out);
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
 int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lip, int levels,
               double* h_obj) {
-  (void)h_obj;
   const size_t n = pl.img_elems();
   GPJC_TRY(op_adjoint_part(pl, st, y));
   GPJC_TRY(launch_combine(pl, pl.vb));
@@ -518,8 +606,19 @@ int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double 
       case 2: GPJC_TRY(launch_fista_step<2>(pl, invL, thr, mom)); break;
       default: GPJC_TRY(launch_fista_step<3>(pl, invL, thr, mom)); break;
     }
+    if (h_obj) GPJC_TRY(fista_objective(pl, st, y, levels, lambda, pl.hist + it));
   }
-  return copy_vec(pl, pl.vx, x, n);
+  GPJC_TRY(copy_vec(pl, pl.vx, x, n));
+  // numeric status: the squared norm of the result, summed in FP64, must be finite
+  hipLaunchKernelGGL(k_norm2, dim3(kRedBlocks), dim3(256), 0, pl.stream, pl.vx, pl.red, n);
+  hipLaunchKernelGGL(k_flag_nonfinite, dim3(1), dim3(256), 0, pl.stream, pl.red, kRedBlocks, pl.flag);
+  GPJC_HIP(hipGetLastError());
+  int flag = 0;
+  GPJC_HIP(hipMemcpyAsync(&flag, pl.flag, sizeof(int), hipMemcpyDeviceToHost, pl.stream));
+  if (h_obj) GPJC_HIP(hipMemcpyAsync(h_obj, pl.hist, sizeof(double) * iters, hipMemcpyDeviceToHost, pl.stream));
+  GPJC_HIP(hipStreamSynchronize(pl.stream));
+  if (flag) return fail(GPJC_E_NUMERIC, "FISTA: non-finite iterate");
+  return GPJC_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -281,12 +281,16 @@ class Plan:
                                       None if hist is None else hist.ctypes.data_as(ctypes.c_void_p)))
         return (x, hist) if want_resid else x
 
-    def recon_fista(self, y, iters, lam, lipschitz, levels=3, prec="fp32", out=None):
+    def recon_fista(self, y, iters, lam, lipschitz, levels=3, prec="fp32", out=None, want_obj=False):
+        """FISTA-L1; with want_obj also the objective after every iteration
+        (returns (x, objectives))."""
         x = self._empty(self.image_shape()) if out is None else out
+        obj = np.zeros(int(iters), np.float64) if want_obj else None
         self._begin()
         _check(self.lib.gpjc_recon_fista(self.handle, _prec(prec), self._in(y), _ptr(x), int(iters), float(lam),
-                                         float(lipschitz), int(levels), None))
-        return x
+                                         float(lipschitz), int(levels),
+                                         None if obj is None else obj.ctypes.data_as(ctypes.c_void_p)))
+        return (x, obj) if want_obj else x
 
     def power_iteration(self, x0, iters=50, prec="fp32"):
         self._begin()

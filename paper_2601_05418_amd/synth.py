@@ -230,7 +230,7 @@ def unrolled_slices(batch: int = 8, seed: int = 0) -> List[Slice]:
 
 def batch_draws(n_slices: int = 64, seed: int = 0) -> List[Slice]:
     """Uneven slices: N in {128..256 step 32}, Nc in {16, 24, 32}, os 6 or 8,
-    patch length an even divisor of nt in [16, 48] with 16-96 patches, K such
+    patch length any divisor of nt in [16, 48] with 16-96 patches, K such
     that the compression factor is U(12, 20), R in {3, 4, 5} with 8
     calibration lines, wave 7 cycles / +-6 rad, one group per patch."""
     rs = _streams(4, seed)
@@ -241,7 +241,7 @@ def batch_draws(n_slices: int = 64, seed: int = 0) -> List[Slice]:
         nc = int(draw.choice([16, 24, 32]))
         os_ = int(draw.choice([6, 8]))
         nt = os_ * n
-        cands = [p for p in range(16, 49, 2) if nt % p == 0 and 16 <= nt // p <= 96]
+        cands = [p for p in range(16, 49) if nt % p == 0 and 16 <= nt // p <= 96]
         p = int(draw.choice(cands))
         f = float(draw.uniform(12.0, 20.0))
         k = max(1, int(round(nc * p / f)))

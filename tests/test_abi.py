@@ -53,7 +53,6 @@ FAKE = ctypes.c_void_p(0x100000)  # never dereferenced: validation fails first
     (dict(batch=0), gpjc.GPJC_E_INVAL),
     (dict(os=1 << 20), gpjc.GPJC_E_INVAL),         # os * nx overflows the int sample count
     (dict(nx=22, ny=22, os=2, patch_len=4, n_groups=11), gpjc.GPJC_E_UNSUPPORTED),  # FFT length 22 not built
-    (dict(patch_len=1, n_groups=256, k=4), gpjc.GPJC_E_UNSUPPORTED),  # odd patch length
 ])
 def test_invalid_geometry(over, code):
     lib = gpjc.load()

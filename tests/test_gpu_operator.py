@@ -4,6 +4,8 @@ Bound: relative L2 <= 1e-5 per FP32 application, and every element within
 1e-5 of the largest reference magnitude.  Inputs are rounded to complex64
 once and the oracle receives the same rounded values.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -221,3 +223,93 @@ def test_runtime_is_torchs(gpu_lib):
     import os
     path = gpjc.runtime_path()
     assert os.path.dirname(os.path.realpath(path)) == os.path.dirname(os.path.realpath(torch.__file__)) + "/lib", path
+
+
+# Odd patch lengths: a contraction chunk of two complex samples may span two
+# coils (P odd), and with Ns = Nc P odd the contraction ends mid-chunk.
+ODD_CASES = {
+    # P = 9, Nc = 3: Ns = 27 odd; 16 patches, ragged 2K = 14
+    "odd9": lambda: synth._make_rect(0, nx=48, ny=32, nc=3, os_=3, patch_len=9, k=7, accel=3, acs=6, cycles=3,
+                                     phase_max=2.0),
+    # P = 3: a 16-sample k-tile crosses five coils; Ns = 15 odd
+    "odd3": lambda: synth._make_rect(1, nx=32, ny=48, nc=5, os_=3, patch_len=3, k=4, accel=2, acs=4, cycles=2,
+                                     phase_max=1.5),
+    # P = 21, Nc = 4: Ns = 84 even, but chunks still straddle coils
+    "odd21": lambda: synth._make_rect(2, nx=112, ny=64, nc=4, os_=3, patch_len=21, k=9, accel=3, acs=6,
+                                      cycles=3, phase_max=2.0),
+}
+
+
+@pytest.mark.parametrize("bank", ["oracle", "random"])
+@pytest.mark.parametrize("case", list(ODD_CASES))
+def test_odd_patch_length(gpu_lib, case, bank):
+    """Forward, adjoint, normal and data compression with an odd patch
+    length (any divisor of Nt forms a partition, Section 2.3), every element
+    against the oracle."""
+    sl = H.rounded_slice(ODD_CASES[case]())
+    g = sl.geom
+    assert g.patch_len % 2 == 1 and g.nt % g.patch_len == 0
+    a = H.oracle_bank(sl)[0] if bank == "oracle" else H.random_bank(g, seed=5)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    rng = np.random.default_rng(21)
+    x = H.round64(H.crandn(rng, (1, g.ny, g.nx)))
+    check(host(plan.forward(dev(x)))[0], ops["fwd"](x[0]))
+    y = H.round64(H.crandn(rng, plan.data_shape()))
+    check(host(plan.adjoint(dev(y)))[0], ops["adj"](y[0]))
+    check(host(plan.normal(dev(x)))[0], ops["nrm"](x[0]))
+    s_acq = H.round64(H.crandn(rng, (g.nc, g.ms, g.nt)))
+    check(host(plan.compress(dev(s_acq[None])))[0], oc.compress(s_acq, a, g.patch_group, g.patch_len))
+
+
+def test_odd_patch_length_batched_images(gpu_lib):
+    sl = H.rounded_slice(ODD_CASES["odd9"]())
+    g = sl.geom
+    a = H.random_bank(g, seed=6)
+    plan = gpjc.Plan.from_slice(sl, batch=3)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(H.crandn(np.random.default_rng(22), (3, g.ny, g.nx)))
+    n = host(plan.normal(dev(x)))
+    for b in range(3):
+        check(n[b], ops["nrm"](x[b]))
+
+
+def test_odd_patch_length_highfield_full_size(gpu_lib):
+    """224 x 224, 32 coils, os 6 (1344 samples) cut into 64 patches of
+    P = 21 (Ns = 672, K = 42: 16x), the odd divisor of 1344 that the uneven
+    batch's patch-length draw admits: forward, adjoint and normal operator in
+    the default launch configuration, every element against the oracle
+    (random orthonormal bank)."""
+    base = synth.highfield_slice(0)
+    g0 = base.geom
+    np_ = g0.nt // 21
+    geom = dataclasses.replace(g0, patch_len=21, patch_group=synth.sequential_groups(np_), n_groups=np_, k=42)
+    sl = H.rounded_slice(dataclasses.replace(base, geom=geom))
+    g = sl.geom
+    a = H.random_bank(g, seed=17)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(sl.image)[None]
+    check(host(plan.forward(dev(x)))[0], ops["fwd"](x[0]))
+    y = H.round64(H.crandn(np.random.default_rng(18), plan.data_shape()))
+    check(host(plan.adjoint(dev(y)))[0], ops["adj"](y[0]))
+    check(host(plan.normal(dev(x)))[0], ops["nrm"](x[0]))
+
+
+def test_highfield_normal_full_size(gpu_lib):
+    """E'^H E' in FP32 on the benchmark's slice and launch configuration
+    (224 x 224, 32 coils, 42 groups of 32, K = 64; the compressing
+    contraction's default k-split and the fused phase-encode stage for
+    Ny = 224), every element against the oracle (random orthonormal bank)."""
+    sl = H.rounded_slice(synth.highfield_slice(0))
+    a = H.random_bank(sl.geom, seed=19)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    cfg = plan.gemm_config("fp32")
+    print(f"gemm config {cfg}", flush=True)
+    ops = H.oracle_ops(sl, a)
+    x = H.round64(sl.image)[None]
+    check(host(plan.normal(dev(x)))[0], ops["nrm"](x[0]))
