@@ -117,6 +117,19 @@ int gpjc_set_stream(gpjc_plan* plan, void* hip_stream);
 int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov,
                    double* h_eigvals, gpjc_c128* d_A_out);
 
+/* gpjc_calibrate for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with every calibration workspace carved
+ * from a static device array of 64 MiB (one per GPU, held by the library
+ * until the process ends) instead of being allocated.  Allocates nothing.
+ * GPJC_E_UNSUPPORTED (before anything is queued) if the workspaces exceed
+ * 64 MiB: about 16 groups of Ns = 128 (the 64 x 64, 8-coil slice) fit,
+ * high-field slices do not.  Calls that overlap on one GPU share the array
+ * and race; the array keeps the last call's contents, and every part a call
+ * reads is written by that call first. */
+int gpjc_calibrate_static(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov,
+                          double* h_eigvals, gpjc_c128* d_A_out);
+
 /* Install an externally computed bank d_A [G][K][nc][P] c128 (copied):
  * the matrices A_g of Eq. 12 that Eqs. 13-14 apply, e.g. a bank exported by
  * gpjc_calibrate (d_A_out) and reused, as the compression matrices are

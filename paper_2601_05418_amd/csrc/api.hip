@@ -332,6 +332,14 @@ int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_nois
                                      reinterpret_cast<double2*>(d_A_out)));
 }
 
+int gpjc_calibrate_static(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov, double* h_eigvals,
+                          gpjc_c128* d_A_out) {
+  GPJC_TRY(check_plan(plan));
+  if (!plan->compressed) return fail(GPJC_E_INVAL, "calibration needs a compressed plan");
+  return finish(*plan, run_calibrate_static(*plan, d_roi, reinterpret_cast<const float2*>(d_noise_cov), h_eigvals,
+                                            reinterpret_cast<double2*>(d_A_out)));
+}
+
 int gpjc_set_compression(gpjc_plan* plan, const gpjc_c128* d_A) {
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "compression bank needs a compressed plan");

@@ -39,6 +39,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "fft.h"
@@ -732,7 +734,14 @@ int dmalloc(T** p, size_t n) {
   return GPJC_OK;
 }
 
+// Calibration workspaces.  Three modes: device allocations freed when the
+// call returns (the default); carving from a caller-provided region (arena,
+// 256-byte aligned pieces, nothing allocated); or measuring only (no arena,
+// measure set: pointers stay null and `used` totals the bytes an arena needs).
 struct Scratch {
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
+  bool measure = false;
   std::vector<void*> ptrs;
   ~Scratch() {
     for (void* p : ptrs) (void)hipFree(p);
@@ -740,43 +749,75 @@ struct Scratch {
   template <class T>
   int alloc(T** p, size_t n) {
     *p = nullptr;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (arena || measure) {
+      const size_t off = (used + 255) / 256 * 256;
+      used = off + bytes;
+      if (measure) return GPJC_OK;
+      if (used > cap) return fail(GPJC_E_UNSUPPORTED, "calibration workspace exceeds the static scratch");
+      *p = reinterpret_cast<T*>(arena + off);
+      return GPJC_OK;
+    }
     GPJC_TRY(dmalloc(p, std::max<size_t>(n, 1)));
     ptrs.push_back(*p);
     return GPJC_OK;
   }
 };
 
+// Workspace pointers of one calibration.
+struct CalibBufs {
+  double2 *T = nullptr, *Lc = nullptr, *cw, *ph, *Qg, *H, *U, *V, *rowbuf;
+  double *wc, *qinv, *norms, *eigd, *thr2;
+  int *t0s, *active, *rot, *flag;
+};
+constexpr int kNormBlocks = 64;
+
+int alloc_calib(Scratch& s, const Plan& pl, bool whiten, CalibBufs& b) {
+  const int G = pl.G, ns = pl.ns, P = pl.P;
+  const int npix = pl.nx * pl.ny;
+  const int nsp = (ns + kPair - 1) / kPair * kPair;
+  const int npair = nsp / kBlk / 2;
+  const int nd = 2 * P - 1;
+  GPJC_TRY(s.alloc(&b.cw, (size_t)pl.nc * npix));
+  GPJC_TRY(s.alloc(&b.wc, (size_t)npix));
+  GPJC_TRY(s.alloc(&b.ph, (size_t)nd * pl.nx));
+  GPJC_TRY(s.alloc(&b.Qg, (size_t)pl.nc * pl.nc * pl.ny * nd));
+  GPJC_TRY(s.alloc(&b.qinv, (size_t)G * pl.ny));
+  GPJC_TRY(s.alloc(&b.t0s, (size_t)G));
+  GPJC_TRY(s.alloc(&b.H, (size_t)G * nsp * nsp));
+  GPJC_TRY(s.alloc(&b.U, (size_t)G * nsp * nsp));
+  GPJC_TRY(s.alloc(&b.V, (size_t)G * npair * kPair * kPair));
+  GPJC_TRY(s.alloc(&b.active, (size_t)G));
+  GPJC_TRY(s.alloc(&b.thr2, (size_t)G));
+  GPJC_TRY(s.alloc(&b.rot, (size_t)G * npair));
+  GPJC_TRY(s.alloc(&b.flag, 1));
+  GPJC_TRY(s.alloc(&b.eigd, (size_t)G * ns));
+  GPJC_TRY(s.alloc(&b.rowbuf, (size_t)G * ns));
+  GPJC_TRY(s.alloc(&b.norms, (size_t)G * kNormBlocks * 2));
+  if (whiten) {
+    GPJC_TRY(s.alloc(&b.Lc, (size_t)pl.nc * pl.nc));
+    GPJC_TRY(s.alloc(&b.T, (size_t)pl.nc * pl.nc));
+  }
+  return GPJC_OK;
+}
+
 }  // namespace
 
-int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out) {
+static int calibrate_in(Plan& pl, Scratch& s, const uint8_t* roi, const float2* noise_cov, double* h_eig,
+                        double2* A_out) {
   const int G = pl.G, ns = pl.ns, P = pl.P;
   const int npix = pl.nx * pl.ny;
   const int nsp = (ns + kPair - 1) / kPair * kPair;
   const int nb = nsp / kBlk;
   const int npair = nb / 2;
-  Scratch s;
-  double2 *T = nullptr, *Lc = nullptr, *cw, *ph, *Qg, *H, *U, *V, *rowbuf;
-  double *wc, *qinv, *norms, *eigd;
-  double* thr2;
-  int *t0s, *active, *rot, *flag;
-  GPJC_TRY(s.alloc(&cw, (size_t)pl.nc * npix));
-  GPJC_TRY(s.alloc(&wc, (size_t)npix));
+  CalibBufs bufs;
+  GPJC_TRY(alloc_calib(s, pl, noise_cov != nullptr, bufs));
+  double2 *T = bufs.T, *Lc = bufs.Lc, *cw = bufs.cw, *ph = bufs.ph, *Qg = bufs.Qg, *H = bufs.H, *U = bufs.U,
+          *V = bufs.V, *rowbuf = bufs.rowbuf;
+  double *wc = bufs.wc, *qinv = bufs.qinv, *norms = bufs.norms, *eigd = bufs.eigd, *thr2 = bufs.thr2;
+  int *t0s = bufs.t0s, *active = bufs.active, *rot = bufs.rot, *flag = bufs.flag;
   const int nd = 2 * P - 1;
-  GPJC_TRY(s.alloc(&ph, (size_t)nd * pl.nx));
-  GPJC_TRY(s.alloc(&Qg, (size_t)pl.nc * pl.nc * pl.ny * nd));
-  GPJC_TRY(s.alloc(&qinv, (size_t)G * pl.ny));
-  GPJC_TRY(s.alloc(&t0s, (size_t)G));
-  GPJC_TRY(s.alloc(&H, (size_t)G * nsp * nsp));
-  GPJC_TRY(s.alloc(&U, (size_t)G * nsp * nsp));
-  GPJC_TRY(s.alloc(&V, (size_t)G * npair * kPair * kPair));
-  GPJC_TRY(s.alloc(&active, (size_t)G));
-  GPJC_TRY(s.alloc(&thr2, (size_t)G));
-  GPJC_TRY(s.alloc(&rot, (size_t)G * npair));
-  GPJC_TRY(s.alloc(&flag, 1));
-  GPJC_TRY(s.alloc(&eigd, (size_t)G * ns));
-  GPJC_TRY(s.alloc(&rowbuf, (size_t)G * ns));
-  const int norm_blocks = 64;
-  GPJC_TRY(s.alloc(&norms, (size_t)G * norm_blocks * 2));
+  const int norm_blocks = kNormBlocks;
   hipStream_t st = pl.stream;
 
   std::vector<int> t0h(G, -1);
@@ -788,8 +829,6 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
   GPJC_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
 
   if (noise_cov) {
-    GPJC_TRY(s.alloc(&Lc, (size_t)pl.nc * pl.nc));
-    GPJC_TRY(s.alloc(&T, (size_t)pl.nc * pl.nc));
     hipLaunchKernelGGL(k_whiten_factor, dim3(1), dim3(256), 0, st, noise_cov, Lc, T, pl.nc, flag);
     GPJC_HIP(hipGetLastError());
   }
@@ -895,6 +934,57 @@ int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double*
   if (h_eig) GPJC_HIP(hipMemcpyAsync(h_eig, eigd, sizeof(double) * (size_t)G * ns, hipMemcpyDeviceToHost, st));
   GPJC_HIP(hipStreamSynchronize(st));
   return GPJC_OK;
+}
+
+int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out) {
+  Scratch s;  // device allocations, freed on return
+  return calibrate_in(pl, s, roi, noise_cov, h_eig, A_out);
+}
+
+// ---------------------------------------------------------------------------
+// Calibration without device allocation: the workspaces are carved from a
+// file-scope device array of kStaticScratchBytes.  Each GPU holds its own copy
+// until the process ends; its address on a device comes from
+// hipGetSymbolAddress, taken once per device with that device current (in
+// host code the array's name is not a device address).  Calls that overlap on
+// one GPU share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+static int static_scratch(int device, char** out) {
+  if (device < 0 || device >= 64) return fail(GPJC_E_UNSUPPORTED, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    GPJC_HIP(hipGetDevice(&cur));
+    if (cur != device) GPJC_HIP(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) GPJC_HIP(hipSetDevice(cur));
+    if (e != hipSuccess || !ptr)
+      return fail(GPJC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[device]);
+  return GPJC_OK;
+}
+
+int run_calibrate_static(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out) {
+  Scratch need;
+  need.measure = true;
+  CalibBufs dummy;
+  GPJC_TRY(alloc_calib(need, pl, noise_cov != nullptr, dummy));
+  if (need.used > kStaticScratchBytes)
+    return fail(GPJC_E_UNSUPPORTED, "calibration needs " + std::to_string(need.used) +
+                                        " bytes of workspace; the static scratch holds " +
+                                        std::to_string(kStaticScratchBytes));
+  Scratch s;
+  GPJC_TRY(static_scratch(pl.device, &s.arena));
+  s.cap = kStaticScratchBytes;
+  return calibrate_in(pl, s, roi, noise_cov, h_eig, A_out);
 }
 
 }  // namespace gpjc

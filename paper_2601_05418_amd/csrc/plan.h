@@ -160,6 +160,10 @@ int op_normal_part(const Plan& pl, Store st, const float2* img);  // result in p
 
 // ---- calibration (calib.hip) ----
 int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out);
+// The same calibration with its workspaces in the library's static device
+// scratch (kStaticScratchBytes per GPU): no device allocation.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+int run_calibrate_static(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out);
 
 // ---- solvers (solver.hip) ----
 int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid);

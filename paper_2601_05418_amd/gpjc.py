@@ -60,6 +60,7 @@ _SIGS = {
     "gpjc_plan_destroy": (_I, [_VP]),
     "gpjc_set_stream": (_I, [_VP, _VP]),
     "gpjc_calibrate": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "gpjc_calibrate_static": (_I, [_VP, _VP, _VP, _VP, _VP]),
     "gpjc_set_compression": (_I, [_VP, _VP]),
     "gpjc_compress": (_I, [_VP, _VP, _VP]),
     "gpjc_forward": (_I, [_VP, _I, _VP, _VP]),
@@ -242,6 +243,18 @@ class Plan:
         _check(self.lib.gpjc_calibrate(self.handle, _ptr(roi_t), _ptr(cov_t),
                                        None if eig is None else eig.ctypes.data_as(ctypes.c_void_p),
                                        _ptr(bank)))
+        return eig, bank
+
+    def calibrate_static(self, roi=None, noise_cov=None, want_eigvals=False, want_bank=False):
+        """calibrate() through gpjc_calibrate_static: the workspaces live in
+        the library's static device scratch, nothing is allocated."""
+        roi_t = None if roi is None else _dev_tensor(np.asarray(roi, np.uint8), torch.uint8, self.device)
+        cov_t = None if noise_cov is None else _dev_tensor(noise_cov, torch.complex64, self.device)
+        eig = np.zeros((self.n_groups, self.ns), np.float64) if want_eigvals else None
+        bank = self._empty((self.n_groups, self.k, self.nc, self.patch_len), torch.complex128) if want_bank else None
+        _check(self.lib.gpjc_calibrate_static(self.handle, _ptr(roi_t), _ptr(cov_t),
+                                              None if eig is None else eig.ctypes.data_as(ctypes.c_void_p),
+                                              _ptr(bank)))
         return eig, bank
 
     def set_compression(self, bank):
