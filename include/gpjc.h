@@ -56,11 +56,12 @@ typedef struct { double re, im; } gpjc_c128;
  * product from three real products).  BF16 / FP16 (compressed plans with
  * patch_len % 4 == 0, else GPJC_E_UNSUPPORTED): the operands of both group
  * contractions are rounded to BF16 / FP16 (round to nearest even) and
- * contracted on MFMA with FP32 accumulation -- the compression matrices, the
- * hybrid data W after the PSF product (forward) and after the expanding
- * contraction (adjoint), and the phase-encode output Z^T feeding the
- * expanding contraction.  FFTs, coil products and the phase-encode stage
- * compute in FP32.  FP16 needs every stored value below 65504 in magnitude
+ * contracted on MFMA with FP32 accumulation -- the compression matrices and
+ * the hybrid data W after the PSF product (forward) and after the expanding
+ * contraction (adjoint).  The phase-encode output Z^T feeding the expanding
+ * contraction is carried as a hi + lo pair of 16-bit values (hi = rn(z),
+ * lo = rn(z - hi)), so it adds almost no rounding of its own.  FFTs, coil
+ * products and the phase-encode stage compute in FP32.  FP16 needs every stored value below 65504 in magnitude
  * (non-finite results surface as GPJC_E_NUMERIC in the solvers). */
 typedef enum { GPJC_FP32 = 0, GPJC_BF16 = 1, GPJC_FP16 = 2 } gpjc_prec;
 

@@ -220,8 +220,8 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
         GPJC_TRY(dalloc(&pl.Aexp16[i], (size_t)pl.G * 2 * pl.K * 2 * pl.ns));
         GPJC_TRY(dalloc(&pl.AH16[i], (size_t)pl.G * 2 * pl.ns * 2 * pl.Kp));
       }
-      GPJC_TRY(dalloc(&pl.Zt16, (size_t)pl.B * pl.np * pl.ny * pl.Kp));
-      GPJC_HIP(hipMemsetAsync(pl.Zt16, 0, sizeof(uint32_t) * (size_t)pl.B * pl.np * pl.ny * pl.Kp, stream));
+      GPJC_TRY(dalloc(&pl.Zt16, (size_t)pl.B * pl.np * pl.ny * 2 * pl.Kp));
+      GPJC_HIP(hipMemsetAsync(pl.Zt16, 0, sizeof(uint32_t) * (size_t)pl.B * pl.np * pl.ny * 2 * pl.Kp, stream));
     }
     GPJC_HIP(hipMemcpyAsync(pl.pgroup, pl.pgroup_h.data(), sizeof(int) * pl.np, hipMemcpyHostToDevice, stream));
   }

@@ -39,6 +39,28 @@ __device__ inline void store_c(void* base, size_t i, float2 v) {
   }
 }
 template <Store ST>
+__device__ inline float from_bits16(uint32_t h) {
+  if constexpr (ST == Store::BF16) return bf16_bits_to_f32(h);
+  else return f16_bits_to_f32(h);
+}
+
+// Element k of Z^T row `row` (rows of kp complex values).  FP32 as is; the
+// 16-bit types as a hi + lo pair, hi = rn(v) and lo = rn(v - hi), in a row of
+// 2 kp pairs: hi at k, lo at kp + k.
+template <Store ST>
+__device__ inline void store_zt(void* Zt, size_t row, int kp, int k, float2 v) {
+  if constexpr (ST == Store::F32) {
+    reinterpret_cast<float2*>(Zt)[row * kp + k] = v;
+  } else {
+    const uint32_t hr = to_bits16<ST>(v.x), hi = to_bits16<ST>(v.y);
+    const float lr = v.x - from_bits16<ST>(hr), li = v.y - from_bits16<ST>(hi);
+    uint32_t* z = reinterpret_cast<uint32_t*>(Zt) + row * 2 * kp;
+    z[k] = hr | (hi << 16);
+    z[kp + k] = to_bits16<ST>(lr) | (to_bits16<ST>(li) << 16);
+  }
+}
+
+template <Store ST>
 __device__ inline float2 load_c(const void* base, size_t i) {
   if constexpr (ST == Store::F32) {
     return reinterpret_cast<const float2*>(base)[i];

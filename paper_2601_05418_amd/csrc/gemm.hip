@@ -10,21 +10,22 @@
 // complex row (compressing) and [Ar, Ai], [-Ai, Ar] per complex column
 // (expanding).  Two ways of forming the complex product:
 // - expanded: one real product with the expanded bank, four real
-//   multiplications per complex one (16-bit types, register-direct and
-//   general forms);
+//   multiplications per complex one (16-bit types and the general forms);
 // - three-multiplication (FP32 LDS-staged forms): only the first expanded
 //   row of each pair is read, conj(A) (compressing) or A (expanding), and
 //   three real products t1, t2, t3 are combined at the end (block_mma).
 //
-// Three families of kernels, chosen per launch:
+// In the 16-bit expanding contraction the phase-encode output Z^T is carried
+// as a hi + lo pair of 16-bit values (hi = rn(z), lo = rn(z - hi)): its rows
+// hold both parts one after the other and meet the same bank row twice, so
+// Z^T adds no rounding beyond the bank's and W's.
+//
+// Two families of kernels, chosen per launch:
 // - LDS-staged (k_compress_lds, k_expand_lds): the work-group loads k-tiles of
 //   one 128-byte line per row cooperatively into LDS and the waves read their
 //   MFMA fragments from there; 32x32x2 FP32 in the three-multiplication form,
-//   or 16x16x32 BF16 / FP16 with FP32 accumulation.  Every geometry of the
-//   compressing contraction, and the expanding one when 2 Kp is a whole
-//   number of k-tiles.
-// - Buffer-addressed register-direct (k_expand_u): each lane loads its own
-//   operand fragments, 16 bytes per lane and block, a few blocks ahead.
+//   or 16x16x32 BF16 / FP16 with FP32 accumulation.  Every geometry whose
+//   operands stay below 2 GiB.
 // - General (k_compress, k_expand): per-lane addressing with masks, for
 //   operands of 2 GiB or more.  In a block of 16 kk (FP32,
 //   v_mfma_f32_16x16x4_f32) lane (i, q) (i = lane % 16, q = lane / 16) holds
@@ -254,12 +255,16 @@ __device__ inline void store_w_quad(void* W, const float* src, int b, int y, int
 }
 
 struct ExpandArgs {
-  const void* Zt;   // [B][np][M][KD] elements, M = ny, KD = 2 kp
-  const void* AH;   // [G][N][KD], N = 2 ns
+  const void* Zt;   // [B][np][M][KD] elements, M = ny; KD = 2 kp (FP32) or 4 kp (16-bit hi | lo)
+  const void* AH;   // [G][N][KDB], N = 2 ns, KDB = 2 kp
   void* W;          // [B][nc][ny][nt] complex (storage per Store)
   const int* pgroup;
   const void* zeros;
-  int M, N, KD, nc, nt, P, np, B;  // the FP32 staged form is launched with N = ns
+  int M, N, KD, KDB, nc, nt, P, np, B;  // the FP32 staged form is launched with N = ns
+  // 16-bit: Z^T rows hold a hi part and a lo part of 2 kp elements each, and
+  // both meet the same bank row: contraction element kk reads bank element
+  // kk - kwrap once kk >= kwrap (kwrap = 2 kp; 0 = no wrap).
+  int kwrap;
 };
 
 template <int WM, int WN, int MT, int NT, Store ST>
@@ -299,7 +304,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand(ExpandArgs a) {
   for (int c = 0; c < NT; ++c) {
     const int cc = col0 + 16 * c + li;
     vb[c] = cc < a.N;
-    brow[c] = Hb + ((size_t)g * a.N + (vb[c] ? cc : 0)) * a.KD;
+    brow[c] = Hb + ((size_t)g * a.N + (vb[c] ? cc : 0)) * a.KDB;
   }
   floatx4 acc[MT][NT];
 #pragma unroll
@@ -309,12 +314,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand(ExpandArgs a) {
   int kk = LW * lq;
   auto load = [&](floatx4(&xa)[MT], floatx4(&xb)[NT]) {
     const bool vk = kk < a.KD;
+    const int kb = (a.kwrap && kk >= a.kwrap) ? kk - a.kwrap : kk;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
       xa[m] = *reinterpret_cast<const floatx4*>((va[m] && vk) ? arow[m] + kk : zeros);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
-      xb[c] = *reinterpret_cast<const floatx4*>((vb[c] && vk) ? brow[c] + kk : zeros);
+      xb[c] = *reinterpret_cast<const floatx4*>((vb[c] && vk) ? brow[c] + kb : zeros);
   };
   floatx4 ra[kDepth][MT], rb[kDepth][NT];
 #pragma unroll
@@ -354,15 +360,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand(ExpandArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Buffer-addressed forms.  Each lane's operand rows are fixed for the whole
-// contraction, so a lane keeps one 32-bit byte offset per operand tile and
-// every block adds the same (wave-uniform) increment to all of them: the
-// inner loop does no per-lane address arithmetic or masking.  Out-of-range
-// rows, columns and blocks past the end of the chunk get offsets >= 2^31;
-// buffer loads beyond the descriptor's extent return zeros.  This needs each
-// operand region below 2^31 bytes and, for the compressing contraction, 2P a
-// multiple of the block so that every lane crosses a coil boundary at the
-// same block.
+// Buffer-addressed loads of the staged forms: a thread keeps 32-bit byte
+// offsets into a buffer resource per operand region; rows, columns and chunks
+// out of range get offsets >= 2^31, and buffer loads beyond the descriptor's
+// extent return zeros.  Each operand region must stay below 2^31 bytes.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOOB = 0x80000000u;
 
@@ -376,7 +377,7 @@ __device__ inline float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
-// MFMA geometry of the buffer-addressed forms: FP32 uses the 32 x 32 x 2
+// MFMA geometry of the staged forms: FP32 uses the 32 x 32 x 2
 // instruction (four independent 32 x 32 accumulators sustain close to the
 // FP32 peak, the 16 x 16 x 4 form does not), the 16-bit types the 16 x 16 x 32
 // one.  A lane (i, h) (i = lane % T, h = lane / T) holds LW consecutive
@@ -398,102 +399,6 @@ struct Geo<Store::F32> {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], c, 0, 0, 0);
   }
 };
-
-template <int WM, int WN, int MT, int NT, Store ST, int DEPTH>
-__global__ __launch_bounds__(64 * WM * WN) void k_expand_u(ExpandArgs a) {
-  using G = Geo<ST>;
-  using E = typename Mma<ST>::E;
-  constexpr int T = G::T, KB = G::KB, LW = G::LW, NE = G::NE, NR = G::NR;
-  constexpr uint32_t BB = KB * sizeof(E);
-  constexpr int TM = WM * MT * T, TN = WN * NT * T;
-  constexpr int LDT = TN + 4;
-  __shared__ float tile[TM * LDT];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane % T, lh = lane / T;
-  const int wm = wave / WN, wn = wave % WN;
-  const int tiles_n = (a.N + TN - 1) / TN, tiles_m = (a.M + TM - 1) / TM;
-  const int total = tiles_n * tiles_m * a.B * a.np;
-  const int logical = xcd_logical(blockIdx.x, total);
-  const int tn = logical % tiles_n;
-  const int rest = logical / tiles_n;
-  const int tm = rest % tiles_m, bp = rest / tiles_m;
-  const int b = bp / a.np, p = bp - b * a.np;
-  const int g = a.pgroup[p];
-  const int row0 = tm * TM + wm * MT * T, col0 = tn * TN + wn * NT * T;
-
-  const __amdgpu_buffer_rsrc_t rA = make_rsrc(static_cast<const E*>(a.Zt) + (size_t)bp * a.M * a.KD,
-                                              (uint32_t)((size_t)a.M * a.KD * sizeof(E)));
-  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const E*>(a.AH) + (size_t)g * a.N * a.KD,
-                                              (uint32_t)((size_t)a.N * a.KD * sizeof(E)));
-  const int nblk = a.KD / KB;
-  uint32_t va[MT], vb[NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int r = row0 + T * m + li;
-    va[m] = r < a.M ? (uint32_t)(((size_t)r * a.KD + LW * lh) * sizeof(E)) : kOOB;
-  }
-#pragma unroll
-  for (int c = 0; c < NT; ++c) {
-    const int cc = col0 + T * c + li;
-    vb[c] = cc < a.N ? (uint32_t)(((size_t)cc * a.KD + LW * lh) * sizeof(E)) : kOOB;
-  }
-  int loaded = 0;
-  auto load = [&](floatx4(&xa)[MT], floatx4(&xb)[NT]) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) xa[m] = bload(rA, va[m]);
-#pragma unroll
-    for (int c = 0; c < NT; ++c) xb[c] = bload(rB, vb[c]);
-#pragma unroll
-    for (int m = 0; m < MT; ++m) va[m] += BB;
-#pragma unroll
-    for (int c = 0; c < NT; ++c) vb[c] += BB;
-    if (++loaded == nblk) {
-#pragma unroll
-      for (int m = 0; m < MT; ++m) va[m] |= kOOB;
-#pragma unroll
-      for (int c = 0; c < NT; ++c) vb[c] |= kOOB;
-    }
-  };
-  typename G::Acc acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int c = 0; c < NT; ++c)
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[m][c][r] = 0.f;
-  floatx4 ra[DEPTH][MT], rb[DEPTH][NT];
-#pragma unroll
-  for (int s = 0; s < DEPTH - 1; ++s) load(ra[s], rb[s]);
-  for (int kb = 0; kb < nblk; kb += DEPTH) {
-#pragma unroll
-    for (int s = 0; s < DEPTH; ++s) {
-      load(ra[(s + DEPTH - 1) % DEPTH], rb[(s + DEPTH - 1) % DEPTH]);
-      if (kb + s < nblk) {
-#pragma unroll
-        for (int e = 0; e < NE; ++e)
-#pragma unroll
-          for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int c = 0; c < NT; ++c) acc[m][c] = G::step(ra[s][m], rb[s][c], e, acc[m][c]);
-      }
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int c = 0; c < NT; ++c)
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        tile[(wm * MT * T + T * m + G::row_of(r, lh)) * LDT + wn * NT * T + T * c + li] = acc[m][c][r];
-  __syncthreads();
-  const int rbase = tm * TM, cbase = tn * TN;
-  for (int e = threadIdx.x; e < TM * (TN / 4); e += 64 * WM * WN) {
-    const int rl = e / (TN / 4), cl = (e - rl * (TN / 4)) * 4;
-    const int y = rbase + rl, col = cbase + cl;
-    if (y >= a.M || col >= a.N) continue;
-    store_w_quad<ST>(a.W, tile + rl * LDT + cl, b, y, col, a.N, a.M, a.nc, a.nt, a.P, p);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Compressing contraction staged through LDS.  The operand layout of an MFMA
@@ -748,10 +653,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 
   const __amdgpu_buffer_rsrc_t rA = make_rsrc(static_cast<const E*>(a.Zt) + (size_t)bp * a.M * a.KD,
                                               (uint32_t)((size_t)a.M * a.KD * ES));
-  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const E*>(a.AH) + (size_t)g * RS * a.N * a.KD,
-                                              (uint32_t)((size_t)RS * a.N * a.KD * ES));
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(static_cast<const E*>(a.AH) + (size_t)g * RS * a.N * a.KDB,
+                                              (uint32_t)((size_t)RS * a.N * a.KDB * ES));
   const int nst = a.KD / KT;
   const int c16 = tid & 7;
+  int kc = (KT / 8) * c16;  // this thread's chunk position along the contraction
   uint32_t va[AR], vb[BR];
 #pragma unroll
   for (int r = 0; r < AR; ++r) {
@@ -761,7 +667,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
-    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * RS * a.KD + (KT / 8) * c16) * ES) : kOOB;
+    const int kb0 = (a.kwrap && kc >= a.kwrap) ? kc - a.kwrap : kc;  // a chunk may start in the lo part
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * RS * a.KDB + kb0) * ES) : kOOB;
   }
   floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
   auto fetch = [&](floatx4(&xa)[AR], floatx4(&xb)[BR]) {
@@ -771,8 +678,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
     for (int r = 0; r < BR; ++r) xb[r] = bload(rB, vb[r]);
 #pragma unroll
     for (int r = 0; r < AR; ++r) va[r] += KT * ES;
+    // the bank offset returns to the row start where the lo part begins
+    const uint32_t back = (a.kwrap && kc < a.kwrap && kc + KT >= a.kwrap) ? (uint32_t)(a.kwrap * ES) : 0u;
+    kc += KT;
 #pragma unroll
-    for (int r = 0; r < BR; ++r) vb[r] += KT * ES;
+    for (int r = 0; r < BR; ++r) vb[r] += KT * ES - back;
   };
   typename G::Acc acc[NA][MT][NT];
 #pragma unroll
@@ -882,18 +792,13 @@ __global__ void k_expand_bank(const double2* __restrict__ A, BankOut o, int G, i
 
 // Tile-shape tables: waves WM x WN per work-group, wave tile MT x NT MFMA
 // tiles, depth.  kCompressLds / kExpandLds: LDS-staged FP32 (32 x 32 tiles
-// of complex rows / columns, depth = k-tiles of register prefetch); the *16 tables: LDS-staged 16-bit
-// (16 x 16 tiles); kExpand32 / kExpand16: the buffer-addressed register-direct
-// expanding forms (depth = register ring).  Index 0 is the default of its
+// of complex rows / columns, depth = k-tiles of register prefetch); the *16
+// tables: LDS-staged 16-bit (16 x 16 tiles).  Index 0 is the default of its
 // class.  The general forms (operands of 2 GiB or more) use one fixed shape.
 struct Shape {
   int wm, wn, mt, nt, depth;
 };
 constexpr int kNumShapes = 8;
-constexpr Shape kExpand32[kNumShapes] = {{1, 2, 1, 4, 3}, {1, 4, 1, 2, 3}, {1, 2, 2, 2, 3}, {1, 1, 1, 4, 3},
-                                         {2, 2, 1, 2, 3}, {1, 2, 1, 4, 4}, {1, 4, 1, 1, 3}, {1, 2, 2, 2, 4}};
-constexpr Shape kExpand16[kNumShapes] = {{1, 2, 4, 4, 4}, {1, 2, 4, 4, 3}, {1, 4, 2, 4, 3}, {2, 2, 4, 2, 3},
-                                         {1, 4, 2, 2, 3}, {1, 4, 2, 4, 5}, {2, 2, 2, 4, 3}, {1, 4, 1, 4, 3}};
 constexpr Shape kCompressLds[kNumShapes] = {{2, 2, 1, 1, 1}, {2, 1, 1, 1, 2}, {2, 1, 1, 1, 1}, {2, 1, 1, 2, 1},
                                             {4, 1, 1, 1, 1}, {2, 4, 1, 1, 1}, {1, 2, 1, 1, 1}, {1, 4, 1, 1, 1}};
 constexpr Shape kExpandLds[kNumShapes] = {{1, 2, 1, 1, 1}, {1, 4, 1, 1, 1}, {1, 2, 1, 1, 2}, {2, 2, 1, 1, 1},
@@ -914,13 +819,12 @@ bool compress_staged(const CompressArgs& a, Store st) {
   return (st == Store::F32 || (2 * a.P) % (int)(16 / esz) == 0) && a.kchunk % staged_ktile(st) == 0 &&
          (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB && (size_t)a.M * a.KD * esz < kOOB;
 }
-bool expand_uniform(const ExpandArgs& a, Store st) {
-  const int kb = st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB;
+// 2 kp is a multiple of 32, so KD (2 kp FP32, 4 kp 16-bit) is always a whole
+// number of k-tiles; the staged form needs 32-bit buffer offsets.
+bool expand_staged(const ExpandArgs& a, Store st) {
   const size_t esz = st == Store::F32 ? 4 : 2;
-  return a.KD % kb == 0 && (size_t)a.M * a.KD * esz < kOOB && (size_t)a.N * a.KD * esz < kOOB;
+  return a.KD % staged_ktile(st) == 0 && (size_t)a.M * a.KD * esz < kOOB && (size_t)a.N * a.KDB * esz < kOOB;
 }
-
-bool expand_staged(const ExpandArgs& a, Store st) { return a.KD % staged_ktile(st) == 0 && expand_uniform(a, st); }
 
 int tiles(int n, int t) { return (n + t - 1) / t; }
 
@@ -958,11 +862,6 @@ void launch_expand_v(hipStream_t s, const ExpandArgs& a) {
     if (ST == Store::F32) e.N = a.N / 2;  // complex columns of the three-multiplication form
     const dim3 grid(tiles(e.N, S.wn * S.nt * T) * tiles(e.M, S.wm * S.mt * T) * rest);
     hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, e);
-  } else if (expand_uniform(a, ST)) {
-    constexpr Shape S = ST == Store::F32 ? kExpand32[V] : kExpand16[V];
-    constexpr int T = Geo<ST>::T;
-    const dim3 grid(tiles(a.N, S.wn * S.nt * T) * tiles(a.M, S.wm * S.mt * T) * rest);
-    hipLaunchKernelGGL((k_expand_u<S.wm, S.wn, S.mt, S.nt, ST, S.depth>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
   } else {
     constexpr Shape S = kExpandGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
@@ -1107,7 +1006,9 @@ int launch_group_expand(const Plan& pl, Store st) {
   a.zeros = pl.zeros;
   a.M = pl.ny;
   a.N = 2 * pl.ns;
-  a.KD = 2 * pl.Kp;
+  a.KDB = 2 * pl.Kp;
+  a.KD = st == Store::F32 ? 2 * pl.Kp : 4 * pl.Kp;
+  a.kwrap = st == Store::F32 ? 0 : 2 * pl.Kp;
   a.nc = pl.nc;
   a.nt = pl.nt;
   a.P = pl.P;

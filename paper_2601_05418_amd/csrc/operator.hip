@@ -540,7 +540,7 @@ __global__ __launch_bounds__(256) void k_pe_adj(const float2* __restrict__ in, v
     const int bp = l / K, k = l - bp * K;
     float2 v = cconj(res[li * LS + fpad(y)]);
     if (y & 1) v = make_float2(-v.x, -v.y);
-    store_c<ST>(Zt, ((size_t)bp * NY + y) * kp + k, v);
+    store_zt<ST>(Zt, (size_t)bp * NY + y, kp, k, v);
   }
 }
 
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_pe_normal(const float2* __restrict__ Zp
     const int bp = l / K, k = l - bp * K;
     float2 v = cconj(res2[li * LS + fpad(y)]);
     if (y & 1) v = make_float2(-v.x, -v.y);
-    store_c<ST>(Zt, ((size_t)bp * NY + y) * kp + k, v);
+    store_zt<ST>(Zt, (size_t)bp * NY + y, kp, k, v);
   }
 }
 
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(256) void k_pe_normal2(const float2* __restrict__ Z
     const int y = i / nl, ln = i - y * nl;
     const int l = l0 + ln;
     const int bp = l / K, k = l - bp * K;
-    store_c<ST>(Zt, ((size_t)bp * NY + y) * kp + k, Zs[ln * NYP + y]);
+    store_zt<ST>(Zt, (size_t)bp * NY + y, kp, k, Zs[ln * NYP + y]);
   }
 }
 

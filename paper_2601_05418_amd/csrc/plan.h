@@ -94,7 +94,7 @@ struct Plan {
   float2* W = nullptr;      // [B][nc][ny][nt] (also holds 16-bit W)
   float2* Zp = nullptr;     // [ksplit][B][np][K][ny]
   float2* Zt = nullptr;     // [B][np][ny][Kp]
-  uint32_t* Zt16 = nullptr; // [B][np][ny][Kp] 16-bit (re, im) pairs, for the 16-bit contractions
+  uint32_t* Zt16 = nullptr; // [B][np][ny][2 Kp] 16-bit (re, im) pairs, hi then lo, for the 16-bit contractions
   float2* part = nullptr;   // [f1h_nchunk][B][ny][nx]
 
   // device: solver state

@@ -103,7 +103,8 @@ def max_rel(a, ref):
 # Error model of the 16-bit operator: the oracle's stages in FP64 with the
 # values rounded (nearest even) exactly where the library stores 16-bit
 # operands -- the bank (after its FP32 copy), W after the PSF product, Z^T
-# after the phase-encode stage, and W after the expanding contraction.
+# after the phase-encode stage as a hi + lo pair (hi = rn(z), lo = rn(z - hi)
+# from the FP32 value), and W after the expanding contraction.
 # ---------------------------------------------------------------------------
 def _round_bf16(x):
     u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
@@ -121,6 +122,13 @@ def round16(z, prec):
     return r(z.real) + 1j * r(z.imag)
 
 
+def round16_pair(z, prec):
+    """hi + lo of the 16-bit pair that represents the FP32 value of z."""
+    z32 = np.asarray(z, np.complex64).astype(np.complex128)
+    hi = round16(z32, prec)
+    return hi + round16(z32 - hi, prec)
+
+
 def rounded_ops(sl, bank, prec):
     g = sl.geom
     nt = g.os * g.nx
@@ -131,7 +139,7 @@ def rounded_ops(sl, bank, prec):
         return oe.group_compress(w, bq, g.patch_group, g.patch_len)
 
     def adj_z(zt):
-        w = round16(oe.group_expand(round16(zt, prec), bq, g.patch_group, g.patch_len, g.nc, nt), prec)
+        w = round16(oe.group_expand(round16_pair(zt, prec), bq, g.patch_group, g.patch_len, g.nc, nt), prec)
         return oe.readout_encode_adj(w, sl.coils, sl.psf, g.os)
 
     return dict(

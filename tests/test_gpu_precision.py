@@ -57,12 +57,10 @@ def check(name, out, ref, model, prec, bound=True, ratio=0.2):
     assert m <= ratio * e  # the model explains the error
 
 
-# The per-application bounds are the targets for the C1-shaped precision
-# configuration and hold on the three small cases.  The "wide" case (P = 32,
-# the 16-bit LDS-staged contractions) is held to the rounding model only: there
-# the model itself, i.e. 16-bit storage of W, the bank and Z with exact
-# arithmetic, is 2.08e-3 from FP64 for the BF16 normal operator.
-BOUNDED = {"small", "rect", "periodic"}
+# The per-application bounds hold on every case.  On the "wide" case (P = 32)
+# 16-bit storage of W, the bank and a rounded Z^T alone came to 2.08e-3 for the
+# BF16 normal operator; carrying Z^T as a hi + lo pair brings the model to
+# 1.4e-3 (the bank and W are the remaining rounding points).
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
@@ -75,7 +73,7 @@ def test_reduced_precision_operator(gpu_lib, case, prec):
     rng = np.random.default_rng(11)
     x = H.round64(sl.image + 0.1 * H.crandn(rng, (g.ny, g.nx)))
     y = H.round64(ops["fwd"](sl.image) + 0.05 * H.crandn(rng, plan.data_shape()[1:]))
-    bd = case in BOUNDED
+    bd = True
     check("forward", host(plan.forward(dev(x[None]), prec=prec))[0], ops["fwd"](x), mod["fwd"](x), prec, bd)
     check("adjoint", host(plan.adjoint(dev(y[None]), prec=prec))[0], ops["adj"](y), mod["adj"](y), prec, bd)
     check("normal", host(plan.normal(dev(x[None]), prec=prec))[0], ops["nrm"](x), mod["nrm"](x), prec, bd)
