@@ -149,6 +149,32 @@ def wave_psf(ny: int, nt: int, cycles: int, phase_max: float) -> np.ndarray:
     return np.exp(-1j * phase_max * yy[:, None] * np.sin(2.0 * np.pi * cycles * t / nt)[None, :])
 
 
+def local_b0_modulation(nx: int, ny: int, nt: int, rng: np.random.Generator, n_b0: int = 8,
+                        cycles: int = 4, phase_max: float = 6.0, sigma: float = 0.35,
+                        radius: float = 0.75) -> np.ndarray:
+    """exp(-i k_m(t, x, y)), [nt][ny][nx], for an array of n_b0 local B0 coils
+    driven with sinusoidal currents (Eqs. 2-3: k_m = sum_l B_l(r) int I_l):
+
+        k_m(t, r) = sum_l a_l B_l(r) sin(2 pi cycles t / nt + phi_l),
+
+    B_l a Gaussian bump (sigma in FOV units) centred on a circle of the given
+    radius (the coils sit around the object), a_l ~ U(0.5, 1) * phase_max,
+    phi_l ~ U(0, 2 pi).  The field is nonlinear in x and y, so the phase does
+    not factor into a readout point-spread function.  Periodic in t with
+    period nt / cycles."""
+    X, Y = grid(nx, ny)
+    t = np.arange(nt)
+    km = np.zeros((nt, ny, nx))
+    for lam in range(n_b0):
+        ang = 2.0 * np.pi * lam / n_b0
+        cx, cy = radius * np.cos(ang), radius * np.sin(ang)
+        amp = rng.uniform(0.5, 1.0) * phase_max
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        field = np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * sigma ** 2))
+        km += amp * field[None] * np.sin(2.0 * np.pi * cycles * t / nt + phi)[:, None, None]
+    return np.exp(-1j * km)
+
+
 def pe_mask(ny: int, accel: int, acs: int) -> np.ndarray:
     """Regular phase-encode undersampling plus a centred calibration block.
 
@@ -248,6 +274,40 @@ def batch_draws(n_slices: int = 64, seed: int = 0) -> List[Slice]:
         r = int(draw.choice([3, 4, 5]))
         out.append(_make(4, seed * 1000 + i + 1, n, nc, os_, 7, 6.0, p, k, r, 8))
     return out
+
+
+@dataclasses.dataclass
+class MapSlice:
+    """A slice encoded with a general modulation map (no readout PSF)."""
+    geom: Geometry
+    image: np.ndarray  # complex128 [ny][nx]
+    coils: np.ndarray  # complex128 [nc][ny][nx]
+    bmod: np.ndarray  # complex128 [nt][ny][nx] = exp(-i k_m(t, x, y))
+    noise: Optional[np.ndarray]
+    snr: Optional[float]
+
+
+def local_b0_slice(seed: int = 0, n: int = 128, nc: int = 16, os_: int = 4, patch_len: int = 16, k: int = 16,
+                   accel: int = 3, acs: int = 8, cycles: int = 4, phase_max: float = 6.0, periodic: bool = False,
+                   snr: Optional[float] = None) -> MapSlice:
+    """Local-B0-array slice (Section 3.1): n x n, nc receive coils, os-fold
+    readout oversampling, an 8-coil local B0 array with `cycles` periods per
+    readout and +-phase_max rad, patches of patch_len samples, K kept per
+    group (default 16 of 256 virtual channels: 16x), R = accel with acs
+    calibration lines.  periodic=True maps the patches onto those of one
+    modulation period (nt / cycles samples)."""
+    rs = _streams(6, seed)
+    nt = os_ * n
+    np_ = nt // patch_len
+    per = nt // cycles
+    pg = periodic_groups(np_, per // patch_len) if periodic else sequential_groups(np_)
+    geom = Geometry(nx=n, ny=n, nc=nc, os=os_, patch_len=patch_len, patch_group=pg.astype(np.int32),
+                    n_groups=int(pg.max()) + 1, k=k, mask=pe_mask(n, accel, acs))
+    image = ellipse_phantom(n, n, rs[_PHANTOM])
+    coils = gaussian_coils(n, n, nc, rs[_COILS], rs[_B1])
+    bmod = local_b0_modulation(n, n, nt, rs[_DRAWS], cycles=cycles, phase_max=phase_max)
+    noise = unit_noise((nc, geom.ms, nt), rs[_NOISE]) if snr is not None else None
+    return MapSlice(geom, image, coils, bmod, noise, snr)
 
 
 def tiny_slice(seed: int = 0, nx: int = 8, ny: int = 8, nc: int = 2, os_: int = 2,
