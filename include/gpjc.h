@@ -100,6 +100,24 @@ typedef struct gpjc_plan gpjc_plan;
  * (Section 2.3); GPJC_E_INVAL otherwise.  Synchronises. */
 int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_psf,
                      void* hip_stream, gpjc_plan** out);
+/* Create a plan for a general modulation map (Section 3.1: nonlinear B0
+ * fields such as a local B0 coil array; Eqs. 1-3), d_bmod [nt][ny][nx] c64 =
+ * exp(-i k_m(t, x, y)), which need not factor into a readout PSF.  The
+ * phase-encode dimension stays Fourier (the modulation repeats on every
+ * phase-encode step, Section 2.3), and each image column y has the dense
+ * readout model E_y[(n, t)][x] = c_n(x, y) exp(-i k_m(t, x, y)) F_Nt[t][x].
+ * Compressed plans only (geom->compressed = 1), FP32 only.  Calibration
+ * (Eqs. 6-12) forms each P_g directly over the pixels; every bank
+ * (gpjc_calibrate / gpjc_set_compression) is turned into the explicit
+ * compressed readout matrices E'_y = blockdiag_p(A_g(p)) E_y (Eq. 14), stored
+ * per column ([ny][Np][K][nx] c64, ny * Np * K * nx * 8 bytes, owned by the
+ * plan), which gpjc_forward / gpjc_adjoint / gpjc_normal and the solvers
+ * apply, each followed or preceded by the phase-encode DFT and mask as for
+ * the Wave operator.  Group legality: member patches' map blocks must agree
+ * within 1e-6 (any grouping is legal for P = 1).  d_bmod is copied;
+ * synchronises. */
+int gpjc_plan_create_bmap(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_bmod,
+                          void* hip_stream, gpjc_plan** out);
 int gpjc_plan_destroy(gpjc_plan* plan);
 /* Switch the stream later calls are queued on. */
 int gpjc_set_stream(gpjc_plan* plan, void* hip_stream);
@@ -221,6 +239,8 @@ enum {
   GPJC_STAGE_PE_COLS,           /* uncompressed phase-encode stages */
   GPJC_STAGE_COMBINE,           /* partial-image sums */
   GPJC_STAGE_SOLVER,            /* CG / FISTA vector kernels */
+  GPJC_STAGE_EXPLICIT_FWD,      /* explicit readout matrices, forward */
+  GPJC_STAGE_EXPLICIT_ADJ,      /* explicit readout matrices, adjoint */
   GPJC_STAGE_COUNT
 };
 int gpjc_stage_timing(gpjc_plan* plan, int enable);

@@ -51,7 +51,8 @@ static int dalloc(T** p, size_t count) {
 static void free_plan(Plan* pl) {
   void* bufs[] = {pl->coils, pl->psf,  pl->psfp, pl->twin, pl->tw_x, pl->tw_y, pl->lines, pl->pgroup,
                   pl->maskf, pl->zeros, pl->A128, pl->Aexp, pl->AH,   pl->W,    pl->Zp,   pl->Zt,    pl->part,
-                  pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->vd,   pl->red,  pl->hist,  pl->flag};
+                  pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->vd,   pl->red,  pl->hist,  pl->flag,
+                  pl->bmod,  pl->Ec};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int i = 0; i < 2; ++i) {
@@ -151,11 +152,17 @@ static void choose_launch(Plan& pl) {
   pl.f3_tb = std::max(1, std::min(16, (lds_f2 - pl.ny) / (2 * lsy)));
 
   if (pl.compressed) default_gemm_config(pl);
-
+  if (pl.general) {
+    // the explicit adjoint leaves one partial image per chunk of rows (p, k);
+    // the explicit forward writes Z whole, so the phase-encode stage reads one split
+    pl.f1h_nchunk = explicit_chunks(pl.np * pl.K, pl.ny, pl.B);
+    pl.gemm[0].ksplit = 1;
+  }
 }
 
 static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, const gpjc_c64* d_psf,
-                      hipStream_t stream) {
+                      const gpjc_c64* d_bmod, hipStream_t stream) {
+  pl.general = d_bmod != nullptr;
   pl.nx = g->nx;
   pl.ny = g->ny;
   pl.nc = g->nc;
@@ -191,7 +198,7 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
   GPJC_TRY(dalloc(&pl.maskf, (size_t)pl.ny));
   GPJC_TRY(dalloc(&pl.zeros, 64));
   GPJC_HIP(hipMemsetAsync(pl.zeros, 0, 64 * sizeof(float), stream));
-  GPJC_TRY(dalloc(&pl.W, (size_t)pl.B * pl.nc * pl.ny * pl.nt));
+  if (!pl.general) GPJC_TRY(dalloc(&pl.W, (size_t)pl.B * pl.nc * pl.ny * pl.nt));
   GPJC_TRY(dalloc(&pl.part, (size_t)pl.f1h_nchunk * pl.B * npix));
   const size_t ni = pl.img_elems();
   GPJC_TRY(dalloc(&pl.vx, ni));
@@ -215,7 +222,11 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
     GPJC_TRY(dalloc(&pl.Zp, (size_t)kMaxKsplit * pl.B * pl.np * pl.K * pl.ny));
     GPJC_TRY(dalloc(&pl.Zt, (size_t)pl.B * pl.np * pl.ny * pl.Kp));
     GPJC_HIP(hipMemsetAsync(pl.Zt, 0, sizeof(float2) * (size_t)pl.B * pl.np * pl.ny * pl.Kp, stream));
-    if (pl.P % 4 == 0) {  // 16-bit contractions: bank copies and a 16-bit Z^T (pads stay zero)
+    if (pl.general) {
+      GPJC_TRY(dalloc(&pl.bmod, (size_t)pl.nt * npix));
+      GPJC_TRY(dalloc(&pl.Ec, explicit_bytes(pl.nx, pl.ny, pl.np, pl.K) / sizeof(float2)));
+    }
+    if (pl.P % 4 == 0 && !pl.general) {  // 16-bit contractions: bank copies and a 16-bit Z^T (pads stay zero)
       for (int i = 0; i < 2; ++i) {
         GPJC_TRY(dalloc(&pl.Aexp16[i], (size_t)pl.G * 2 * pl.K * 2 * pl.ns));
         GPJC_TRY(dalloc(&pl.AH16[i], (size_t)pl.G * 2 * pl.ns * 2 * pl.Kp));
@@ -230,12 +241,43 @@ static int setup_plan(Plan& pl, const gpjc_geom* g, const gpjc_c64* d_coils, con
   GPJC_HIP(hipMemcpyAsync(pl.maskf, mf.data(), sizeof(float) * pl.ny, hipMemcpyHostToDevice, stream));
   GPJC_HIP(hipMemcpyAsync(pl.lines, pl.lines_h.data(), sizeof(int) * pl.ms, hipMemcpyHostToDevice, stream));
   GPJC_HIP(hipMemcpyAsync(pl.coils, d_coils, sizeof(float2) * pl.nc * npix, hipMemcpyDeviceToDevice, stream));
-  GPJC_HIP(hipMemcpyAsync(pl.psf, d_psf, sizeof(float2) * pl.ny * pl.nt, hipMemcpyDeviceToDevice, stream));
+  if (pl.general) {
+    // no readout PSF: a unit table keeps the shared set-up uniform
+    const std::vector<float2> ones((size_t)pl.ny * pl.nt, make_float2(1.f, 0.f));
+    GPJC_HIP(hipMemcpyAsync(pl.psf, ones.data(), sizeof(float2) * ones.size(), hipMemcpyHostToDevice, stream));
+    GPJC_HIP(hipMemcpyAsync(pl.bmod, d_bmod, sizeof(float2) * (size_t)pl.nt * npix, hipMemcpyDeviceToDevice, stream));
+    GPJC_HIP(hipStreamSynchronize(stream));  // `ones` is a host temporary
+  } else {
+    GPJC_HIP(hipMemcpyAsync(pl.psf, d_psf, sizeof(float2) * pl.ny * pl.nt, hipMemcpyDeviceToDevice, stream));
+  }
   GPJC_TRY(launch_prep_tables(pl));
   GPJC_HIP(hipMemsetAsync(pl.hist, 0, sizeof(double) * pl.hist_cap, stream));
 
-  if (pl.compressed && pl.G < pl.np) {
-    // One matrix per group is only valid if every member sees the same modulation.
+  if (pl.compressed && pl.G < pl.np && pl.P > 1 && pl.general) {
+    // the same rule for a general map: member patches' map blocks agree
+    const size_t blk = (size_t)pl.P * npix;
+    std::vector<float2> h((size_t)pl.nt * npix);
+    GPJC_HIP(hipMemcpyAsync(h.data(), pl.bmod, sizeof(float2) * h.size(), hipMemcpyDeviceToHost, stream));
+    GPJC_HIP(hipStreamSynchronize(stream));
+    std::vector<int> first(pl.G, -1);
+    for (int p = 0; p < pl.np; ++p) {
+      const int g0 = pl.pgroup_h[p];
+      if (first[g0] < 0) {
+        first[g0] = p;
+        continue;
+      }
+      const float2* a = h.data() + (size_t)p * blk;
+      const float2* b = h.data() + (size_t)first[g0] * blk;
+      for (size_t i = 0; i < blk; ++i)
+        if (std::hypot(a[i].x - b[i].x, a[i].y - b[i].y) > 1e-6)
+          return fail(GPJC_E_INVAL, "patch " + std::to_string(p) + " does not share the modulation of group " +
+                                        std::to_string(g0));
+    }
+  }
+  if (pl.compressed && pl.G < pl.np && pl.P > 1 && !pl.general) {
+    // One matrix per group is only valid if every member sees the same
+    // modulation.  (With P = 1 a patch's channels differ from another's by one
+    // unit phase per pixel, which cancels in Eq. 7: every grouping is legal.)
     std::vector<float2> h((size_t)pl.ny * pl.nt);
     GPJC_HIP(hipMemcpyAsync(h.data(), pl.psf, sizeof(float2) * h.size(), hipMemcpyDeviceToHost, stream));
     GPJC_HIP(hipStreamSynchronize(stream));
@@ -271,6 +313,8 @@ int check_prec(const Plan& pl, int prec, Store* st) {
   if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
   if (prec != GPJC_FP32 && !pl.compressed)
     return fail(GPJC_E_UNSUPPORTED, "the uncompressed operator is FP32 only");
+  if (prec != GPJC_FP32 && pl.general)
+    return fail(GPJC_E_UNSUPPORTED, "the explicit readout model of a modulation-map plan is FP32 only");
   if (prec != GPJC_FP32 && pl.P % 4)
     return fail(GPJC_E_UNSUPPORTED, "16-bit contractions need patch_len divisible by 4");
   *st = prec == GPJC_FP32 ? Store::F32 : prec == GPJC_BF16 ? Store::BF16 : Store::F16;
@@ -300,7 +344,30 @@ int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_
   GPJC_TRY(check_lds(geom));
   gpjc_plan* pl = new (std::nothrow) gpjc_plan();
   if (!pl) return fail(GPJC_E_NOMEM, "host allocation failed");
-  const int s = setup_plan(*pl, geom, d_coils, d_psf, reinterpret_cast<hipStream_t>(hip_stream));
+  const int s = setup_plan(*pl, geom, d_coils, d_psf, nullptr, reinterpret_cast<hipStream_t>(hip_stream));
+  if (s != GPJC_OK) {
+    free_plan(pl);
+    delete pl;
+    return s;
+  }
+  *out = pl;
+  return GPJC_OK;
+}
+
+int gpjc_plan_create_bmap(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_bmod, void* hip_stream,
+                          gpjc_plan** out) {
+  if (!out) return fail(GPJC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  GPJC_TRY(validate_geom(geom));
+  if (!geom->compressed) return fail(GPJC_E_INVAL, "a modulation-map plan must be compressed");
+  if (!d_coils || !d_bmod) return fail(GPJC_E_INVAL, "coil maps or modulation map is NULL");
+  if (!aligned(d_coils, 8) || !aligned(d_bmod, 8)) return fail(GPJC_E_INVAL, "coil maps / map not 8-byte aligned");
+  if (geom->nx > 512) return fail(GPJC_E_UNSUPPORTED, "modulation-map plans: nx above 512");
+  GPJC_TRY(check_supported(geom));
+  GPJC_TRY(check_lds(geom));
+  gpjc_plan* pl = new (std::nothrow) gpjc_plan();
+  if (!pl) return fail(GPJC_E_NOMEM, "host allocation failed");
+  const int s = setup_plan(*pl, geom, d_coils, nullptr, d_bmod, reinterpret_cast<hipStream_t>(hip_stream));
   if (s != GPJC_OK) {
     free_plan(pl);
     delete pl;
@@ -347,6 +414,7 @@ int gpjc_set_compression(gpjc_plan* plan, const gpjc_c128* d_A) {
   GPJC_HIP(hipMemcpyAsync(plan->A128, d_A, sizeof(double2) * (size_t)plan->G * plan->K * plan->ns,
                           hipMemcpyDeviceToDevice, plan->stream));
   GPJC_TRY(launch_expand_bank(*plan));
+  if (plan->general) GPJC_TRY(launch_build_explicit(*plan));
   plan->have_bank = true;
   return finish(*plan, GPJC_OK);
 }
@@ -518,6 +586,7 @@ int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches) {
 int gpjc_set_gemm_config(gpjc_plan* plan, gpjc_prec prec, int compress_variant, int expand_variant, int ksplit) {
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "GEMM configuration needs a compressed plan");
+  if (plan->general) return fail(GPJC_E_UNSUPPORTED, "modulation-map plans have no group contraction to configure");
   if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
   if (compress_variant < 0 || compress_variant >= gemm_compress_variants() || expand_variant < 0 ||
       expand_variant >= gemm_expand_variants())

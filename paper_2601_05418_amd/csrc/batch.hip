@@ -246,6 +246,7 @@ int gpjc_batch_recon_cg(gpjc_batch* batch, gpjc_prec prec, const gpjc_c64* const
 
 int gpjc_autotune(gpjc_plan* plan, gpjc_prec prec, const char* cache_path, int* h_choice) {
   if (!plan) return fail(GPJC_E_INVAL, "plan is NULL");
+  if (plan->general) return fail(GPJC_E_UNSUPPORTED, "modulation-map plans have no group contraction to tune");
   Store st = Store::F32;
   GPJC_TRY(check_prec(*plan, prec, &st));
   GPJC_TRY(check_bank(*plan));

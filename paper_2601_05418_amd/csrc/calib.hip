@@ -45,27 +45,11 @@
 
 #include "fft.h"
 #include "plan.h"
+#include "zcomplex.h"
 
 namespace gpjc {
 
 namespace {
-
-__device__ inline double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ inline double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ inline double2 zmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// a * conj(b)
-__device__ inline double2 zmulc(double2 a, double2 b) {
-  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-// conj(a) * b
-__device__ inline double2 zcmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ inline double2 zscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ inline double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ inline double zabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
 // Round-robin tournament over n players (n even): step s in [0, n-1), pair i
 // in [0, n/2); every pair of players meets exactly once in n-1 steps.
@@ -312,6 +296,76 @@ __global__ __launch_bounds__(256) void k_gram_assemble(const double2* __restrict
       const int a = n * P + oj[q], b = m * P + ok_[q];
       Hg[(size_t)a * nsp + b] = acc[q];
       if (m != n) Hg[(size_t)b * nsp + a] = zconj(acc[q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gram of a general modulation map exp(-i k_m(t, x, y)), which does not
+// factor into a readout PSF (Section 3.1): the direct form of Eq. 10 over
+// the pixels.  Per group, k_gen_channels writes the weighted composite
+// vectors (patch-common phase dropped: it is one unit scalar per pixel and
+// cancels in e e^H)
+//   u[(n, j)][r] = sqrt(w_r) cw_n(r) b[t0 + j][r] exp(-2 pi i j (ix - nx/2) / nt),
+//   w_r = wc(r) / sum_j |b[t0 + j][r]|^2  (= 1 / |e_r|^2 inside the ROI),
+// and k_gram_direct forms H_g = sum_r u_r u_r^H.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gen_channels(const double2* __restrict__ cw, const double* __restrict__ wc,
+                                                      const float2* __restrict__ bmod, int t0, int P, int nc, int nx,
+                                                      int npix, int nt, double2* __restrict__ u) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < npix; r += gridDim.x * blockDim.x) {
+    const int ix = r % nx;
+    double eb = 0.0;
+    for (int j = 0; j < P; ++j) eb += zabs2(z_of(bmod[(size_t)(t0 + j) * npix + r]));
+    const double sw = (wc[r] > 0.0 && eb > 0.0) ? sqrt(wc[r] / eb) : 0.0;
+    for (int j = 0; j < P; ++j) {
+      const double2 f = zscale(zmul(z_of(bmod[(size_t)(t0 + j) * npix + r]), zroot((long)j * (ix - nx / 2), nt)), sw);
+      for (int n = 0; n < nc; ++n) u[(size_t)(n * P + j) * npix + r] = zmul(cw[(size_t)n * npix + r], f);
+    }
+  }
+}
+
+// H[a][b] = sum_r u[a][r] conj(u[b][r]) for a 32 x 32 tile pair (ta <= tb;
+// the mirrored tile is written as the conjugate transpose).  256 threads,
+// 2 x 2 outputs each; pixels staged 32 at a time in LDS.
+__global__ __launch_bounds__(256) void k_gram_direct(const double2* __restrict__ u, int ns, int npix,
+                                                     double2* __restrict__ H, int nsp) {
+  const int ta = blockIdx.x, tb = blockIdx.y;
+  if (ta > tb) return;
+  __shared__ double2 Ua[32][33], Ub[32][33];
+  const int tid = threadIdx.x;
+  const int i0 = (tid >> 4) * 2, j0 = (tid & 15) * 2;
+  double2 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+  for (int r0 = 0; r0 < npix; r0 += 32) {
+    for (int i = tid; i < 32 * 32; i += 256) {
+      const int row = i >> 5, c = i & 31;
+      const int ra = ta * 32 + row, rb = tb * 32 + row, px = r0 + c;
+      Ua[row][c] = (ra < ns && px < npix) ? u[(size_t)ra * npix + px] : make_double2(0.0, 0.0);
+      Ub[row][c] = (rb < ns && px < npix) ? u[(size_t)rb * npix + px] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int c = 0; c < 32; ++c) {
+      const double2 a0 = Ua[i0][c], a1 = Ua[i0 + 1][c], b0 = Ub[j0][c], b1 = Ub[j0 + 1][c];
+      acc[0][0] = zadd(acc[0][0], zmulc(a0, b0));
+      acc[0][1] = zadd(acc[0][1], zmulc(a0, b1));
+      acc[1][0] = zadd(acc[1][0], zmulc(a1, b0));
+      acc[1][1] = zadd(acc[1][1], zmulc(a1, b1));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int ra = ta * 32 + i0 + a, rb = tb * 32 + j0 + b;
+      if (ra < ns && rb < ns) {
+        H[(size_t)ra * nsp + rb] = acc[a][b];
+        if (ta != tb) H[(size_t)rb * nsp + ra] = zconj(acc[a][b]);
+      }
     }
 }
 
@@ -766,7 +820,7 @@ struct Scratch {
 
 // Workspace pointers of one calibration.
 struct CalibBufs {
-  double2 *T = nullptr, *Lc = nullptr, *cw, *ph, *Qg, *H, *U, *V, *rowbuf;
+  double2 *T = nullptr, *Lc = nullptr, *cw, *ph = nullptr, *Qg = nullptr, *u = nullptr, *H, *U, *V, *rowbuf;
   double *wc, *qinv, *norms, *eigd, *thr2;
   int *t0s, *active, *rot, *flag;
 };
@@ -780,8 +834,12 @@ int alloc_calib(Scratch& s, const Plan& pl, bool whiten, CalibBufs& b) {
   const int nd = 2 * P - 1;
   GPJC_TRY(s.alloc(&b.cw, (size_t)pl.nc * npix));
   GPJC_TRY(s.alloc(&b.wc, (size_t)npix));
-  GPJC_TRY(s.alloc(&b.ph, (size_t)nd * pl.nx));
-  GPJC_TRY(s.alloc(&b.Qg, (size_t)pl.nc * pl.nc * pl.ny * nd));
+  if (pl.general) {  // the weighted composite vectors of one group at a time
+    GPJC_TRY(s.alloc(&b.u, (size_t)ns * npix));
+  } else {
+    GPJC_TRY(s.alloc(&b.ph, (size_t)nd * pl.nx));
+    GPJC_TRY(s.alloc(&b.Qg, (size_t)pl.nc * pl.nc * pl.ny * nd));
+  }
   GPJC_TRY(s.alloc(&b.qinv, (size_t)G * pl.ny));
   GPJC_TRY(s.alloc(&b.t0s, (size_t)G));
   GPJC_TRY(s.alloc(&b.H, (size_t)G * nsp * nsp));
@@ -834,10 +892,20 @@ static int calibrate_in(Plan& pl, Scratch& s, const uint8_t* roi, const float2* 
   }
   hipLaunchKernelGGL(k_calib_maps, dim3(std::min(1024, (npix + 255) / 256)), dim3(256), 0, st, pl.coils, T, roi, cw,
                      wc, pl.nc, npix);
-  hipLaunchKernelGGL(k_calib_tables, dim3(64), dim3(256), 0, st, pl.psf, t0s, ph, qinv, P, pl.nx, pl.ny, pl.nt, G);
+  if (!pl.general)
+    hipLaunchKernelGGL(k_calib_tables, dim3(64), dim3(256), 0, st, pl.psf, t0s, ph, qinv, P, pl.nx, pl.ny, pl.nt, G);
   hipLaunchKernelGGL(k_jac_init, dim3(2048), dim3(256), 0, st, H, U, ns, nsp, G);
   GPJC_HIP(hipGetLastError());
-  {
+  if (pl.general) {
+    const int nt32 = (ns + 31) / 32;
+    for (int g = 0; g < G; ++g) {
+      hipLaunchKernelGGL(k_gen_channels, dim3(std::min(1024, (npix + 255) / 256)), dim3(256), 0, st, cw, wc, pl.bmod,
+                         t0h[g], P, pl.nc, pl.nx, npix, pl.nt, bufs.u);
+      hipLaunchKernelGGL(k_gram_direct, dim3(nt32, nt32), dim3(256), 0, st, bufs.u, ns, npix,
+                         H + (size_t)g * nsp * nsp, nsp);
+    }
+    GPJC_HIP(hipGetLastError());
+  } else {
     const int nout = pl.nc * nd;
     const dim3 gq(pl.ny, pl.nc, (nout + kQO * 256 - 1) / (kQO * 256));
     // pixels / rows per LDS chunk: 16, fewer when the staged rows would not fit
@@ -928,6 +996,7 @@ static int calibrate_in(Plan& pl, Scratch& s, const uint8_t* roi, const float2* 
   GPJC_HIP(hipStreamSynchronize(st));
   if (hflag) return fail(GPJC_E_NUMERIC, "calibration: noise covariance is not positive definite");
   GPJC_TRY(launch_expand_bank(pl));
+  if (pl.general) GPJC_TRY(launch_build_explicit(pl));
   pl.have_bank = true;
   if (A_out)
     GPJC_HIP(hipMemcpyAsync(A_out, pl.A128, sizeof(double2) * (size_t)G * pl.K * ns, hipMemcpyDeviceToDevice, st));

@@ -1090,6 +1090,10 @@ int launch_pe_cols_normal(const Plan& pl) {
 // Whole operators
 // ---------------------------------------------------------------------------
 int op_forward(const Plan& pl, Store st, const float2* img, float2* out) {
+  if (pl.general) {
+    GPJC_TRY(launch_explicit_fwd(pl, img));
+    return launch_pe_fwd(pl, out, Store::F32);
+  }
   if (!pl.compressed) {
     GPJC_TRY(launch_readout_fwd(pl, img, Store::F32));
     return launch_pe_cols_fwd(pl, out);
@@ -1100,6 +1104,10 @@ int op_forward(const Plan& pl, Store st, const float2* img, float2* out) {
 }
 
 int op_adjoint_part(const Plan& pl, Store st, const float2* in) {
+  if (pl.general) {
+    GPJC_TRY(launch_pe_adj(pl, in, Store::F32));
+    return launch_explicit_adj(pl);
+  }
   if (!pl.compressed) {
     GPJC_TRY(launch_pe_cols_adj(pl, in));
     return launch_readout_adj(pl, Store::F32);
@@ -1110,6 +1118,11 @@ int op_adjoint_part(const Plan& pl, Store st, const float2* in) {
 }
 
 int op_normal_part(const Plan& pl, Store st, const float2* img) {
+  if (pl.general) {
+    GPJC_TRY(launch_explicit_fwd(pl, img));
+    GPJC_TRY(launch_pe_normal(pl, Store::F32));
+    return launch_explicit_adj(pl);
+  }
   if (!pl.compressed) {
     GPJC_TRY(launch_readout_fwd(pl, img, Store::F32));
     GPJC_TRY(launch_pe_cols_normal(pl));

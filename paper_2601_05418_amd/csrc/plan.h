@@ -69,6 +69,12 @@ struct Plan {
   GemmCfg& cfg(Store st) { return gemm[st == Store::F32 ? 0 : 1]; }
   long config_gen = 0;      // bumped whenever the launch configuration changes
 
+  // general modulation map (plans from gpjc_plan_create_bmap): no readout PSF;
+  // the compressed readout matrices are stored per phase-encode column
+  bool general = false;
+  float2* bmod = nullptr;   // [nt][ny][nx] exp(-i k_m(t, x, y))
+  float2* Ec = nullptr;     // [ny][np][K][nx] E'_y, rebuilt with every bank
+
   // device: geometry tables
   float2* coils = nullptr;  // [nc][ny][nx]
   float2* psf = nullptr;    // [ny][nt] as given
@@ -184,6 +190,13 @@ int run_gd_step(const Plan& pl, Store st, const float2* x, const float2* b, cons
 int run_gd_step_backward(const Plan& pl, Store st, const float2* g, const float* alpha, const float2* r, float2* gx,
                          float2* gb, float* galpha);
 int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
+
+// ---- explicit readout model for general modulation maps (explicit.hip) ----
+int launch_build_explicit(const Plan& pl);
+int launch_explicit_fwd(const Plan& pl, const float2* img);  // img -> Zp (split 0)
+int launch_explicit_adj(const Plan& pl);                      // Zt -> part
+int explicit_chunks(int rows, int ny, int B);
+size_t explicit_bytes(int nx, int ny, int np, int K);
 
 // Sizing of the two-pass readout forms (operator.hip).
 size_t two_pass_lds_fwd(int nx, int os, int cb);

@@ -26,7 +26,7 @@ FP32, BF16, FP16 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 
 STAGES = ("readout_fwd", "group_compress", "pe_normal", "pe_fwd", "pe_adj", "group_expand", "readout_adj",
-          "pe_cols", "combine", "solver")
+          "pe_cols", "combine", "solver", "explicit_fwd", "explicit_adj")
 
 GPJC_OK = 0
 GPJC_E_INVAL = -1
@@ -57,6 +57,7 @@ _I = ctypes.c_int
 _D = ctypes.c_double
 _SIGS = {
     "gpjc_plan_create": (_I, [ctypes.POINTER(_Geom), _VP, _VP, _VP, ctypes.POINTER(_VP)]),
+    "gpjc_plan_create_bmap": (_I, [ctypes.POINTER(_Geom), _VP, _VP, _VP, ctypes.POINTER(_VP)]),
     "gpjc_plan_destroy": (_I, [_VP]),
     "gpjc_set_stream": (_I, [_VP, _VP]),
     "gpjc_calibrate": (_I, [_VP, _VP, _VP, _VP, _VP]),
@@ -156,7 +157,9 @@ class Plan:
     """
 
     def __init__(self, nx, ny, nc, os_, coils, psf, mask, patch_len=0, patch_group=None, n_groups=0, k=0,
-                 batch=1, compressed=True, device="cuda:0", stream=None):
+                 batch=1, compressed=True, device="cuda:0", stream=None, bmod=None):
+        """psf [ny][nt] (Wave) or, with psf None, bmod [nt][ny][nx] (a general
+        modulation map, gpjc_plan_create_bmap)."""
         self.lib = load()
         self.device = torch.device(device)
         self.nx, self.ny, self.nc, self.os = int(nx), int(ny), int(nc), int(os_)
@@ -175,12 +178,13 @@ class Plan:
                   self.patch_group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.k,
                   self.mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), self.batch, int(self.compressed))
         c = _dev_tensor(coils, torch.complex64, self.device)
-        p = _dev_tensor(psf, torch.complex64, self.device)
+        self.general = bmod is not None
+        p = _dev_tensor(bmod if self.general else psf, torch.complex64, self.device)
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         handle = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)
-        _check(self.lib.gpjc_plan_create(ctypes.byref(g), _ptr(c), _ptr(p), ctypes.c_void_p(st),
-                                         ctypes.byref(handle)))
+        create = self.lib.gpjc_plan_create_bmap if self.general else self.lib.gpjc_plan_create
+        _check(create(ctypes.byref(g), _ptr(c), _ptr(p), ctypes.c_void_p(st), ctypes.byref(handle)))
         self.handle = handle
         self._inputs = []
 
@@ -189,6 +193,13 @@ class Plan:
         g = sl.geom
         return cls(g.nx, g.ny, g.nc, g.os, sl.coils, sl.psf, g.mask, g.patch_len, g.patch_group, g.n_groups,
                    g.k, batch=batch, compressed=compressed, **kw)
+
+    @classmethod
+    def from_map_slice(cls, sl, batch=1, **kw):
+        """A plan for a slice with a general modulation map (synth.MapSlice)."""
+        g = sl.geom
+        return cls(g.nx, g.ny, g.nc, g.os, sl.coils, None, g.mask, g.patch_len, g.patch_group, g.n_groups, g.k,
+                   batch=batch, compressed=True, bmod=sl.bmod, **kw)
 
     def close(self):
         if getattr(self, "handle", None):
