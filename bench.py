@@ -192,45 +192,144 @@ def unrolled_bench(steps, warmup, prec):
     }
 
 
-def cpu_baseline(sl, budget_s):
-    """The oracle's E'^H E' on the host cores: as many applications as fit in
-    the time budget (at least one)."""
+def explicit_bench(reps=20):
+    """The explicit compressed readout model on a local-B0-array slice (a
+    nonlinear modulation map, no readout PSF): 224 x 224, 32 coils, os 6
+    (1344 samples), an 8-coil local B0 array with 7 cycles per readout and
+    +-6 rad.  Joint compression: 42 patches of 32 samples on the 6 groups of
+    one modulation period, K = 64 (16x).  RF-only compression: P = 1, one
+    group for every sample, K = 10 (3.2x) -- the comparison of Table S2.
+    Reported: explicit-matrix size, build and calibration time, and E'^H E'
+    applications per image per second for 1 and 8 images per application,
+    with the HBM rate of the explicit forward / adjoint kernels."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2601_05418_amd import gpjc, synth
+    dev = torch.device("cuda:0")
+    base = synth.local_b0_slice(0, n=224, nc=32, os_=6, patch_len=32, k=64, accel=4, acs=16, cycles=7,
+                                phase_max=6.0, periodic=True)
+    g = base.geom
+    rf_geom = dataclasses.replace(g, patch_len=1, patch_group=np.zeros(g.nt, np.int32), n_groups=1, k=10)
+    out = {"workload": "local-B0 slice 224x224, 32 coils, os 6 (1344 samples), 8-coil B0 array, 7 cycles, "
+                       "+-6 rad, R=4+16 ACS; joint P=32 (6 periodic groups), K=64 vs RF-only P=1, K=10"}
+    for name, geom in (("joint_16x", g), ("rf_only_3.2x", rf_geom)):
+        sl = dataclasses.replace(base, geom=geom)
+        rows = geom.n_patches * geom.k
+        ebytes = 8.0 * geom.ny * rows * geom.nx
+        res = {"patch_len": geom.patch_len, "groups": geom.n_groups, "k": geom.k,
+               "compression_factor": geom.nc * geom.patch_len / geom.k, "explicit_matrix_GB": ebytes / 1e9}
+        for batch in (1, 8):
+            plan = gpjc.Plan.from_map_slice(sl, batch=batch)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            plan.calibrate()
+            torch.cuda.synchronize()
+            if batch == 1:
+                res["calibrate_and_build_s"] = time.perf_counter() - t
+            x = torch.as_tensor(np.ascontiguousarray(np.broadcast_to(sl.image, (batch, g.ny, g.nx)),
+                                                     np.complex64)).to(dev)
+            o = torch.empty_like(x)
+            for _ in range(3):
+                plan.normal(x, out=o)
+            plan.stage_timing(True, stages=["explicit_fwd", "explicit_adj"])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                plan.normal(x, out=o)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / reps
+            st = plan.stage_times()
+            plan.stage_timing(False)
+            kb = {}
+            for stg in ("explicit_fwd", "explicit_adj"):
+                ms, n = st[stg]
+                sec = ms / n / 1e3
+                byts = ebytes + 8.0 * batch * (geom.ny * geom.nx + rows * geom.ny)
+                kb[stg] = {"us_per_launch": sec * 1e6, "GB_per_s": byts / sec / 1e9, "hbm_frac": byts / sec / 8e12}
+            res[f"batch{batch}"] = {"ms_per_application": dt * 1e3, "image_applications_per_s": batch / dt,
+                                    "kernels": kb}
+            plan.close()
+            torch.cuda.empty_cache()
+        out[name] = res
+        log(f"explicit {name}: {res['explicit_matrix_GB']:.2f} GB, "
+            f"B=1 {res['batch1']['ms_per_application']:.3f} ms, B=8 {res['batch8']['ms_per_application']:.3f} ms")
+    out["joint_speedup_over_rf_only"] = {
+        f"batch{b}": out["joint_16x"][f"batch{b}"]["image_applications_per_s"]
+        / out["rf_only_3.2x"][f"batch{b}"]["image_applications_per_s"] for b in (1, 8)}
+    return out
+
+
+def cpu_baseline(sl, budget_s, gpu_normal=None):
+    """The oracle on the host cores, on a bounded sample of the workload:
+    E'^H E' applications for about budget_s seconds (the unit of `value`),
+    the wavelet prox of one FISTA iteration, and the Gram + eigen-selection
+    of one of the slice's groups.  FISTA-50 and calibration of the whole
+    slice are extrapolated from these (50 applications + 50 proxes; G times
+    one group).  gpu_normal(bank, x) -> the GPU's FP32 E'^H E' x with the same
+    bank; its distance to the first oracle application is reported."""
     import numpy as np
 
+    from oracle import compression as oc
     from oracle import encoding as oe
+    from oracle import solvers as osv
     g = sl.geom
     rng = np.random.default_rng(0)
     bank = np.empty((g.n_groups, g.k, g.nc, g.patch_len), complex)
     for i in range(g.n_groups):
         q, _ = np.linalg.qr(rng.standard_normal((g.ns, g.k)) + 1j * rng.standard_normal((g.ns, g.k)))
         bank[i] = q.conj().T.reshape(g.k, g.nc, g.patch_len)
-    x = sl.image
+    r64 = lambda a: np.asarray(a, np.complex64).astype(np.complex128)  # the values the GPU holds
+    coils, psf = r64(sl.coils), r64(sl.psf)
+    x = r64(sl.image)
+    first = None
     n = 0
     t0 = time.perf_counter()
     c0 = os.times()
     while True:
-        x = oe.normal(x, sl.coils, sl.psf, g.mask, g.os, bank, g.patch_group, g.patch_len)
-        x = x / np.linalg.norm(x)
+        y = oe.normal(x, coils, psf, g.mask, g.os, bank, g.patch_group, g.patch_len)
+        if first is None:
+            first = (x, y)
+        x = y / np.linalg.norm(y)
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     wall = time.perf_counter() - t0
+    t = time.perf_counter()
+    osv.wavelet_prox(x, 1e-3, LEVELS)
+    t_prox = time.perf_counter() - t
+    t = time.perf_counter()
+    e = oc.virtual_channels(coils, psf, g.os, g.patch_len, 0)
+    oc.compression_matrix(oc.gram(e), g.k, g.patch_len)
+    t_group = time.perf_counter() - t
     c1 = os.times()
     cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    wall_all = time.perf_counter() - t0
     try:
         import threadpoolctl
         blas = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
     except Exception:
         blas = None
-    return {
+    out = {
         "value": n / wall,
         "unit": "E'^H E' applications/s",
-        "cores": max(1, int(round(cpu / wall))),
+        "cores": len(os.sched_getaffinity(0)),
+        "threads_used": round(cpu / wall_all, 2),
         "kind": "oracle",
-        "sample": f"{n} FP64 NumPy applications of E'^H E' on the same 224x224 / 32-coil / 42-group slice "
-                  f"(random orthonormal bank), {wall:.1f} s wall; host affinity {len(os.sched_getaffinity(0))} "
-                  f"cores, BLAS threads {blas}, np.fft single-threaded",
+        "sample": f"{n} FP64 NumPy applications of E'^H E' ({wall:.1f} s), one wavelet prox and the Gram + "
+                  f"eigen-selection of 1 of {g.n_groups} groups, on the same {g.nx}x{g.ny} / {g.nc}-coil slice "
+                  f"(random orthonormal bank); BLAS threads {blas}, np.fft single-threaded",
+        "fista50_s_per_slice_extrapolated": ITERS * (wall / n + t_prox),
+        "calibrate_s_extrapolated": g.n_groups * t_group,
+        "calibrate_one_group_s": t_group,
     }
+    if gpu_normal is not None:
+        xin, yref = first
+        out["gpu_fp32_normal_rel_l2_vs_oracle"] = float(np.linalg.norm(gpu_normal(bank, xin) - yref)
+                                                        / np.linalg.norm(yref))
+    return out
 
 
 def main():
@@ -244,6 +343,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched CG measurement")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled-network training step")
+    ap.add_argument("--no-explicit", action="store_true", help="skip the explicit-model (local B0 map) measurement")
     ap.add_argument("--tune-cache", default=None, help="tile autotuning cache file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (reference for byte counters)")
@@ -312,6 +412,16 @@ def main():
     x0 = torch.as_tensor(np.ascontiguousarray(synth.unit_noise((1, g.ny, g.nx), rng), np.complex64)).to(dev)
     lip = plan.power_iteration(x0, 50, prec=args.prec) * 1.01
     log(f"lambda {lam:.4e}, L {lip:.4e}")
+    # The oracle's stored FISTA-50 run of this slice (tests/golden, written by
+    # a script that calls only the oracle): with its lambda and L the GPU runs
+    # the same schedule, and its result is compared with the stored iterate.
+    gold = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "highfield_fista50.npz")
+    if not args.periodic and os.path.exists(gold_path):
+        gold = np.load(gold_path)
+        lam_gpu, lip_gpu = lam, lip
+        lam, lip = float(gold["lam"]), float(gold["lip"])
+        log(f"using the stored oracle's lambda {lam:.4e} and L {lip:.4e}")
 
     x = torch.empty((1, g.ny, g.nx), dtype=torch.complex64, device=dev)
     # Untimed pass with every stage launch bracketed by HIP events: the
@@ -342,6 +452,19 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = ITERS * args.steps / dt
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms per slice, {value:.1f} E'^H E' per s")
+    accuracy = {}
+    if gold is not None:
+        xr = x.cpu().numpy()[0].astype(np.complex128)
+        ref = gold["x"].astype(np.complex128)
+        mag = np.abs(ref)
+        accuracy = {
+            "fista50_nrmse_vs_stored_oracle": float(np.sqrt(np.mean(np.abs(xr - ref) ** 2)) / (mag.max() - mag.min())),
+            "lambda_rel_diff_gpu_vs_oracle": abs(lam_gpu - lam) / lam,
+            "lipschitz_rel_diff_gpu_vs_oracle": abs(lip_gpu - lip) / lip,
+            "note": "GPU FISTA-50 (its own calibration, the oracle's lambda and L) against the oracle's FP64 run "
+                    "stored in tests/golden/highfield_fista50.npz; NRMSE normalised by the reference's range",
+        }
+        log(f"FISTA-50 NRMSE vs stored oracle: {accuracy['fista50_nrmse_vs_stored_oracle']:.2e}")
 
     # operator alone
     out = torch.empty_like(x)
@@ -446,6 +569,7 @@ def main():
         "stages_note": "one untimed FISTA step with every launch bracketed by HIP events (the events add gaps); "
                        "the timed steps bracket only the roofline kernel",
         "roofline": roof,
+        "accuracy": accuracy,
         "cpu_baseline": None,
     }
     if not args.no_batch:
@@ -457,9 +581,21 @@ def main():
         log("unrolled network training step ...")
         result["unrolled"] = unrolled_bench(max(1, args.steps // 2), 1, args.prec)
         log(f"unrolled: {result['unrolled']['s_per_training_step'] * 1e3:.1f} ms per training step")
+    if not args.no_explicit:
+        log("explicit readout model on a local-B0 map ...")
+        result["explicit_local_b0"] = explicit_bench()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(sl, args.cpu_seconds)
+
+        def gpu_normal(bank, xin):
+            p = gpjc.Plan.from_slice(sl)
+            p.set_compression(torch.as_tensor(bank).to(dev))
+            xt = torch.as_tensor(np.ascontiguousarray(xin[None], np.complex64)).to(dev)
+            out_np = p.normal(xt).cpu().numpy()[0].astype(np.complex128)
+            p.close()
+            return out_np
+
+        result["cpu_baseline"] = cpu_baseline(sl, args.cpu_seconds, gpu_normal)
     print(json.dumps(result), flush=True)
 
 

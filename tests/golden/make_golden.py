@@ -13,6 +13,11 @@ oracle's own FP64 runs, rounded to complex64 for storage:
 * ``batch_largest_cg20.npz`` -- the two largest slices of the 64-slice
   uneven batch (random orthonormal banks and random data, drawn in the same
   order as the batch test), CG-20 on the normal equations (Eq. 16).
+* ``unrolled_fd.npz`` -- the unrolled gradient-descent network at full size
+  (256 x 256, 32 coils, os 8, 64 groups, K = 80; 10 steps
+  x <- x - alpha_k E'^H E' x, i.e. zero data) on image 0: the loss
+  1/2 ||x_10 - truth||^2 at x0 +- eps v for a unit direction v, eps = 1e-3,
+  and their central difference, in FP64.
 
 Run from the repository root:  python tests/golden/make_golden.py [which]
 """
@@ -36,6 +41,7 @@ from paper_2601_05418_amd import synth  # noqa: E402
 from tests import helpers as H  # noqa: E402
 
 FISTA_FILE = os.path.join(HERE, "highfield_fista50.npz")
+UNROLLED_FILE = os.path.join(HERE, "unrolled_fd.npz")
 BATCH_FILE = os.path.join(HERE, "batch_largest_cg20.npz")
 FISTA_ITERS, LEVELS, POWER_ITERS = 50, 3, 50
 
@@ -102,9 +108,52 @@ def batch_largest():
     log(f"wrote {BATCH_FILE}")
 
 
+def unrolled_inputs():
+    """Shared by this script and the full-size unrolled test: slice 0 of the
+    unrolled workload (inputs rounded to complex64), its random orthonormal
+    bank, the batch of starting images x0, the unit direction v on image 0,
+    and the step sizes alpha_k = c_k / L_b with L_b = max_r sum_n |c_n(r)|^2,
+    an upper bound of ||E'^H E'|| (unitary DFTs, unit-modulus PSF, bank rows
+    orthonormal)."""
+    slices = synth.unrolled_slices(8, 0)
+    sl = H.rounded_slice(slices[0])
+    g = sl.geom
+    rng = np.random.default_rng(43)
+    bank = synth.orthonormal_bank(g.n_groups, g.k, g.nc, g.patch_len, rng)
+    x0 = H.round64(0.1 * synth.unit_noise((8, g.ny, g.nx), rng))
+    v = synth.unit_noise((g.ny, g.nx), rng)
+    v = H.round64(v / np.linalg.norm(v))
+    truth = H.round64(np.stack([s.image for s in slices]))
+    lb = float(np.max(np.sum(np.abs(sl.coils) ** 2, axis=0)))
+    alphas = np.asarray(np.linspace(0.6, 1.2, 10) / lb, np.float32).astype(np.float64)
+    return sl, bank, x0, v, truth, alphas
+
+
+def unrolled_fd():
+    sl, bank, x0, v, truth, alphas = unrolled_inputs()
+    g = sl.geom
+    args = (sl.coils, sl.psf, g.mask, g.os, bank, g.patch_group, g.patch_len)
+    eps = 1e-3
+
+    def loss(x):
+        for a in alphas:
+            x = x - a * oe.normal(x, *args)
+        return 0.5 * float(np.vdot(x - truth[0], x - truth[0]).real)
+
+    log("unrolled network, image 0: loss at x0 + eps v")
+    lp = loss(x0[0] + eps * v)
+    log("unrolled network, image 0: loss at x0 - eps v")
+    lm = loss(x0[0] - eps * v)
+    np.savez_compressed(UNROLLED_FILE, eps=eps, loss_plus=lp, loss_minus=lm, fd=(lp - lm) / (2 * eps),
+                        alphas=alphas)
+    log(f"wrote {UNROLLED_FILE}: fd {(lp - lm) / (2 * eps):.9e}")
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("all", "fista"):
         highfield_fista()
     if which in ("all", "batch"):
         batch_largest()
+    if which in ("all", "unrolled"):
+        unrolled_fd()

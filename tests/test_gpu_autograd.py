@@ -145,6 +145,23 @@ def test_step_size_gradients_vs_fp64_autograd_and_differences(gpu_lib):
     err = np.linalg.norm(grad_gpu - grad_ref) / np.linalg.norm(grad_ref)
     print(f"step-size gradient vs FP64 autograd: {err:.2e}", flush=True)
     assert err <= 1e-4
+
+    # central differences at eps = 1e-3 (relative to alpha_k) of the FP64
+    # network: the GPU gradient within 1e-3
+    def loss64(a):
+        xx = x0.copy()
+        for k in range(STEPS):
+            xx = xx - a[k] * (per_image(ops["nrm"], xx) - b.numpy())
+        return 0.5 * np.sum(np.abs(xx - t) ** 2)
+
+    for k in (0, STEPS // 2, STEPS - 1):
+        h = 1e-3 * al[k]
+        ap, am = al.copy(), al.copy()
+        ap[k] += h
+        am[k] -= h
+        fd64 = (loss64(ap) - loss64(am)) / (2 * h)
+        print(f"alpha_{k}: GPU {grad_gpu[k]:.6e}, FP64 differences {fd64:.6e}", flush=True)
+        assert abs(grad_gpu[k] - fd64) <= 1e-3 * abs(fd64)
     assert abs(float(loss.detach()) - float(l64.detach())) <= 1e-5 * float(l64.detach())
 
     # central differences of the GPU loss (quadratic in each step size)
@@ -219,3 +236,65 @@ def test_unrolled_full_size_directional_differences(gpu_lib):
     ga3 = float(net.alpha.grad[3])
     print(f"full size alpha_3: autograd {ga3:.6e}, differences {fa:.6e}", flush=True)
     assert abs(fa - ga3) <= 5e-3 * abs(ga3) + 1e-6 * float(loss.detach())
+
+
+def _adjoint_gap(plan, x, v):
+    """|<E'x, v> - <x, E'^H v>| / (||E'x|| ||v||) with E'^H v from autograd
+    through Encode (its backward is the library's adjoint)."""
+    xt = dev(x).requires_grad_(True)
+    out = ga.Encode.apply(xt, plan)
+    (out.conj() * dev(v)).real.sum().backward()
+    ex = host(out)
+    lhs = np.vdot(ex, v)
+    rhs = np.vdot(x, host(xt.grad))
+    return abs(lhs - rhs) / (np.linalg.norm(ex) * np.linalg.norm(v))
+
+
+def test_adjoint_dot_product_test(gpu_lib):
+    """The dot-product test at 1e-6, normalised by the Cauchy-Schwarz bound
+    ||E'x|| ||v|| (a plain ratio of the two inner products would divide by an
+    inner product of random vectors, itself ~||E'x|| ||v|| / sqrt(n)): on the
+    rect case (B = 2) and at the unrolled network's full size (8 x 256^2, 32
+    coils, os 8, 64 groups, K = 80)."""
+    sl, plan, ops, y, x0, t, lip = setup()
+    gap = _adjoint_gap(plan, x0, y)
+    print(f"rect: adjoint gap {gap:.2e}", flush=True)
+    assert gap <= 1e-6
+    slices = synth.unrolled_slices(8, 0)
+    sl = H.rounded_slice(slices[0])
+    g = sl.geom
+    rng = np.random.default_rng(44)
+    big = gpjc.Plan.from_slice(sl, batch=8)
+    big.set_compression(torch.as_tensor(synth.orthonormal_bank(g.n_groups, g.k, g.nc, g.patch_len, rng)).cuda())
+    x = H.round64(synth.unit_noise(big.image_shape(), rng))
+    v = H.round64(synth.unit_noise(big.data_shape(), rng))
+    gap = _adjoint_gap(big, x, v)
+    print(f"full size: adjoint gap {gap:.2e}", flush=True)
+    assert gap <= 1e-6
+
+
+def test_unrolled_full_size_gradient_vs_fp64_differences(gpu_lib):
+    """Full size (8 x 256^2, 32 coils, os 8, 64 groups, K = 80), zero data:
+    the GPU autograd directional derivative of 1/2 ||x_10 - truth||^2 along a
+    unit direction v on image 0 against central differences at eps = 1e-3 of
+    the same network evaluated in FP64 by the oracle (stored by
+    tests/golden/make_golden.py); relative error <= 1e-3.  (FP32 evaluations
+    of the loss carry ~1e-5 relative rounding, too much for differences at
+    this eps; the quadratic loss has no truncation error.)"""
+    from tests.golden.make_golden import UNROLLED_FILE, unrolled_inputs
+    sl, bank, x0, v, truth, alphas = unrolled_inputs()
+    gold = np.load(UNROLLED_FILE)
+    assert np.array_equal(gold["alphas"], alphas) and float(gold["eps"]) == 1e-3
+    plan = gpjc.Plan.from_slice(sl, batch=8)
+    plan.set_compression(torch.as_tensor(bank).cuda())
+    net = ga.UnrolledGD(plan, steps=STEPS, checkpoint_every=2)
+    with torch.no_grad():
+        net.alpha.copy_(torch.as_tensor(alphas, dtype=torch.float32))
+    y = torch.zeros(plan.data_shape(), dtype=torch.complex64, device="cuda")
+    x = dev(x0).requires_grad_(True)
+    loss = 0.5 * (net(y, x) - dev(truth)).abs().pow(2).sum()
+    loss.backward()
+    ad = float(np.vdot(host(x.grad)[0], v).real)  # dL = Re <g, dx>
+    fd = float(gold["fd"])
+    print(f"full size: autograd {ad:.9e}, FP64 differences {fd:.9e}, rel {abs(ad - fd) / abs(fd):.2e}", flush=True)
+    assert abs(ad - fd) <= 1e-3 * abs(fd)

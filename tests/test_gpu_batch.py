@@ -6,8 +6,10 @@ gpjc_recon_cg calls, so its images and residual histories must equal those
 bit for bit; the graph is replayed across several calls with eager work in
 between, and every replay is checked.  Parity with the oracle is
 same-schedule CG (NRMSE <= 1e-4).  The 64-slice workload uses random
-orthonormal banks and random data: its cost, not its content, matters, and
-two of its slices are checked against the oracle at full size.
+orthonormal banks and random data: its cost, not its content, matters.  Its
+two smallest slices are checked against the oracle run here, its two
+largest (256 x 256, 32 coils, 2048 samples) against the oracle's CG-20
+stored by tests/golden/make_golden.py.
 """
 import dataclasses
 import os
@@ -180,14 +182,28 @@ def c4_plans(n=64):
     return slices, plans, banks, ys
 
 
+GOLDEN_BATCH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_largest_cg20.npz")
+
+
 def test_batch_64_uneven_slices(gpu_lib):
     slices, plans, banks, ys = c4_plans()
-    print(f"64 slices: W total {sum(p.nc * p.ny * p.nt * 8 for p in plans) / 1e9:.2f} GB", flush=True)
+    print(f"64 slices: W total {sum(p.nc * p.ny * p.nt * 8 for p in plans) / 1e9:.2f} GB; patch lengths "
+          f"{sorted(set(p.patch_len for p in plans))}", flush=True)
     batch = gpjc.Batch(plans)
     xs, hs = batch.recon_cg([dev(y) for y in ys], 20, want_resid=True)
     assert np.all(np.isfinite(hs)) and np.all(hs[:, -1] < hs[:, 0])
-    # two full-size slices against the oracle's same-schedule CG
     order = sorted(range(64), key=lambda i: plans[i].nc * plans[i].ny * plans[i].nt)
+    # the two largest slices against the oracle's stored same-schedule CG-20
+    gold = np.load(GOLDEN_BATCH)
+    assert list(gold["index"]) == order[-2:]
+    for i in order[-2:]:
+        g = slices[i].geom
+        e = osv.nrmse(host(xs[i])[0], gold[f"x{i}"].astype(np.complex128))
+        print(f"slice {i} ({g.nx}x{g.ny}, nc {g.nc}, os {g.os}, P {g.patch_len}, K {g.k}): NRMSE vs stored "
+              f"oracle {e:.2e}", flush=True)
+        assert e <= H.NRMSE_RECON
+        assert np.allclose(hs[i], gold[f"resid{i}"], rtol=1e-3)
+    # the two smallest against the oracle's same-schedule CG run here
     for i in order[:2]:
         sl = H.rounded_slice(slices[i])
         g = sl.geom

@@ -120,3 +120,36 @@ def test_stage_timing_select_times_only_named_stages(gpu_lib):
     assert t["group_expand"][1] == 5 and t["group_expand"][0] > 0
     assert all(v[1] == 0 for k, v in t.items() if k != "group_expand")
     assert plan.lib.gpjc_stage_timing_select(plan.handle, 1 << len(gpjc.STAGES)) == gpjc.GPJC_E_INVAL
+
+
+def test_highfield_fista50_against_stored_oracle(gpu_lib):
+    """The benchmark's reconstruction end to end: 224 x 224, 32 coils, 42
+    groups of 32, K = 64, R = 4 + 16 ACS, SNR 30.  The GPU calibrates its own
+    bank, compresses the acquired k-space (Eq. 13) and runs FISTA-50 with
+    3-level Haar and the oracle's lambda and L (Section 3.4, Eq. 17).  FISTA
+    depends on the bank only through the projectors A_g^H A_g, so the result
+    must match the oracle's stored same-schedule run (its own calibration) to
+    NRMSE <= 1e-4, and the objective history to 1e-5 relative.  The GPU's own
+    lambda = 1e-3 max|W E'^H S'| and power-iteration L from the same start
+    agree with the oracle's."""
+    from tests.golden.make_golden import FISTA_FILE, FISTA_ITERS, LEVELS, POWER_ITERS, highfield_inputs
+    gold = np.load(FISTA_FILE)
+    lam, lip = float(gold["lam"]), float(gold["lip"])
+    sl, s = highfield_inputs()
+    g = sl.geom
+    plan = gpjc.Plan.from_slice(sl)
+    plan.calibrate()
+    y = plan.compress(dev(s[None]))
+    x, obj = plan.recon_fista(y, FISTA_ITERS, lam, lip, levels=LEVELS, want_obj=True)
+    e = osv.nrmse(host(x)[0], gold["x"].astype(np.complex128))
+    rel = np.abs(obj - gold["obj"]) / gold["obj"]
+    print(f"FISTA-{FISTA_ITERS}: NRMSE vs stored oracle {e:.2e}; objective rel err max {rel.max():.2e}", flush=True)
+    assert e <= H.NRMSE_RECON
+    assert rel.max() <= 1e-5
+    lam_gpu = 1e-3 * plan.wavelet_absmax(plan.adjoint(y), LEVELS)
+    rng = np.random.default_rng(0)  # the oracle's power-iteration start
+    v0 = rng.standard_normal((g.ny, g.nx)) + 1j * rng.standard_normal((g.ny, g.nx))
+    lip_gpu = 1.01 * plan.power_iteration(dev(v0[None]), POWER_ITERS)
+    print(f"lambda {lam_gpu:.6e} vs {lam:.6e}; L {lip_gpu:.6e} vs {lip:.6e}", flush=True)
+    assert abs(lam_gpu - lam) <= 1e-5 * lam
+    assert abs(lip_gpu - lip) <= 1e-5 * lip
