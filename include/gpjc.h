@@ -212,6 +212,24 @@ int gpjc_gd_step_backward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64*
 int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
                      double lambda, double lipschitz, int haar_levels, double* h_obj);
 
+/* Reconstruction algorithm #1 (Section 3.4, Fig. 6A): hybrid-space least
+ * squares (Eq. 16) for a regular R-fold mask without calibration lines (the
+ * acquired lines are exactly those with (ky - Ny/2) divisible by R; else
+ * GPJC_E_UNSUPPORTED).  The zero-filled inverse DFT of d_y along the phase
+ * encodes folds image rows yr + q Ny/R (q < R) onto each other, so Eq. 16
+ * splits into Ny/R independent readout problems per image (unknowns: R Nx
+ * pixels; data: the Np K compressed samples of one line), each solved by LSQR
+ * (Paige and Saunders) from zero for `iters` iterations; all sets advance
+ * together through the operator's column stages, and each set's norms and
+ * scalars are its own (FP64, fixed reduction order), so each set follows its
+ * own LSQR recurrence.  d_y in gpjc_forward's layout, d_x [B][ny][nx] receives
+ * the assembled image.  h_resid [iters+1] (optional) receives
+ * sqrt(sum over sets of the LSQR residual estimate^2) = ||E' x_k - y||.
+ * Compressed plans (Wave or modulation map), at most 1024 sets (B Ny/R).
+ * Synchronises; GPJC_E_NUMERIC on a non-finite residual. */
+int gpjc_recon_lsqr(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
+                    double* h_resid);
+
 /* Largest eigenvalue of E'^H E' (the Lipschitz constant of FISTA's
  * gradient) by power iteration from the caller's start d_x0 [B][ny][nx]
  * (normalised first): v <- A v / ||A v||, lambda_k = <v_{k-1}, A v_{k-1}>.

@@ -522,6 +522,22 @@ int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_
                                  iters, lambda, lipschitz, haar_levels, h_obj));
 }
 
+int gpjc_recon_lsqr(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
+                    double* h_resid) {
+  GPJC_TRY(check_plan(plan));
+  Store st;
+  GPJC_TRY(check_prec(*plan, prec, &st));
+  if (!plan->compressed) return fail(GPJC_E_UNSUPPORTED, "algorithm #1 is built for compressed plans");
+  if (!d_y || !d_x || !aligned(d_y, 8) || !aligned(d_x, 8)) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
+  if (iters < 0 || iters + 1 > plan->hist_cap) return fail(GPJC_E_INVAL, "iters out of range");
+  if (!regular_accel(*plan))
+    return fail(GPJC_E_UNSUPPORTED, "algorithm #1 needs a regular R-fold mask without calibration lines");
+  if (4L * plan->B * plan->ms > 4096) return fail(GPJC_E_UNSUPPORTED, "more than 1024 aliased sets");
+  GPJC_TRY(check_bank(*plan));
+  return finish(*plan, run_lsqr(*plan, st, reinterpret_cast<const float2*>(d_y), reinterpret_cast<float2*>(d_x), iters,
+                                h_resid));
+}
+
 int gpjc_power_iteration(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x0, int iters, double* h_lambda) {
   GPJC_TRY(check_plan(plan));
   Store st;

@@ -1117,6 +1117,18 @@ int op_adjoint_part(const Plan& pl, Store st, const float2* in) {
   return launch_readout_adj(pl, st);
 }
 
+int op_fwd_columns(const Plan& pl, Store st, const float2* img) {
+  if (pl.general) return launch_explicit_fwd(pl, img);
+  GPJC_TRY(launch_readout_fwd(pl, img, st));
+  return launch_group_compress(pl, st);
+}
+
+int op_adj_columns(const Plan& pl, Store st) {
+  if (pl.general) return launch_explicit_adj(pl);
+  GPJC_TRY(launch_group_expand(pl, st));
+  return launch_readout_adj(pl, st);
+}
+
 int op_normal_part(const Plan& pl, Store st, const float2* img) {
   if (pl.general) {
     GPJC_TRY(launch_explicit_fwd(pl, img));

@@ -163,6 +163,14 @@ int launch_compress_data(const Plan& pl, const float2* ksp, float2* out);
 int op_forward(const Plan& pl, Store st, const float2* img, float2* out);
 int op_adjoint_part(const Plan& pl, Store st, const float2* in);  // result in pl.part
 int op_normal_part(const Plan& pl, Store st, const float2* img);  // result in pl.part
+// The column stages alone (compressed plans): readout model and group
+// contraction per image column, without the phase-encode DFT.
+int op_fwd_columns(const Plan& pl, Store st, const float2* img);  // img -> Zp (split partials)
+int op_adj_columns(const Plan& pl, Store st);                      // Z^T -> pl.part
+
+// ---- reconstruction algorithm #1 (hybrid.hip) ----
+int regular_accel(const Plan& pl);  // R of a regular mask without calibration lines, else 0
+int run_lsqr(Plan& pl, Store st, const float2* y, float2* x, int iters, double* h_resid);
 
 // ---- calibration (calib.hip) ----
 int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out);

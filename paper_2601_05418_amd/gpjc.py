@@ -69,6 +69,7 @@ _SIGS = {
     "gpjc_normal": (_I, [_VP, _I, _VP, _VP]),
     "gpjc_recon_cg": (_I, [_VP, _I, _VP, _VP, _I, _I, _VP]),
     "gpjc_recon_fista": (_I, [_VP, _I, _VP, _VP, _I, _D, _D, _I, _VP]),
+    "gpjc_recon_lsqr": (_I, [_VP, _I, _VP, _VP, _I, _VP]),
     "gpjc_power_iteration": (_I, [_VP, _I, _VP, _I, _VP]),
     "gpjc_wavelet_absmax": (_I, [_VP, _VP, _I, _VP]),
     "gpjc_stage_timing": (_I, [_VP, _I]),
@@ -315,6 +316,16 @@ class Plan:
                                          float(lipschitz), int(levels),
                                          None if obj is None else obj.ctypes.data_as(ctypes.c_void_p)))
         return (x, obj) if want_obj else x
+
+    def recon_lsqr(self, y, iters, prec="fp32", want_resid=False):
+        """Reconstruction algorithm #1: LSQR over the aliased sets of a regular
+        mask; returns the image (and the residual norm per iteration)."""
+        x = self._empty(self.image_shape())
+        hist = np.zeros(int(iters) + 1, np.float64) if want_resid else None
+        self._begin()
+        _check(self.lib.gpjc_recon_lsqr(self.handle, _prec(prec), self._in(y), _ptr(x), int(iters),
+                                        None if hist is None else hist.ctypes.data_as(ctypes.c_void_p)))
+        return (x, hist) if want_resid else x
 
     def power_iteration(self, x0, iters=50, prec="fp32"):
         self._begin()
