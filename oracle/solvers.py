@@ -4,10 +4,10 @@ TEST INFRASTRUCTURE (see the package docstring of ``oracle.encoding``).
 
 * Least squares (Eq. 16) is solved by conjugate gradients on the normal
   equations E'^H E' x = E'^H S', which has the same minimiser.
-* The regularised problem (Eq. 17, wavelet term only) is solved by FISTA
-  (Beck and Teboulle) on 1/2 ||E' x - S'||^2 + lam ||W x||_1, W an
-  orthonormal separable Haar transform; the wavelet term is applied by
-  soft-thresholding (Section 3.4).
+* The regularised problem (Eq. 17) is solved by FISTA (Beck and Teboulle) on
+  1/2 ||E' x - S'||^2 + lam_tv TV_eps(x) + lam ||W x||_1, W an orthonormal
+  separable Haar transform; the wavelet term is applied by soft-thresholding
+  and the total variation through a smooth approximation (Section 3.4).
 * Quality: NRMSE normalised by the range of the reference (Section 3.4).
 """
 from __future__ import annotations
@@ -118,6 +118,63 @@ def fista(normal_op, b, iters, lam, lipschitz, levels, objective=None):
     objs = []
     for _ in range(iters):
         grad = normal_op(y) - b
+        x = wavelet_prox(y - grad / lipschitz, lam / lipschitz, levels)
+        t_next = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        y = x + ((t - 1.0) / t_next) * (x - x_prev)
+        x_prev, t = x, t_next
+        if objective is not None:
+            objs.append(objective(x))
+    return x_prev, np.array(objs)
+
+
+# ----------------------------------------------------------------------------
+# Total variation (Eq. 17's TV term), smoothed as the paper does in practice:
+#   TV_eps(x) = sum over pixels of sqrt(|Dx x|^2 + |Dy x|^2 + eps^2),
+# Dx, Dy forward differences along x and y with a zero difference at the last
+# column / row.  Its gradient (the conjugate-Wirtinger gradient, as used for
+# 1/2 ||E'x - S'||^2) is D^H (D x / m), m = sqrt(|Dx x|^2 + |Dy x|^2 + eps^2);
+# it is Lipschitz with constant ||D||^2 / eps <= 8 / eps.
+# ----------------------------------------------------------------------------
+def tv_diff(x):
+    dx = np.zeros_like(x)
+    dy = np.zeros_like(x)
+    dx[:, :-1] = x[:, 1:] - x[:, :-1]
+    dy[:-1, :] = x[1:, :] - x[:-1, :]
+    return dx, dy
+
+
+def tv_diff_adj(qx, qy):
+    """D^H (qx, qy): the adjoint of tv_diff."""
+    out = np.zeros_like(qx)
+    out[:, :-1] -= qx[:, :-1]
+    out[:, 1:] += qx[:, :-1]
+    out[:-1, :] -= qy[:-1, :]
+    out[1:, :] += qy[:-1, :]
+    return out
+
+
+def tv_smooth(x, eps):
+    dx, dy = tv_diff(x)
+    return float(np.sum(np.sqrt(np.abs(dx) ** 2 + np.abs(dy) ** 2 + eps * eps)))
+
+
+def tv_grad(x, eps):
+    dx, dy = tv_diff(x)
+    m = np.sqrt(np.abs(dx) ** 2 + np.abs(dy) ** 2 + eps * eps)
+    return tv_diff_adj(dx / m, dy / m)
+
+
+def fista_tv(normal_op, b, iters, lam, lam_tv, eps, lipschitz, levels, objective=None):
+    """FISTA on 1/2 ||E'x - S'||^2 + lam_tv TV_eps(x) + lam ||W x||_1 (Eq. 17):
+    the smoothed TV term joins the gradient step, the wavelet term stays the
+    proximal step; step 1/L with L >= ||E'^H E'|| + 8 lam_tv / eps.
+    lam_tv = 0 is :func:`fista`."""
+    x_prev = np.zeros_like(b)
+    y = np.zeros_like(b)
+    t = 1.0
+    objs = []
+    for _ in range(iters):
+        grad = normal_op(y) - b + lam_tv * tv_grad(y, eps)
         x = wavelet_prox(y - grad / lipschitz, lam / lipschitz, levels)
         t_next = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
         y = x + ((t - 1.0) / t_next) * (x - x_prev)

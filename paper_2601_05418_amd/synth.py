@@ -186,6 +186,47 @@ def pe_mask(ny: int, accel: int, acs: int) -> np.ndarray:
     return m.astype(np.uint8)
 
 
+def poisson_disc_mask(ny: int, accel: float, rng: np.random.Generator, center: int = 8,
+                      density_power: float = 2.0, max_tries: int = 2000) -> np.ndarray:
+    """Variable-density Poisson-disc phase-encode mask [ny] (the PD-VD
+    undersampling of Section 3.4, here drawn by the project rather than by an
+    external tool): the `center` lines around ky = 0 are always acquired;
+    further lines are accepted in random order (dart throwing) if no acquired
+    line lies within r(ky) = r0 (1 + |ky| / (ny/2))^density_power, and r0 is
+    set by bisection so that about ny / accel lines are acquired."""
+    ky = np.arange(ny) - ny // 2
+    target = max(center, int(round(ny / accel)))
+
+    def draw(r0, seed_rng):
+        m = np.zeros(ny, bool)
+        m[np.abs(ky + 0.5) < center / 2] = True
+        order = seed_rng.permutation(ny)
+        radius = r0 * (1.0 + np.abs(ky) / (ny / 2)) ** density_power
+        for i in order:
+            if m[i]:
+                continue
+            lo, hi = int(np.floor(i - radius[i])), int(np.ceil(i + radius[i]))
+            near = np.nonzero(m[max(0, lo):min(ny, hi + 1)])[0] + max(0, lo)
+            if np.all(np.abs(near - i) >= radius[i]):
+                m[i] = True
+        return m
+
+    state = rng.bit_generator.state
+    lo, hi = 0.0, float(ny)
+    best = None
+    for _ in range(40):
+        r0 = 0.5 * (lo + hi)
+        rng.bit_generator.state = state
+        m = draw(r0, rng)
+        if best is None or abs(int(m.sum()) - target) < abs(int(best.sum()) - target):
+            best = m
+        if m.sum() > target:
+            lo = r0
+        else:
+            hi = r0
+    return best.astype(np.uint8)
+
+
 def sequential_groups(n_patches: int) -> np.ndarray:
     return np.arange(n_patches, dtype=np.int32)
 

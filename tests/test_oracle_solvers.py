@@ -216,3 +216,62 @@ def test_nrmse_hand_example():
     ref = np.array([1.0, 3.0, 2.0, 5.0])
     x = ref + np.array([0.4, 0, 0, 0])
     assert osv.nrmse(x, ref) == pytest.approx(0.2 / 4.0)
+
+
+# ---------------------------------------------------------------------------
+# Total variation (smoothed) and FISTA with it (Eq. 17)
+# ---------------------------------------------------------------------------
+def _crandn(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def test_tv_difference_adjoint_and_norm_bound():
+    rng = np.random.default_rng(0)
+    x = _crandn(rng, (12, 10))
+    qx, qy = _crandn(rng, (12, 10)), _crandn(rng, (12, 10))
+    dx, dy = osv.tv_diff(x)
+    lhs = np.vdot(dx, qx) + np.vdot(dy, qy)
+    assert abs(lhs - np.vdot(x, osv.tv_diff_adj(qx, qy))) <= 1e-12 * abs(lhs)
+    v = _crandn(rng, (12, 10))
+    for _ in range(200):  # power iteration on D^H D
+        v = osv.tv_diff_adj(*osv.tv_diff(v))
+        lam = np.linalg.norm(v)
+        v /= lam
+    assert lam <= 8.0
+
+
+def test_tv_hand_example_and_constant_image():
+    x = np.array([[0.0, 3.0], [4.0, 0.0]], complex)
+    # pixel (0,0): dx = 3, dy = 4 -> 5; (0,1): dx = 0, dy = -3 -> 3; (1,0): dx = -4 -> 4; (1,1): 0
+    assert abs(osv.tv_smooth(x, 0.0) - 12.0) <= 1e-12
+    c = np.full((6, 5), 2.0 - 1.0j)
+    assert abs(osv.tv_smooth(c, 0.1) - 30 * 0.1) <= 1e-12
+    assert np.all(osv.tv_grad(c, 0.1) == 0)
+
+
+def test_tv_gradient_against_differences():
+    """Re <grad, v> = d/dt TV_eps(x + t v) at t = 0 (central differences, FP64)."""
+    rng = np.random.default_rng(1)
+    x, v = _crandn(rng, (9, 11)), _crandn(rng, (9, 11))
+    h = 1e-6
+    fd = (osv.tv_smooth(x + h * v, 0.05) - osv.tv_smooth(x - h * v, 0.05)) / (2 * h)
+    ad = np.vdot(osv.tv_grad(x, 0.05), v).real
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+def test_fista_tv_reduces_to_fista_and_reaches_a_stationary_point():
+    rng = np.random.default_rng(2)
+    n = 16
+    q = _crandn(rng, (n * n, n * n)) / n
+    a = q.conj().T @ q + 0.5 * np.eye(n * n)
+    op = lambda v: (a @ v.reshape(-1)).reshape(n, n)
+    b = _crandn(rng, (n, n))
+    lip = np.linalg.eigvalsh(a).max()
+    x1, _ = osv.fista(op, b, 30, 0.1, lip * 1.01, 2)
+    x2, _ = osv.fista_tv(op, b, 30, 0.1, 0.0, 0.05, lip * 1.01, 2)
+    assert np.array_equal(x1, x2)
+    # lam = 0: the minimiser of the smooth objective, where its gradient vanishes
+    lam_tv, eps = 0.3, 0.1
+    x, _ = osv.fista_tv(op, b, 3000, 0.0, lam_tv, eps, lip + 8 * lam_tv / eps, 2)
+    g = op(x) - b + lam_tv * osv.tv_grad(x, eps)
+    assert np.linalg.norm(g) <= 1e-6 * np.linalg.norm(b)
