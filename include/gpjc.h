@@ -212,6 +212,19 @@ int gpjc_gd_step_backward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64*
 int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
                      double lambda, double lipschitz, int haar_levels, double* h_obj);
 
+/* FISTA on the full Eq. 17 (Section 3.4): 1/2 ||E' x - y||^2 +
+ * lambda_tv TV_eps(x) + lambda ||W x||_1, with the total variation in the
+ * smooth approximation TV_eps(x) = sum over pixels of
+ * sqrt(|Dx x|^2 + |Dy x|^2 + tv_eps^2) (Dx, Dy forward differences, zero at
+ * the last column / row of each image), whose gradient
+ * D^H (D x / sqrt(|D x|^2 + tv_eps^2)) joins the gradient step; the wavelet
+ * term stays the proximal step.  lipschitz must bound ||E'^H E'|| +
+ * 8 lambda_tv / tv_eps.  Otherwise as gpjc_recon_fista (which is the
+ * lambda_tv = 0 case); h_obj includes the TV term. */
+int gpjc_recon_fista_tv(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
+                        double lambda, double lambda_tv, double tv_eps, double lipschitz, int haar_levels,
+                        double* h_obj);
+
 /* Reconstruction algorithm #1 (Section 3.4, Fig. 6A): hybrid-space least
  * squares (Eq. 16) for a regular R-fold mask without calibration lines (the
  * acquired lines are exactly those with (ky - Ny/2) divisible by R; else

@@ -506,6 +506,13 @@ int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64
 
 int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, double lambda,
                      double lipschitz, int haar_levels, double* h_obj) {
+  return gpjc_recon_fista_tv(plan, prec, d_y, d_x, iters, lambda, 0.0, 1.0, lipschitz, haar_levels, h_obj);
+}
+
+int gpjc_recon_fista_tv(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, double lambda,
+                        double lambda_tv, double tv_eps, double lipschitz, int haar_levels, double* h_obj) {
+  if (!(lambda_tv >= 0.0) || !std::isfinite(lambda_tv)) return fail(GPJC_E_INVAL, "lambda_tv must be >= 0");
+  if (!(tv_eps > 0.0) || !std::isfinite(tv_eps)) return fail(GPJC_E_INVAL, "tv_eps must be positive");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -519,7 +526,7 @@ int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_
   if (h_obj && iters > plan->hist_cap) return fail(GPJC_E_INVAL, "iters too large for the objective history");
   GPJC_TRY(check_bank(*plan));
   return finish(*plan, run_fista(*plan, st, reinterpret_cast<const float2*>(d_y), reinterpret_cast<float2*>(d_x),
-                                 iters, lambda, lipschitz, haar_levels, h_obj));
+                                 iters, lambda, lambda_tv, tv_eps, lipschitz, haar_levels, h_obj));
 }
 
 int gpjc_recon_lsqr(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,

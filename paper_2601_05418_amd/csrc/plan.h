@@ -189,8 +189,8 @@ bool cg_refresh_at(int it, int iters, int refine_every, Store st);
 
 // ---- GEMM tile autotuning (tune.hip) ----
 int autotune(Plan& pl, Store st, const char* cache_path, int* h_choice);
-int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lip,
-              int levels, double* h_obj);
+int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lam_tv, double eps,
+              double lip, int levels, double* h_obj);
 
 int run_power_iteration(Plan& pl, Store st, const float2* x0, int iters, double* h_lambda);
 int run_gd_step(const Plan& pl, Store st, const float2* x, const float2* b, const float* alpha, float2* x_out,

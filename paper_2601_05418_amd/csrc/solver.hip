@@ -455,7 +455,8 @@ __device__ inline float2 haar_lanes(float2 v, int i, int j, bool inverse) {
 // pixels per tile, whole tiles per wave.
 template <int LEV>
 __global__ __launch_bounds__(256) void k_fista_step(const float2* __restrict__ part, int nchunk,
-                                                    const float2* __restrict__ bvec, float2* __restrict__ yv,
+                                                    const float2* __restrict__ bvec, const float2* __restrict__ tvg,
+                                                    float lam_tv, float2* __restrict__ yv,
                                                     float2* __restrict__ xprev, int nx, int ny, int B, float invL,
                                                     float thr, float mom) {
   constexpr int S = 1 << LEV, T = S * S;
@@ -471,7 +472,11 @@ __global__ __launch_bounds__(256) void k_fista_step(const float2* __restrict__ p
   const int ty = rem / tx_n, tx = rem - ty * tx_n;
   const size_t n = (size_t)B * nx * ny;
   const size_t idx = ((size_t)b * ny + ty * S + i) * nx + tx * S + j;
-  const float2 g = csub(sum_chunks(part, nchunk, n, idx), bvec[idx]);
+  float2 g = csub(sum_chunks(part, nchunk, n, idx), bvec[idx]);
+  if (lam_tv != 0.f) {
+    const float2 t = tvg[idx];
+    g = make_float2(fmaf(lam_tv, t.x, g.x), fmaf(lam_tv, t.y, g.y));
+  }
   const float2 yy = yv[idx];
   float2 c = make_float2(fmaf(-invL, g.x, yy.x), fmaf(-invL, g.y, yy.y));
   c = haar_lanes<LEV>(c, i, j, false);
@@ -488,13 +493,69 @@ __global__ __launch_bounds__(256) void k_fista_step(const float2* __restrict__ p
 }
 
 template <int LEV>
-static int launch_fista_step(const Plan& pl, float invL, float thr, float mom) {
+static int launch_fista_step(const Plan& pl, float invL, float thr, float mom, float lam_tv) {
   StageScope sc(pl, GPJC_STAGE_SOLVER);
   const size_t lanes = pl.img_elems();
   hipLaunchKernelGGL(k_fista_step<LEV>, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, pl.stream, pl.part,
-                     pl.f1h_nchunk, pl.vb, pl.vp, pl.vx, pl.nx, pl.ny, pl.B, invL, thr, mom);
+                     pl.f1h_nchunk, pl.vb, pl.vq, lam_tv, pl.vp, pl.vx, pl.nx, pl.ny, pl.B, invL, thr, mom);
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Smoothed total variation (Eq. 17's TV term): TV_eps(x) = sum over pixels of
+// sqrt(|Dx x|^2 + |Dy x|^2 + eps^2), forward differences with a zero
+// difference at the last column / row of each image.
+// ---------------------------------------------------------------------------
+// q = D x / m at pixel (i, j) of image b (zero outside the image)
+__device__ inline void tv_q(const float2* __restrict__ x, int b, int i, int j, int nx, int ny, float eps2,
+                            float2* qx, float2* qy) {
+  if (i < 0 || j < 0) {
+    *qx = *qy = make_float2(0.f, 0.f);
+    return;
+  }
+  const float2* xb = x + (size_t)b * ny * nx;
+  const float2 c = xb[(size_t)i * nx + j];
+  const float2 dx = j + 1 < nx ? csub(xb[(size_t)i * nx + j + 1], c) : make_float2(0.f, 0.f);
+  const float2 dy = i + 1 < ny ? csub(xb[(size_t)(i + 1) * nx + j], c) : make_float2(0.f, 0.f);
+  const float inv = rsqrtf(dx.x * dx.x + dx.y * dx.y + dy.x * dy.x + dy.y * dy.y + eps2);
+  *qx = cscale(dx, inv);
+  *qy = cscale(dy, inv);
+}
+
+// g = D^H (D x / m): the gradient of TV_eps at x
+__global__ __launch_bounds__(256) void k_tv_grad(const float2* __restrict__ x, float2* __restrict__ g, int nx, int ny,
+                                                 int B, float eps2) {
+  const size_t n = (size_t)B * ny * nx;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx % nx);
+    const int i = (int)((idx / nx) % ny);
+    const int b = (int)(idx / ((size_t)nx * ny));
+    float2 qx, qy, qxl, qyl, qxu, qyu;
+    tv_q(x, b, i, j, nx, ny, eps2, &qx, &qy);
+    tv_q(x, b, i, j - 1, nx, ny, eps2, &qxl, &qyl);
+    tv_q(x, b, i - 1, j, nx, ny, eps2, &qxu, &qyu);
+    // (D^H q)[i][j] = qx[i][j-1] - qx[i][j] + qy[i-1][j] - qy[i][j]  (qx = 0 at j = nx-1, qy = 0 at i = ny-1)
+    g[idx] = make_float2(qxl.x - qx.x + qyu.x - qy.x, qxl.y - qx.y + qyu.y - qy.y);
+  }
+}
+
+// partial sums of TV_eps(x) on the fixed grid
+__global__ __launch_bounds__(256) void k_tv_value(const float2* __restrict__ x, double* __restrict__ red, int nx,
+                                                  int ny, int B, double eps2) {
+  __shared__ double sh[8];
+  const size_t n = (size_t)B * ny * nx;
+  double acc = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx % nx);
+    const int i = (int)((idx / nx) % ny);
+    const float2 c = x[idx];
+    const float2 dx = j + 1 < nx ? csub(x[idx + 1], c) : make_float2(0.f, 0.f);
+    const float2 dy = i + 1 < ny ? csub(x[idx + nx], c) : make_float2(0.f, 0.f);
+    acc += sqrt((double)dx.x * dx.x + (double)dx.y * dx.y + (double)dy.x * dy.x + (double)dy.y * dy.y + eps2);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -546,13 +607,15 @@ __global__ __launch_bounds__(256) void k_wavelet_l1(const float2* __restrict__ i
   if (threadIdx.x == 0) red[blockIdx.x] = s;
 }
 
-// *out = 1/2 sum(red_d) + lambda sum(red_w); single block
-__global__ void k_store_obj(const double* __restrict__ red_d, const double* __restrict__ red_w, int nb, double lambda,
+// *out = 1/2 sum(red_d) + lambda sum(red_w) + lambda_tv sum(red_t); single block
+__global__ void k_store_obj(const double* __restrict__ red_d, const double* __restrict__ red_w,
+                            const double* __restrict__ red_t, int nb, double lambda, double lambda_tv,
                             double* __restrict__ out) {
   __shared__ double sh[8];
   const double d = sum_partials(red_d, nb, sh);
   const double w = sum_partials(red_w, nb, sh);
-  if (threadIdx.x == 0) *out = 0.5 * d + lambda * w;
+  const double t = lambda_tv != 0.0 ? sum_partials(red_t, nb, sh) : 0.0;
+  if (threadIdx.x == 0) *out = 0.5 * d + lambda * w + lambda_tv * t;
 }
 
 __global__ __launch_bounds__(256) void k_norm2(const float2* __restrict__ v, double* __restrict__ red, size_t n);
@@ -570,24 +633,28 @@ static size_t data_elems(const Plan& pl) {
 
 // Objective of x = pl.vx into *out (device): forward application into pl.vd,
 // then the two reductions.
-static int fista_objective(const Plan& pl, Store st, const float2* y, int levels, double lambda, double* out) {
+static int fista_objective(const Plan& pl, Store st, const float2* y, int levels, double lambda, double lam_tv,
+                           double eps, double* out) {
   GPJC_TRY(op_forward(pl, st, pl.vx, pl.vd));
   const int nb = kRedBlocks;
   double* red_d = pl.red;
   double* red_w = pl.red + nb;
+  double* red_t = pl.red + 2 * nb;
+  if (lam_tv != 0.0)
+    hipLaunchKernelGGL(k_tv_value, dim3(nb), dim3(256), 0, pl.stream, pl.vx, red_t, pl.nx, pl.ny, pl.B, eps * eps);
   hipLaunchKernelGGL(k_resid2, dim3(nb), dim3(256), 0, pl.stream, pl.vd, y, red_d, data_elems(pl));
   switch (levels) {
     case 1: hipLaunchKernelGGL(k_wavelet_l1<1>, dim3(nb), dim3(256), 0, pl.stream, pl.vx, pl.nx, pl.ny, pl.B, red_w); break;
     case 2: hipLaunchKernelGGL(k_wavelet_l1<2>, dim3(nb), dim3(256), 0, pl.stream, pl.vx, pl.nx, pl.ny, pl.B, red_w); break;
     default: hipLaunchKernelGGL(k_wavelet_l1<3>, dim3(nb), dim3(256), 0, pl.stream, pl.vx, pl.nx, pl.ny, pl.B, red_w); break;
   }
-  hipLaunchKernelGGL(k_store_obj, dim3(1), dim3(256), 0, pl.stream, red_d, red_w, nb, lambda, out);
+  hipLaunchKernelGGL(k_store_obj, dim3(1), dim3(256), 0, pl.stream, red_d, red_w, red_t, nb, lambda, lam_tv, out);
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
 }
 
-int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lip, int levels,
-              double* h_obj) {
+int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double lambda, double lam_tv, double eps,
+              double lip, int levels, double* h_obj) {
   const size_t n = pl.img_elems();
   GPJC_TRY(op_adjoint_part(pl, st, y));
   GPJC_TRY(launch_combine(pl, pl.vb));
@@ -596,17 +663,24 @@ int run_fista(Plan& pl, Store st, const float2* y, float2* x, int iters, double 
   const float invL = (float)(1.0 / lip);
   const float thr = (float)(lambda / lip);
   double t = 1.0;
+  const float ltv = (float)lam_tv;
   for (int it = 0; it < iters; ++it) {
     GPJC_TRY(op_normal_part(pl, st, pl.vp));
+    if (lam_tv != 0.0) {
+      StageScope sc(pl, GPJC_STAGE_SOLVER);
+      hipLaunchKernelGGL(k_tv_grad, dim3(kRedBlocks), dim3(256), 0, pl.stream, pl.vp, pl.vq, pl.nx, pl.ny, pl.B,
+                         (float)(eps * eps));
+      GPJC_HIP(hipGetLastError());
+    }
     const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
     const float mom = (float)((t - 1.0) / tn);
     t = tn;
     switch (levels) {
-      case 1: GPJC_TRY(launch_fista_step<1>(pl, invL, thr, mom)); break;
-      case 2: GPJC_TRY(launch_fista_step<2>(pl, invL, thr, mom)); break;
-      default: GPJC_TRY(launch_fista_step<3>(pl, invL, thr, mom)); break;
+      case 1: GPJC_TRY(launch_fista_step<1>(pl, invL, thr, mom, ltv)); break;
+      case 2: GPJC_TRY(launch_fista_step<2>(pl, invL, thr, mom, ltv)); break;
+      default: GPJC_TRY(launch_fista_step<3>(pl, invL, thr, mom, ltv)); break;
     }
-    if (h_obj) GPJC_TRY(fista_objective(pl, st, y, levels, lambda, pl.hist + it));
+    if (h_obj) GPJC_TRY(fista_objective(pl, st, y, levels, lambda, lam_tv, eps, pl.hist + it));
   }
   GPJC_TRY(copy_vec(pl, pl.vx, x, n));
   // numeric status: the squared norm of the result, summed in FP64, must be finite

@@ -70,6 +70,7 @@ _SIGS = {
     "gpjc_recon_cg": (_I, [_VP, _I, _VP, _VP, _I, _I, _VP]),
     "gpjc_recon_fista": (_I, [_VP, _I, _VP, _VP, _I, _D, _D, _I, _VP]),
     "gpjc_recon_lsqr": (_I, [_VP, _I, _VP, _VP, _I, _VP]),
+    "gpjc_recon_fista_tv": (_I, [_VP, _I, _VP, _VP, _I, _D, _D, _D, _D, _I, _VP]),
     "gpjc_power_iteration": (_I, [_VP, _I, _VP, _I, _VP]),
     "gpjc_wavelet_absmax": (_I, [_VP, _VP, _I, _VP]),
     "gpjc_stage_timing": (_I, [_VP, _I]),
@@ -315,6 +316,17 @@ class Plan:
         _check(self.lib.gpjc_recon_fista(self.handle, _prec(prec), self._in(y), _ptr(x), int(iters), float(lam),
                                          float(lipschitz), int(levels),
                                          None if obj is None else obj.ctypes.data_as(ctypes.c_void_p)))
+        return (x, obj) if want_obj else x
+
+    def recon_fista_tv(self, y, iters, lam, lam_tv, tv_eps, lipschitz, levels=3, prec="fp32", out=None,
+                       want_obj=False):
+        """FISTA on Eq. 17 with the smoothed TV term (gpjc_recon_fista_tv)."""
+        x = self._empty(self.image_shape()) if out is None else out
+        obj = np.zeros(int(iters), np.float64) if want_obj else None
+        self._begin()
+        _check(self.lib.gpjc_recon_fista_tv(self.handle, _prec(prec), self._in(y), _ptr(x), int(iters), float(lam),
+                                            float(lam_tv), float(tv_eps), float(lipschitz), int(levels),
+                                            None if obj is None else obj.ctypes.data_as(ctypes.c_void_p)))
         return (x, obj) if want_obj else x
 
     def recon_lsqr(self, y, iters, prec="fp32", want_resid=False):
