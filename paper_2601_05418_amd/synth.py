@@ -227,6 +227,80 @@ def poisson_disc_mask(ny: int, accel: float, rng: np.random.Generator, center: i
     return best.astype(np.uint8)
 
 
+def wave_caipi_psf(ny: int, nz: int, nt: int, cycles: int, phase_y: float, phase_z: float) -> np.ndarray:
+    """3D Wave-CAIPI point-spread function [nz][ny][nt]: sinusoidal G_y and
+    cosinusoidal G_z (a corkscrew k-space trajectory),
+        exp(-i [phase_y yn sin(2 pi c t / nt) + phase_z zn cos(2 pi c t / nt)]),
+    yn = (iy - ny/2)/(ny/2), zn = (iz - nz/2)/(nz/2)."""
+    yn = (np.arange(ny) - ny / 2) / (ny / 2)
+    zn = (np.arange(nz) - nz / 2) / (nz / 2)
+    t = 2.0 * np.pi * cycles * np.arange(nt) / nt
+    ph = phase_y * yn[None, :, None] * np.sin(t)[None, None, :] + phase_z * zn[:, None, None] * np.cos(t)[None, None, :]
+    return np.exp(-1j * ph)
+
+
+def caipi_mask(ny: int, nz: int, ry: int, rz: int, shift: int, acs: int = 0) -> np.ndarray:
+    """2D CAIPIRINHA phase-encode mask [nz][ny]: point (kz, ky), with
+    centred coordinates ky - ny/2 = ry a, acquired when
+    (kz - nz/2 - shift a) is divisible by rz; plus an acs x acs centre block."""
+    ky = np.arange(ny) - ny // 2
+    kz = np.arange(nz) - nz // 2
+    m = np.zeros((nz, ny), bool)
+    for iy, y in enumerate(ky):
+        if y % ry:
+            continue
+        a = y // ry
+        m[:, iy] = (kz - shift * a) % rz == 0
+    if acs:
+        cz = np.abs(kz + 0.5) < acs / 2
+        cy = np.abs(ky + 0.5) < acs / 2
+        m[np.ix_(cz, cy)] = True
+    return m.astype(np.uint8)
+
+
+@dataclasses.dataclass
+class Volume:
+    """A 3D volume: geom.ny is the in-plane phase-encode size, nz the second
+    phase-encode size; geom.mask is unused (mask2 [nz][ny] holds the points)."""
+    geom: Geometry
+    nz: int
+    mask2: np.ndarray  # uint8 [nz][ny]
+    image: np.ndarray  # complex128 [nz][ny][nx]
+    coils: np.ndarray  # complex128 [nc][nz][ny][nx]
+    psf: np.ndarray  # complex128 [nz][ny][nt]
+
+    @property
+    def ms(self) -> int:
+        return int(self.mask2.sum())
+
+
+def volume(seed: int = 0, n: int = 32, nz: int = 16, nc: int = 4, os_: int = 4, patch_len: int = 16, k: int = 12,
+           ry: int = 2, rz: int = 2, shift: int = 1, acs: int = 0, cycles: int = 4, phase: float = 3.0,
+           periodic: bool = False) -> Volume:
+    """A seeded 3D Wave-CAIPI volume: n x n x nz, nc coils (3D Gaussian bumps:
+    the 2D maps of each slice scaled by a bump along z), os-fold readout, a
+    corkscrew PSF, an ry x rz CAIPI mask with the given shift.  The phantom is
+    ellipsoidal: the 2D ellipses scaled by a z-profile per ellipse."""
+    rs = _streams(7, seed)
+    nt = os_ * n
+    np_ = nt // patch_len
+    pg = periodic_groups(np_, (nt // cycles) // patch_len) if periodic else sequential_groups(np_)
+    geom = Geometry(nx=n, ny=n, nc=nc, os=os_, patch_len=patch_len, patch_group=pg.astype(np.int32),
+                    n_groups=int(pg.max()) + 1, k=k, mask=np.ones(n, np.uint8))
+    zc = (np.arange(nz) - nz / 2) / nz
+    img = np.zeros((nz, n, n), complex)
+    for e in range(4):
+        sl = ellipse_phantom(n, n, rs[_PHANTOM], n_ellipses=2)
+        z0, zr = rs[_PHANTOM].uniform(-0.2, 0.2), rs[_PHANTOM].uniform(0.15, 0.4)
+        prof = (np.abs(zc - z0) <= zr).astype(float)
+        img = np.where(np.abs(sl)[None] > 0, sl[None] * prof[:, None, None], img)
+    c2 = gaussian_coils(n, n, nc, rs[_COILS])
+    zoff = rs[_B1].uniform(-0.3, 0.3, size=nc)
+    coils = c2[:, None] * np.exp(-((zc[None, :] - zoff[:, None]) ** 2) / (2 * 0.5 ** 2))[:, :, None, None]
+    psf = wave_caipi_psf(n, nz, nt, cycles, phase, phase)
+    return Volume(geom, nz, caipi_mask(n, nz, ry, rz, shift, acs), img, coils, psf)
+
+
 def sequential_groups(n_patches: int) -> np.ndarray:
     return np.arange(n_patches, dtype=np.int32)
 
