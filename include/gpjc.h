@@ -100,6 +100,23 @@ typedef struct gpjc_plan gpjc_plan;
  * (Section 2.3); GPJC_E_INVAL otherwise.  Synchronises. */
 int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_psf,
                      void* hip_stream, gpjc_plan** out);
+/* Create a plan for a 3D volume with two phase-encode dimensions (Section
+ * 3.4: both are reconstructed by FFT; Table S2, Figs. 8-9): geom->ny is the
+ * in-plane phase-encode size, nz the second; images are [B][nz][ny][nx],
+ * d_coils [nc][nz][ny][nx], d_psf [nz][ny][nt] (e.g. the Wave-CAIPI corkscrew
+ * exp(-i k_m(t, y, z))), mask2 host [nz][ny] (nonzero = (kz, ky) acquired;
+ * geom->mask is ignored).  The readout stage, group contraction and
+ * calibration act on the nz * ny rows (z, y) as on the rows of a slice; the
+ * phase-encode stage is the centred unitary 2D DFT over (z, y), and data
+ * (gpjc_forward's output, gpjc_compress's input lines) list the acquired
+ * points in raster order (kz major, ky fastest): Ms = number of them.
+ * Compressed plans only; nx, ny, nz built FFT lengths.  CG, FISTA with the
+ * Haar term (2D Haar of every z partition), batching, autotuning and the
+ * 16-bit precisions work as for slices; algorithm #1 and the TV term are
+ * built for slices (GPJC_E_UNSUPPORTED).  Synchronises. */
+int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, const gpjc_c64* d_coils,
+                        const gpjc_c64* d_psf, void* hip_stream, gpjc_plan** out);
+
 /* Create a plan for a general modulation map (Section 3.1: nonlinear B0
  * fields such as a local B0 coil array; Eqs. 1-3), d_bmod [nt][ny][nx] c64 =
  * exp(-i k_m(t, x, y)), which need not factor into a readout PSF.  The

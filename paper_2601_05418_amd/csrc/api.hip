@@ -52,7 +52,7 @@ static void free_plan(Plan* pl) {
   void* bufs[] = {pl->coils, pl->psf,  pl->psfp, pl->twin, pl->tw_x, pl->tw_y, pl->lines, pl->pgroup,
                   pl->maskf, pl->zeros, pl->A128, pl->Aexp, pl->AH,   pl->W,    pl->Zp,   pl->Zt,    pl->part,
                   pl->vx,    pl->vr,   pl->vp,   pl->vq,   pl->vb,   pl->vd,   pl->red,  pl->hist,  pl->flag,
-                  pl->bmod,  pl->Ec};
+                  pl->bmod,  pl->Ec,   pl->T3,   pl->pts3, pl->sel3, pl->maskf3, pl->tw_y3, pl->tw_z3};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int i = 0; i < 2; ++i) {
@@ -354,6 +354,51 @@ int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_
   return GPJC_OK;
 }
 
+int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, const gpjc_c64* d_coils,
+                        const gpjc_c64* d_psf, void* hip_stream, gpjc_plan** out) {
+  if (!out) return fail(GPJC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!geom) return fail(GPJC_E_INVAL, "geom is NULL");
+  if (nz < 2) return fail(GPJC_E_INVAL, "nz must be >= 2 (use gpjc_plan_create for a 2D slice)");
+  if (!mask2) return fail(GPJC_E_INVAL, "mask2 is NULL");
+  if (!geom->compressed) return fail(GPJC_E_UNSUPPORTED, "3D plans are built for the compressed operator");
+  if ((long)nz * geom->ny > (1L << 20)) return fail(GPJC_E_INVAL, "nz * ny out of range");
+  if (!fft_size_supported(geom->nx) || !fft_size_supported(geom->ny) || !fft_size_supported(nz))
+    return fail(GPJC_E_UNSUPPORTED, "nx, ny and nz must be built FFT lengths");
+  // the 2D machinery on (z, y) rows
+  gpjc_geom g2 = *geom;
+  g2.ny = nz * geom->ny;
+  g2.mask = mask2;
+  GPJC_TRY(validate_geom(&g2));
+  if (!d_coils || !d_psf) return fail(GPJC_E_INVAL, "coil maps or PSF is NULL");
+  if (!aligned(d_coils, 8) || !aligned(d_psf, 8)) return fail(GPJC_E_INVAL, "coil maps / PSF not 8-byte aligned");
+  const long line = 2L * geom->os * fline(geom->nx) + geom->nx;
+  if (line > kLdsSlots || (long)geom->os * geom->nx > 16 * 256)
+    return fail(GPJC_E_UNSUPPORTED, "os * nx too large for the readout stages");
+  gpjc_plan* pl = new (std::nothrow) gpjc_plan();
+  if (!pl) return fail(GPJC_E_NOMEM, "host allocation failed");
+  int s = setup_plan(*pl, &g2, d_coils, d_psf, nullptr, reinterpret_cast<hipStream_t>(hip_stream));
+  if (s == GPJC_OK) {
+    Plan& p = *pl;
+    p.nz = nz;
+    p.ny2 = geom->ny;
+    s = dalloc(&p.T3, (size_t)p.B * p.np * p.K * p.ny);
+    if (s == GPJC_OK) s = dalloc(&p.pts3, (size_t)p.ms);
+    if (s == GPJC_OK) s = dalloc(&p.sel3, (size_t)p.ny);
+    if (s == GPJC_OK) s = dalloc(&p.maskf3, (size_t)p.ny);
+    if (s == GPJC_OK) s = dalloc(&p.tw_y3, (size_t)p.ny2);
+    if (s == GPJC_OK) s = dalloc(&p.tw_z3, (size_t)nz);
+    if (s == GPJC_OK) s = setup_pe3(p, mask2);
+  }
+  if (s != GPJC_OK) {
+    free_plan(pl);
+    delete pl;
+    return s;
+  }
+  *out = pl;
+  return GPJC_OK;
+}
+
 int gpjc_plan_create_bmap(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_bmod, void* hip_stream,
                           gpjc_plan** out) {
   if (!out) return fail(GPJC_E_INVAL, "out is NULL");
@@ -513,6 +558,8 @@ int gpjc_recon_fista_tv(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gp
                         double lambda_tv, double tv_eps, double lipschitz, int haar_levels, double* h_obj) {
   if (!(lambda_tv >= 0.0) || !std::isfinite(lambda_tv)) return fail(GPJC_E_INVAL, "lambda_tv must be >= 0");
   if (!(tv_eps > 0.0) || !std::isfinite(tv_eps)) return fail(GPJC_E_INVAL, "tv_eps must be positive");
+  if (plan && plan->nz > 1 && lambda_tv != 0.0)
+    return fail(GPJC_E_UNSUPPORTED, "the total-variation term is built for 2D slices");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -522,7 +569,9 @@ int gpjc_recon_fista_tv(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gp
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(GPJC_E_INVAL, "lambda must be >= 0");
   if (haar_levels < 1 || haar_levels > 3) return fail(GPJC_E_UNSUPPORTED, "haar_levels must be 1, 2 or 3");
   const int t = 1 << haar_levels;
-  if (plan->nx % t || plan->ny % t) return fail(GPJC_E_INVAL, "nx and ny must be divisible by 2^haar_levels");
+  // 3D volumes: the 2D Haar transform of every z partition (tiles never cross one)
+  const int rows_per_image = plan->nz > 1 ? plan->ny2 : plan->ny;
+  if (plan->nx % t || rows_per_image % t) return fail(GPJC_E_INVAL, "nx and ny must be divisible by 2^haar_levels");
   if (h_obj && iters > plan->hist_cap) return fail(GPJC_E_INVAL, "iters too large for the objective history");
   GPJC_TRY(check_bank(*plan));
   return finish(*plan, run_fista(*plan, st, reinterpret_cast<const float2*>(d_y), reinterpret_cast<float2*>(d_x),
@@ -537,6 +586,7 @@ int gpjc_recon_lsqr(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c
   if (!plan->compressed) return fail(GPJC_E_UNSUPPORTED, "algorithm #1 is built for compressed plans");
   if (!d_y || !d_x || !aligned(d_y, 8) || !aligned(d_x, 8)) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
   if (iters < 0 || iters + 1 > plan->hist_cap) return fail(GPJC_E_INVAL, "iters out of range");
+  if (plan->nz > 1) return fail(GPJC_E_UNSUPPORTED, "algorithm #1 is built for 2D slices");
   if (!regular_accel(*plan))
     return fail(GPJC_E_UNSUPPORTED, "algorithm #1 needs a regular R-fold mask without calibration lines");
   if (4L * plan->B * plan->ms > 4096) return fail(GPJC_E_UNSUPPORTED, "more than 1024 aliased sets");
@@ -560,7 +610,9 @@ int gpjc_wavelet_absmax(gpjc_plan* plan, const gpjc_c64* d_img, int haar_levels,
   if (!d_img || !aligned(d_img, 8) || !h_out) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
   if (haar_levels < 1 || haar_levels > 3) return fail(GPJC_E_UNSUPPORTED, "haar_levels must be 1, 2 or 3");
   const int t = 1 << haar_levels;
-  if (plan->nx % t || plan->ny % t) return fail(GPJC_E_INVAL, "nx and ny must be divisible by 2^haar_levels");
+  // 3D volumes: the 2D Haar transform of every z partition (tiles never cross one)
+  const int rows_per_image = plan->nz > 1 ? plan->ny2 : plan->ny;
+  if (plan->nx % t || rows_per_image % t) return fail(GPJC_E_INVAL, "nx and ny must be divisible by 2^haar_levels");
   return finish(*plan, run_wavelet_absmax(*plan, reinterpret_cast<const float2*>(d_img), haar_levels, h_out));
 }
 

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_build_explicit(const double2* __restric
 
 // Forward: one wave per row (rows strided over the work-group's four waves),
 // lanes along x in 16-byte pairs of complex values, XB pairs per lane; BC
-// images from b0 on.  Each row's sums are reduced across the wave in a fixed
+// images (up to 8, one pass over E' per 8 images) from b0 on.  Each row's sums are reduced across the wave in a fixed
 // butterfly order.
 template <int BC, int XB>
 __global__ __launch_bounds__(256) void k_explicit_fwd(const float2* __restrict__ Ec, const float2* __restrict__ img,
@@ -152,14 +152,24 @@ __global__ __launch_bounds__(256) void k_explicit_adj(const float2* __restrict__
 #pragma unroll
     for (int b = 0; b < BC; ++b) acc[b] = make_float2(0.f, 0.f);
     if (act) {
+      // eight rows' loads in flight before their products (rows past the
+      // chunk load row nr - 1 and are weighted by zero)
       const float2* col = Ec + ((size_t)y * rows + r_beg) * nx + x;
-      for (int rr = sub; rr < nr; rr += nsub) {
-        const float2 e = col[(size_t)rr * nx];
+      for (int r0 = sub; r0 < nr; r0 += 8 * nsub) {
+        float2 e[8];
 #pragma unroll
-        for (int b = 0; b < BC; ++b) {
-          const float2 z = zs[b][rr];
-          acc[b].x += e.x * z.x + e.y * z.y;  // conj(e) z
-          acc[b].y += e.x * z.y - e.y * z.x;
+        for (int u = 0; u < 8; ++u) e[u] = col[(size_t)min(r0 + u * nsub, nr - 1) * nx];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int rr = r0 + u * nsub;
+          if (rr < nr) {
+#pragma unroll
+            for (int b = 0; b < BC; ++b) {
+              const float2 z = zs[b][rr];
+              acc[b].x += e[u].x * z.x + e[u].y * z.y;  // conj(e) z
+              acc[b].y += e[u].x * z.y - e[u].y * z.x;
+            }
+          }
         }
       }
     }
@@ -197,7 +207,7 @@ void launch_fwd_bc(const Plan& pl, const float2* img, int b0, int xb, dim3 grid,
 constexpr int kFwdRowsPerWg = 64;
 
 int explicit_chunks(int rows, int ny, int B) {
-  const int bp = (B + 3) / 4;
+  const int bp = (B + 7) / 8;
   int c = (2048 + ny * bp - 1) / (ny * bp);
   c = std::max(c, (rows + kAdjRows - 1) / kAdjRows);
   return std::max(1, std::min(c, rows));
@@ -219,11 +229,12 @@ int launch_explicit_fwd(const Plan& pl, const float2* img) {
   const int xb = (pl.nx / 2 + 63) / 64;  // 16-byte pairs per lane
   if (xb > 4) return fail(GPJC_E_UNSUPPORTED, "explicit model: nx above 512");
   const dim3 grid((rows + kFwdRowsPerWg - 1) / kFwdRowsPerWg, pl.ny);
-  for (int b0 = 0; b0 < pl.B; b0 += 4) {
+  for (int b0 = 0; b0 < pl.B; b0 += 8) {
     const int left = pl.B - b0;
     if (left == 1) launch_fwd_bc<1>(pl, img, b0, xb, grid, kFwdRowsPerWg);
     else if (left == 2) launch_fwd_bc<2>(pl, img, b0, xb, grid, kFwdRowsPerWg);
-    else launch_fwd_bc<4>(pl, img, b0, xb, grid, kFwdRowsPerWg);
+    else if (left <= 4) launch_fwd_bc<4>(pl, img, b0, xb, grid, kFwdRowsPerWg);
+    else launch_fwd_bc<8>(pl, img, b0, xb, grid, kFwdRowsPerWg);
   }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
@@ -236,7 +247,7 @@ int launch_explicit_adj(const Plan& pl) {
   const int rc = (rows + nchunk - 1) / nchunk;
   if (rc > kAdjRows) return fail(GPJC_E_UNSUPPORTED, "explicit model: rows per chunk above the LDS stage");
   const dim3 grid(nchunk, pl.ny);
-  for (int b0 = 0; b0 < pl.B; b0 += 4) {
+  for (int b0 = 0; b0 < pl.B; b0 += 8) {
     const int left = pl.B - b0;
     if (left == 1)
       hipLaunchKernelGGL((k_explicit_adj<1>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny, pl.np,
@@ -244,8 +255,11 @@ int launch_explicit_adj(const Plan& pl) {
     else if (left == 2)
       hipLaunchKernelGGL((k_explicit_adj<2>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny, pl.np,
                          pl.K, pl.Kp, rc, pl.part);
-    else
+    else if (left <= 4)
       hipLaunchKernelGGL((k_explicit_adj<4>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny, pl.np,
+                         pl.K, pl.Kp, rc, pl.part);
+    else
+      hipLaunchKernelGGL((k_explicit_adj<8>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny, pl.np,
                          pl.K, pl.Kp, rc, pl.part);
   }
   GPJC_HIP(hipGetLastError());

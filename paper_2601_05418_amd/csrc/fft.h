@@ -35,6 +35,10 @@ __host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y
 // -i * a
 __host__ __device__ inline float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
+// Transform lengths the readout and phase-encode kernels are instantiated for.
+#define GPJC_FFT_SIZES(X) \
+  X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128) X(160) X(192) X(224) X(256) X(320) X(384) X(448) X(512)
+
 // ---------------------------------------------------------------------------
 // Compile-time radix plan: greedy 8, 4, 2, then 7, 5, 3.
 // ---------------------------------------------------------------------------

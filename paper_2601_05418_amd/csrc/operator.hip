@@ -876,8 +876,6 @@ int two_pass_coils(int nx, int os, int nc, int* threads) {
 // ---------------------------------------------------------------------------
 // Launch dispatch over the instantiated FFT lengths.
 // ---------------------------------------------------------------------------
-#define GPJC_FFT_SIZES(X) \
-  X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128) X(160) X(192) X(224) X(256) X(320) X(384) X(448) X(512)
 
 bool fft_size_supported(int n) {
 #define GPJC_CASE(N) \
@@ -1059,9 +1057,11 @@ int launch_combine(const Plan& pl, float2* out) {
 }
 
 int launch_pe_fwd(const Plan& pl, float2* out, Store st) {
+  if (pl.nz > 1) return launch_pe3_fwd(pl, out);
   return dispatch_n<PeFwd>(pl.ny, pl, out, pl.cfg(st).ksplit);
 }
 int launch_pe_adj(const Plan& pl, const float2* in, Store st) {
+  if (pl.nz > 1) return launch_pe3_adj(pl, in, st);
   switch (st) {
     case Store::F32: return dispatch_n<PeAdj<Store::F32>::L>(pl.ny, pl, in);
     case Store::BF16: return dispatch_n<PeAdj<Store::BF16>::L>(pl.ny, pl, in);
@@ -1069,6 +1069,7 @@ int launch_pe_adj(const Plan& pl, const float2* in, Store st) {
   }
 }
 int launch_pe_normal(const Plan& pl, Store st) {
+  if (pl.nz > 1) return launch_pe3_normal(pl, st);
   switch (st) {
     case Store::F32: return dispatch_n<PeNormal<Store::F32>::L>(pl.ny, pl);
     case Store::BF16: return dispatch_n<PeNormal<Store::BF16>::L>(pl.ny, pl);

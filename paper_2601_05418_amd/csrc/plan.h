@@ -69,6 +69,16 @@ struct Plan {
   GemmCfg& cfg(Store st) { return gemm[st == Store::F32 ? 0 : 1]; }
   long config_gen = 0;      // bumped whenever the launch configuration changes
 
+  // 3D volumes (gpjc_plan_create_3d): rows are (z, y) pairs, ny = nz * ny2;
+  // the phase-encode stage is the 2D DFT over (z, y) with a 2D mask
+  int nz = 1, ny2 = 0;
+  float2* T3 = nullptr;     // [B][np][K][nz][ny2] planes between the 2D-DFT passes
+  int* pts3 = nullptr;      // [ms] row (kz * ny2 + ky) of each acquired point
+  int* sel3 = nullptr;      // [ny] acquired-point index of every row, or -1
+  float* maskf3 = nullptr;  // [ny] 0 / 1
+  float2* tw_y3 = nullptr;  // [ny2] exp(-2 pi i m / ny2)
+  float2* tw_z3 = nullptr;  // [nz]
+
   // general modulation map (plans from gpjc_plan_create_bmap): no readout PSF;
   // the compressed readout matrices are stored per phase-encode column
   bool general = false;
@@ -198,6 +208,12 @@ int run_gd_step(const Plan& pl, Store st, const float2* x, const float2* b, cons
 int run_gd_step_backward(const Plan& pl, Store st, const float2* g, const float* alpha, const float2* r, float2* gx,
                          float2* gb, float* galpha);
 int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
+
+// ---- phase-encode stage of 3D volumes (pe3d.hip) ----
+int launch_pe3_fwd(const Plan& pl, float2* out);
+int launch_pe3_adj(const Plan& pl, const float2* in, Store st);
+int launch_pe3_normal(const Plan& pl, Store st);
+int setup_pe3(Plan& pl, const uint8_t* mask2);
 
 // ---- explicit readout model for general modulation maps (explicit.hip) ----
 int launch_build_explicit(const Plan& pl);

@@ -58,6 +58,7 @@ _D = ctypes.c_double
 _SIGS = {
     "gpjc_plan_create": (_I, [ctypes.POINTER(_Geom), _VP, _VP, _VP, ctypes.POINTER(_VP)]),
     "gpjc_plan_create_bmap": (_I, [ctypes.POINTER(_Geom), _VP, _VP, _VP, ctypes.POINTER(_VP)]),
+    "gpjc_plan_create_3d": (_I, [ctypes.POINTER(_Geom), _I, _VP, _VP, _VP, _VP, ctypes.POINTER(_VP)]),
     "gpjc_plan_destroy": (_I, [_VP]),
     "gpjc_set_stream": (_I, [_VP, _VP]),
     "gpjc_calibrate": (_I, [_VP, _VP, _VP, _VP, _VP]),
@@ -159,15 +160,18 @@ class Plan:
     """
 
     def __init__(self, nx, ny, nc, os_, coils, psf, mask, patch_len=0, patch_group=None, n_groups=0, k=0,
-                 batch=1, compressed=True, device="cuda:0", stream=None, bmod=None):
+                 batch=1, compressed=True, device="cuda:0", stream=None, bmod=None, nz=1):
         """psf [ny][nt] (Wave) or, with psf None, bmod [nt][ny][nx] (a general
-        modulation map, gpjc_plan_create_bmap)."""
+        modulation map, gpjc_plan_create_bmap); nz > 1: a 3D volume with
+        mask [nz][ny], coils [nc][nz][ny][nx], psf [nz][ny][nt]
+        (gpjc_plan_create_3d)."""
         self.lib = load()
         self.device = torch.device(device)
         self.nx, self.ny, self.nc, self.os = int(nx), int(ny), int(nc), int(os_)
         self.nt = self.os * self.nx
         self.batch = int(batch)
         self.compressed = bool(compressed)
+        self.nz = int(nz)
         self.mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         self.ms = int((self.mask != 0).sum())
         self.patch_len = int(patch_len)
@@ -185,8 +189,13 @@ class Plan:
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         handle = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)
-        create = self.lib.gpjc_plan_create_bmap if self.general else self.lib.gpjc_plan_create
-        _check(create(ctypes.byref(g), _ptr(c), _ptr(p), ctypes.c_void_p(st), ctypes.byref(handle)))
+        if self.nz > 1:
+            _check(self.lib.gpjc_plan_create_3d(ctypes.byref(g), self.nz,
+                                                self.mask.ctypes.data_as(ctypes.c_void_p), _ptr(c), _ptr(p),
+                                                ctypes.c_void_p(st), ctypes.byref(handle)))
+        else:
+            create = self.lib.gpjc_plan_create_bmap if self.general else self.lib.gpjc_plan_create
+            _check(create(ctypes.byref(g), _ptr(c), _ptr(p), ctypes.c_void_p(st), ctypes.byref(handle)))
         self.handle = handle
         self._inputs = []
 
@@ -195,6 +204,13 @@ class Plan:
         g = sl.geom
         return cls(g.nx, g.ny, g.nc, g.os, sl.coils, sl.psf, g.mask, g.patch_len, g.patch_group, g.n_groups,
                    g.k, batch=batch, compressed=compressed, **kw)
+
+    @classmethod
+    def from_volume(cls, v, batch=1, **kw):
+        """A plan for a 3D volume (synth.Volume)."""
+        g = v.geom
+        return cls(g.nx, g.ny, g.nc, g.os, v.coils, v.psf, v.mask2, g.patch_len, g.patch_group, g.n_groups, g.k,
+                   batch=batch, compressed=True, nz=v.nz, **kw)
 
     @classmethod
     def from_map_slice(cls, sl, batch=1, **kw):
@@ -225,6 +241,8 @@ class Plan:
         return (self.batch, self.nc, self.ms, self.nt)
 
     def image_shape(self):
+        if self.nz > 1:
+            return (self.batch, self.nz, self.ny, self.nx)
         return (self.batch, self.ny, self.nx)
 
     def _empty(self, shape, dtype=torch.complex64):
