@@ -262,6 +262,134 @@ def explicit_bench(reps=20):
     return out
 
 
+def solvers_bench(steps=3):
+    """The other reconstruction algorithms of Section 3.4 on the high-field
+    slice (224 x 224, 32 coils, 42 groups of 32, K = 64), GPU calibration and
+    compression of the acquired data:
+    - algorithm #1, LSQR-20 over the 56 aliased sets of a regular R = 4 mask
+      without calibration lines, beside CG-20 on the same data (both Eq. 16);
+    - FISTA-50 on Eq. 17 with smoothed TV (lambda_tv = 2e-3, eps = 1e-2 of
+      max|b|) and the Haar term (lambda = 1e-3 max|W b|) on a variable-density
+      Poisson-disc mask (~4x, 16 centre lines), compressed and plain operator."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2601_05418_amd import gpjc, synth
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def acquire(sl):
+        full = gpjc.Plan.from_slice(sl, compressed=False)
+        img = torch.as_tensor(np.ascontiguousarray(sl.image[None], np.complex64)).to(dev)
+        s_h = full.forward(img).cpu().numpy().astype(np.complex128)
+        rng = np.random.default_rng(3)
+        noise = synth.unit_noise(s_h.shape, rng)
+        full.close()
+        return torch.as_tensor(np.ascontiguousarray(s_h + synth.scaled_noise(s_h, noise, 30.0), np.complex64)).to(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    base = synth.highfield_slice(0)
+    g = base.geom
+    ky = np.arange(g.ny) - g.ny // 2
+    reg = dataclasses.replace(base, geom=dataclasses.replace(g, mask=(ky % 4 == 0).astype(np.uint8)))
+    ksp = acquire(reg)
+    plan = gpjc.Plan.from_slice(reg)
+    plan.calibrate()
+    y = plan.compress(ksp)
+    out["lsqr_alg1"] = {
+        "workload": "224x224, 32 coils, 42 groups of 32, K=64, regular R=4 without calibration lines (56 aliased "
+                    "sets of 4x224 unknowns, 2688 samples each), SNR 30",
+        "lsqr20_s_per_slice": timed(lambda: plan.recon_lsqr(y, 20)),
+        "cg20_s_per_slice_same_data": timed(lambda: plan.recon_cg(y, 20)),
+    }
+    plan.close()
+    log(f"algorithm #1 LSQR-20: {out['lsqr_alg1']['lsqr20_s_per_slice'] * 1e3:.2f} ms")
+
+    mask = synth.poisson_disc_mask(g.ny, 4, np.random.default_rng(9), center=16)
+    pd = dataclasses.replace(base, geom=dataclasses.replace(g, mask=mask))
+    ksp = acquire(pd)
+    plan = gpjc.Plan.from_slice(pd)
+    plan.calibrate()
+    y = plan.compress(ksp)
+    unc = gpjc.Plan.from_slice(pd, compressed=False)
+    res = {"workload": f"224x224, 32 coils, 42 groups of 32, K=64, variable-density Poisson-disc mask "
+                       f"({int(mask.sum())} of {g.ny} lines), SNR 30; FISTA-50 with TV + 3-level Haar"}
+    x0 = torch.as_tensor(np.ascontiguousarray(synth.unit_noise((1, g.ny, g.nx), np.random.default_rng(1)),
+                                              np.complex64)).to(dev)
+    for name, p, data in (("compressed", plan, y), ("uncompressed", unc, ksp)):
+        b = p.adjoint(data)
+        amax = float(b.abs().max())
+        lam = 1e-3 * p.wavelet_absmax(b, LEVELS)
+        lam_tv, eps = 2e-3 * amax, 1e-2 * amax
+        lip = p.power_iteration(x0, 30) * 1.01 + 8 * lam_tv / eps
+        res[f"{name}_s_per_slice"] = timed(lambda: p.recon_fista_tv(data, ITERS, lam, lam_tv, eps, lip, LEVELS))
+    res["speedup_of_compressed"] = res["uncompressed_s_per_slice"] / res["compressed_s_per_slice"]
+    out["fista_tv_poisson_disc"] = res
+    plan.close()
+    unc.close()
+    log(f"FISTA-TV-50 PD: compressed {res['compressed_s_per_slice'] * 1e3:.2f} ms, "
+        f"uncompressed {res['uncompressed_s_per_slice'] * 1e3:.2f} ms")
+    return out
+
+
+def volume_bench(steps=3):
+    """A 3D Wave-CAIPI volume close to the 3D ex vivo case of Table S2
+    (180 x 180 x 80, 32 coils, os 8): 192 x 192 x 64, 32 coils, os 8 (1536
+    samples), corkscrew PSF with 8 cycles and +-6 rad, 48 patches of 32 on the
+    6 groups of one period, K = 56 (18x), CAIPI 4 x 3 shift 1 with a 16 x 16
+    centre.  Calibration, E'^H E' per volume (FP32, BF16), CG-20."""
+    import numpy as np
+    import torch
+
+    from paper_2601_05418_amd import gpjc, synth
+    dev = torch.device("cuda:0")
+    v = synth.volume(0, n=192, nz=64, nc=32, os_=8, patch_len=32, k=56, ry=4, rz=3, shift=1, acs=16, cycles=8,
+                     phase=6.0, periodic=True)
+    g = v.geom
+    plan = gpjc.Plan.from_volume(v)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan.calibrate()
+    torch.cuda.synchronize()
+    t_cal = time.perf_counter() - t
+    x = torch.as_tensor(np.ascontiguousarray(v.image[None], np.complex64)).to(dev)
+    o = torch.empty_like(x)
+    res = {"workload": f"3D Wave-CAIPI {g.nx}x{g.ny}x{v.nz}, {g.nc} coils, os {g.os} ({g.nt} samples), "
+                       f"{g.n_patches} patches of {g.patch_len} on {g.n_groups} periodic groups, K={g.k} "
+                       f"({g.ns / g.k:.0f}x), CAIPI 4x3 shift 1 + 16x16 centre ({v.ms} of {g.ny * v.nz} points)",
+           "calibrate_s": t_cal, "W_GB": 8.0 * g.nc * g.ny * v.nz * g.nt / 1e9}
+    for prec in ("fp32", "bf16"):
+        for _ in range(2):
+            plan.normal(x, prec=prec, out=o)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            plan.normal(x, prec=prec, out=o)
+        torch.cuda.synchronize()
+        res[f"normal_ms_{prec}"] = (time.perf_counter() - t) / steps * 1e3
+    y = plan.forward(x)
+    plan.recon_cg(y, 2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan.recon_cg(y, 20)
+    torch.cuda.synchronize()
+    res["cg20_s_per_volume"] = time.perf_counter() - t
+    plan.close()
+    log(f"3D volume: calibrate {t_cal:.2f} s, E'^H E' {res['normal_ms_fp32']:.2f} ms, "
+        f"CG-20 {res['cg20_s_per_volume']:.3f} s")
+    return res
+
+
 def cpu_baseline(sl, budget_s, gpu_normal=None):
     """The oracle on the host cores, on a bounded sample of the workload:
     E'^H E' applications for about budget_s seconds (the unit of `value`),
@@ -344,6 +472,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched CG measurement")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled-network training step")
     ap.add_argument("--no-explicit", action="store_true", help="skip the explicit-model (local B0 map) measurement")
+    ap.add_argument("--no-solvers", action="store_true", help="skip the algorithm #1 and FISTA-TV measurements")
+    ap.add_argument("--no-volume", action="store_true", help="skip the 3D volume measurement")
     ap.add_argument("--tune-cache", default=None, help="tile autotuning cache file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (reference for byte counters)")
@@ -584,6 +714,12 @@ def main():
     if not args.no_explicit:
         log("explicit readout model on a local-B0 map ...")
         result["explicit_local_b0"] = explicit_bench()
+    if not args.no_solvers:
+        log("algorithm #1 and FISTA-TV ...")
+        result["solvers"] = solvers_bench()
+    if not args.no_volume:
+        log("3D volume ...")
+        result["volume_3d"] = volume_bench()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
 
