@@ -554,10 +554,10 @@ def main():
         log(f"using the stored oracle's lambda {lam:.4e} and L {lip:.4e}")
 
     x = torch.empty((1, g.ny, g.nx), dtype=torch.complex64, device=dev)
-    # Untimed pass with every stage launch bracketed by HIP events: the
-    # per-stage breakdown, and the dominant kernel.  Event pairs between
-    # launches cost a few microseconds each, so the timed steps bracket only
-    # the dominant kernel.
+    # Untimed pass with every stage timed by HIP events: the per-stage
+    # breakdown, and the dominant kernel.  A single-kernel stage hands its
+    # event pair to the kernel's own dispatch (the events mark the kernel's
+    # start and end); the timed steps time only the dominant kernel.
     plan.stage_timing(True)
     plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec=args.prec, out=x)
     torch.cuda.synchronize()
@@ -696,8 +696,9 @@ def main():
         "calibrate_s": t_cal,
         "compress_s": t_comp,
         "stages": per_stage,
-        "stages_note": "one untimed FISTA step with every launch bracketed by HIP events (the events add gaps); "
-                       "the timed steps bracket only the roofline kernel",
+        "stages_note": "one untimed FISTA step with every stage timed by HIP events (single-kernel stages by "
+                       "events on the kernel's own dispatch, hipExtLaunchKernel; the others by event records "
+                       "around them); the timed steps time only the roofline kernel, the same way",
         "roofline": roof,
         "accuracy": accuracy,
         "cpu_baseline": None,

@@ -310,8 +310,9 @@ int gpjc_get_gemm_config(const gpjc_plan* plan, gpjc_prec prec, int* compress_va
                          int* ksplit, int* n_compress_variants, int* n_expand_variants);
 
 /* Tile autotuning of the group contractions: times every built tile shape
- * (and contraction split) of both contractions on the plan's own buffers and
- * installs the fastest, as gpjc_set_gemm_config would.  Results are cached
+ * of both contractions on the plan's own buffers, each split of the
+ * compressing one together with the phase-encode stage that reads its
+ * partials back, and installs the fastest, as gpjc_set_gemm_config would.  Results are cached
  * per (precision, Ns, K, Ny, B*Np) bucket for the process and, if cache_path
  * is not NULL, in that text file (appended; read on first use), so later
  * plans of the same bucket -- in this or another process -- skip the timing.

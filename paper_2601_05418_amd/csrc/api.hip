@@ -629,7 +629,7 @@ int gpjc_stage_timing_select(gpjc_plan* plan, unsigned stage_mask) {
     if (t.ev.empty()) {
       const int cap = 16384;
       t.ev.resize(2 * cap);
-      for (auto& e : t.ev) GPJC_HIP(hipEventCreate(&e));
+      for (auto& e : t.ev) GPJC_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       t.stage.assign(cap, 0);
     }
     t.used = 0;

@@ -7,8 +7,10 @@
 // iteration count that selects the residual slot and the history entry) is
 // device-resident, so the same graph serves every iteration.  Slices are
 // dealt to a few streams (longest first onto the least-loaded stream) so that
-// kernels of different slices overlap inside the graph.  Set-up (E'^H y, the
-// first residual) and the copy-out run eagerly on the same streams.
+// the operator kernels of different slices overlap inside the graph; the CG
+// vector steps of all slices then run as work-list kernels, one launch per
+// step for the whole batch, whose items are (slice, block) pairs.  Set-up
+// (E'^H y, the first residual) and the copy-out run eagerly on the lanes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +35,9 @@ struct gpjc_batch {
     long gen = -1;
   };
   Graph graphs[3][2];  // [precision][refresh iteration]
+  std::vector<gpjc::CgSlice> h_list;  // the slices' CG vectors, for the work-list kernels
+  gpjc::CgSlice* d_list = nullptr;
+  int list_grid = 1024;  // persistent grid of the work-list kernels
 };
 
 namespace gpjc {
@@ -49,6 +54,7 @@ void destroy_batch(gpjc_batch* b) {
   for (hipStream_t s : b->lanes)
     if (s) (void)hipStreamDestroy(s);
   if (b->origin) (void)hipStreamDestroy(b->origin);
+  if (b->d_list) (void)hipFree(b->d_list);
   delete b;
 }
 
@@ -95,11 +101,30 @@ int join_lanes(gpjc_batch& b) {
   return GPJC_OK;
 }
 
+// The operator part of every slice on the lanes, then back on origin.
+int lanes_op_part(gpjc_batch& b, Store st, int phase) {
+  int status = fork_lanes(b);
+  for (size_t i = 0; status == GPJC_OK && i < b.plans.size(); ++i) status = cg_op_part(*b.plans[i], st, phase);
+  if (status == GPJC_OK) status = join_lanes(b);
+  return status;
+}
+
+int list_step(gpjc_batch& b, int op) {
+  return launch_cg_list(b.d_list, (int)b.plans.size(), op, b.list_grid, b.origin);
+}
+
 int capture_iteration(gpjc_batch& b, Store st, bool refresh, hipGraphExec_t* exec) {
   GPJC_HIP(hipStreamBeginCapture(b.origin, hipStreamCaptureModeThreadLocal));
-  int status = fork_lanes(b);
-  for (size_t i = 0; status == GPJC_OK && i < b.plans.size(); ++i) status = cg_iteration(*b.plans[i], st, refresh);
-  if (status == GPJC_OK) status = join_lanes(b);
+  int status = lanes_op_part(b, st, 0);
+  if (status == GPJC_OK) status = list_step(b, kCgListQ);
+  if (status == GPJC_OK) status = list_step(b, kCgListUpdate);
+  if (refresh) {
+    if (status == GPJC_OK) status = lanes_op_part(b, st, 1);
+    if (status == GPJC_OK) status = list_step(b, kCgListStart);
+    if (status == GPJC_OK) status = list_step(b, kCgListNorm);
+  } else if (status == GPJC_OK) {
+    status = list_step(b, kCgListDir);
+  }
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(b.origin, &graph);
   if (status == GPJC_OK && e != hipSuccess) status = fail(GPJC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
@@ -173,6 +198,10 @@ int gpjc_batch_create(gpjc_plan* const* plans, int n, int lanes, gpjc_batch** ou
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     b->join.push_back(ev);
   }
+  if (e == hipSuccess) e = hipMalloc(&b->d_list, sizeof(CgSlice) * n);
+  int cus = 0;
+  if (e == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) == hipSuccess && cus > 0)
+    b->list_grid = 4 * cus;
   if (e != hipSuccess) {
     destroy_batch(b);
     return fail(GPJC_E_DEVICE, std::string("batch streams: ") + hipGetErrorString(e));
@@ -218,6 +247,13 @@ int gpjc_batch_recon_cg(gpjc_batch* batch, gpjc_prec prec, const gpjc_c64* const
   int status = GPJC_OK;
   {
     LaneBinding bind(b);
+    // the slices' vectors for the work-list kernels (the graphs read the list
+    // when they run)
+    b.h_list.resize(n);
+    for (int i = 0; i < n; ++i) b.h_list[i] = cg_slice_of(*b.plans[i]);
+    const hipError_t ec =
+        hipMemcpyAsync(b.d_list, b.h_list.data(), sizeof(CgSlice) * n, hipMemcpyHostToDevice, b.origin);
+    if (ec != hipSuccess) return fail(GPJC_E_DEVICE, std::string("batch list: ") + hipGetErrorString(ec));
     status = fork_lanes(b);
     for (int i = 0; status == GPJC_OK && i < n; ++i)
       status = cg_setup(*b.plans[i], st, refine, reinterpret_cast<const float2*>(d_y[i]),

@@ -487,14 +487,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   const int twoP = 2 * a.P;
   const size_t cstride = (size_t)a.N * a.nt * 2;
 
-  const E* Ab = static_cast<const E*>(a.A) + (size_t)g * RS * a.M * a.KD;
-  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)RS * a.M * a.KD * ES));
-  const E* Bb = static_cast<const E*>(a.in) + (size_t)b * a.nc * cstride + (size_t)p * twoP;
-  const __amdgpu_buffer_rsrc_t rB = make_rsrc(Bb, (uint32_t)((a.nc * cstride - (size_t)p * twoP) * ES));
-
   const int kbeg = ks * a.kchunk;
   const int kend = min(a.KD, kbeg + a.kchunk);
   const int nst = max(0, (kend - kbeg + KT - 1) / KT);
+
+  const E* Ab = static_cast<const E*>(a.A) + (size_t)g * RS * a.M * a.KD;
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(Ab, (uint32_t)((size_t)RS * a.M * a.KD * ES));
+  // The data operand's buffer starts at the first coil of this k-chunk and
+  // spans the coils it touches, so 32-bit offsets reach any data size whose
+  // per-chunk span fits (the host picks the split for that).
+  const int nn0 = kend > kbeg ? kbeg / twoP : 0;
+  const int nspan = kend > kbeg ? (kend - 1) / twoP - nn0 + 1 : 0;
+  const E* Bb = static_cast<const E*>(a.in) + ((size_t)b * a.nc + nn0) * cstride + (size_t)p * twoP;
+  const __amdgpu_buffer_rsrc_t rB =
+      make_rsrc(Bb, nspan ? (uint32_t)((nspan * cstride - (size_t)p * twoP) * ES) : 0u);
   // This thread's 16-byte chunk along the contraction: element kk of the
   // (coil, in-patch sample) index, i.e. coil nn, sample jj.  With 2P a
   // multiple of the chunk a chunk never straddles a coil; k-tiles may, so the
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
     const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
-    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)nn * cstride + jj) * ES) : kOOB;
+    vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * a.nt * 2 + (size_t)(nn - nn0) * cstride + jj) * ES) : kOOB;
   }
   const uint32_t wrap = (uint32_t)((cstride - (size_t)twoP) * ES);  // end of a coil's patch -> next coil's
   floatx4 pa[PF][AR], pb[PF][BR];  // PF k-tiles of loads in flight
@@ -813,11 +819,23 @@ constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
 // Whether the LDS-staged and buffer-addressed forms apply.  The staged forms
 // take k-tiles of one 128-byte line per row.
 int staged_ktile(Store st) { return st == Store::F32 ? 32 : 64; }
+// Coils that the widest k-chunk of a split touches (the staged compressing
+// form addresses the data operand from the first of them).
+int chunk_coil_span(int KD, int kchunk, int ksplit, int twoP) {
+  int span = 0;
+  for (int ks = 0; ks < ksplit; ++ks) {
+    const int kbeg = ks * kchunk, kend = std::min(KD, kbeg + kchunk);
+    if (kend > kbeg) span = std::max(span, (kend - 1) / twoP - kbeg / twoP + 1);
+  }
+  return span;
+}
+bool compress_span_fits(size_t coil_elems, int span, size_t esz) { return (size_t)span * coil_elems * esz < kOOB; }
 bool compress_staged(const CompressArgs& a, Store st) {
   const size_t esz = st == Store::F32 ? 4 : 2;
+  const int span = chunk_coil_span(a.KD, a.kchunk, a.ksplit, 2 * a.P);
   // FP32 takes any P (odd P through the two-half data loads), 16-bit types 2P a multiple of 8
   return (st == Store::F32 || (2 * a.P) % (int)(16 / esz) == 0) && a.kchunk % staged_ktile(st) == 0 &&
-         (size_t)a.nc * a.N * a.nt * 2 * esz < kOOB && (size_t)a.M * a.KD * esz < kOOB;
+         compress_span_fits((size_t)a.N * a.nt * 2, span, esz) && (size_t)a.M * a.KD * esz < kOOB;
 }
 // 2 kp is a multiple of 32, so KD (2 kp FP32, 4 kp 16-bit) is always a whole
 // number of k-tiles; the staged form needs 32-bit buffer offsets.
@@ -829,7 +847,7 @@ bool expand_staged(const ExpandArgs& a, Store st) {
 int tiles(int n, int t) { return (n + t - 1) / t; }
 
 template <int V, Store ST>
-void launch_compress_v(hipStream_t s, const CompressArgs& a) {
+void launch_compress_v(StageScope& sc, hipStream_t s, const CompressArgs& a) {
   const int rest = a.B * a.np * a.ksplit;
   if (compress_staged(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kCompressLds[V] : kCompressLds16[V];
@@ -839,21 +857,21 @@ void launch_compress_v(hipStream_t s, const CompressArgs& a) {
     const dim3 grid(tiles(c.N, S.wn * S.nt * T) * tiles(c.M, S.wm * S.mt * T) * rest);
     if constexpr (ST == Store::F32) {
       if (a.P & 1) {
-        hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, true>), grid, dim3(64 * S.wm * S.wn),
+        sc.launch(k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, true>, grid, dim3(64 * S.wm * S.wn),
                            0, s, c);
         return;
       }
     }
-    hipLaunchKernelGGL((k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, false>), grid, dim3(64 * S.wm * S.wn), 0,
+    sc.launch(k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, false>, grid, dim3(64 * S.wm * S.wn), 0,
                        s, c);
   } else {
     constexpr Shape S = kCompressGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
-    hipLaunchKernelGGL((k_compress<S.wm, S.wn, S.mt, S.nt, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    sc.launch(k_compress<S.wm, S.wn, S.mt, S.nt, ST>, grid, dim3(64 * S.wm * S.wn), 0, s, a);
   }
 }
 template <int V, Store ST>
-void launch_expand_v(hipStream_t s, const ExpandArgs& a) {
+void launch_expand_v(StageScope& sc, hipStream_t s, const ExpandArgs& a) {
   const int rest = a.B * a.np;
   if (expand_staged(a, ST)) {
     constexpr Shape S = ST == Store::F32 ? kExpandLds[V] : kExpandLds16[V];
@@ -861,38 +879,38 @@ void launch_expand_v(hipStream_t s, const ExpandArgs& a) {
     ExpandArgs e = a;
     if (ST == Store::F32) e.N = a.N / 2;  // complex columns of the three-multiplication form
     const dim3 grid(tiles(e.N, S.wn * S.nt * T) * tiles(e.M, S.wm * S.mt * T) * rest);
-    hipLaunchKernelGGL((k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, e);
+    sc.launch(k_expand_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST>, grid, dim3(64 * S.wm * S.wn), 0, s, e);
   } else {
     constexpr Shape S = kExpandGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
-    hipLaunchKernelGGL((k_expand<S.wm, S.wn, S.mt, S.nt, ST>), grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    sc.launch(k_expand<S.wm, S.wn, S.mt, S.nt, ST>, grid, dim3(64 * S.wm * S.wn), 0, s, a);
   }
 }
 
 template <Store ST>
-void compress_variant(int v, hipStream_t s, const CompressArgs& a) {
+void compress_variant(int v, StageScope& sc, hipStream_t s, const CompressArgs& a) {
   switch (v) {
-    case 0: launch_compress_v<0, ST>(s, a); break;
-    case 1: launch_compress_v<1, ST>(s, a); break;
-    case 2: launch_compress_v<2, ST>(s, a); break;
-    case 3: launch_compress_v<3, ST>(s, a); break;
-    case 4: launch_compress_v<4, ST>(s, a); break;
-    case 5: launch_compress_v<5, ST>(s, a); break;
-    case 6: launch_compress_v<6, ST>(s, a); break;
-    default: launch_compress_v<7, ST>(s, a); break;
+    case 0: launch_compress_v<0, ST>(sc, s, a); break;
+    case 1: launch_compress_v<1, ST>(sc, s, a); break;
+    case 2: launch_compress_v<2, ST>(sc, s, a); break;
+    case 3: launch_compress_v<3, ST>(sc, s, a); break;
+    case 4: launch_compress_v<4, ST>(sc, s, a); break;
+    case 5: launch_compress_v<5, ST>(sc, s, a); break;
+    case 6: launch_compress_v<6, ST>(sc, s, a); break;
+    default: launch_compress_v<7, ST>(sc, s, a); break;
   }
 }
 template <Store ST>
-void expand_variant(int v, hipStream_t s, const ExpandArgs& a) {
+void expand_variant(int v, StageScope& sc, hipStream_t s, const ExpandArgs& a) {
   switch (v) {
-    case 0: launch_expand_v<0, ST>(s, a); break;
-    case 1: launch_expand_v<1, ST>(s, a); break;
-    case 2: launch_expand_v<2, ST>(s, a); break;
-    case 3: launch_expand_v<3, ST>(s, a); break;
-    case 4: launch_expand_v<4, ST>(s, a); break;
-    case 5: launch_expand_v<5, ST>(s, a); break;
-    case 6: launch_expand_v<6, ST>(s, a); break;
-    default: launch_expand_v<7, ST>(s, a); break;
+    case 0: launch_expand_v<0, ST>(sc, s, a); break;
+    case 1: launch_expand_v<1, ST>(sc, s, a); break;
+    case 2: launch_expand_v<2, ST>(sc, s, a); break;
+    case 3: launch_expand_v<3, ST>(sc, s, a); break;
+    case 4: launch_expand_v<4, ST>(sc, s, a); break;
+    case 5: launch_expand_v<5, ST>(sc, s, a); break;
+    case 6: launch_expand_v<6, ST>(sc, s, a); break;
+    default: launch_expand_v<7, ST>(sc, s, a); break;
   }
 }
 static_assert(kNumShapes == 8, "the variant switches list every shape");
@@ -904,9 +922,16 @@ int bank16_index(const Plan& pl, Store st) {
   return i;
 }
 
+// The staged forms take k-tiles of 32 (FP32) or 64 (16-bit) elements.
+int compress_kchunk(int KD, int ksplit, Store st) {
+  const int kb = staged_ktile(st);
+  return ((KD + ksplit - 1) / ksplit + kb - 1) / kb * kb;
+}
+
 int kblock(Store st) { return st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store::BF16>::KB; }
 
-int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* out, int ksplit, int cvar) {
+int gemm_compress(const Plan& pl, StageScope& sc, Store st, const void* in, int ncol, float2* out, int ksplit,
+                  int cvar) {
   CompressArgs a;
   if (st == Store::F32) {
     a.A = pl.Aexp;
@@ -929,14 +954,12 @@ int gemm_compress(const Plan& pl, Store st, const void* in, int ncol, float2* ou
   a.K = pl.K;
   a.B = pl.B;
   a.ksplit = ksplit;
-  // the staged forms take k-tiles of 32 (FP32) or 64 (16-bit) elements
-  const int kb = st == Store::F32 ? 32 : 64;
-  a.kchunk = ((a.KD + ksplit - 1) / ksplit + kb - 1) / kb * kb;
+  a.kchunk = compress_kchunk(a.KD, ksplit, st);
   a.split_stride = (size_t)pl.B * pl.np * pl.K * ncol;
   switch (st) {
-    case Store::F32: compress_variant<Store::F32>(cvar, pl.stream, a); break;
-    case Store::BF16: compress_variant<Store::BF16>(cvar, pl.stream, a); break;
-    default: compress_variant<Store::F16>(cvar, pl.stream, a); break;
+    case Store::F32: compress_variant<Store::F32>(cvar, sc, pl.stream, a); break;
+    case Store::BF16: compress_variant<Store::BF16>(cvar, sc, pl.stream, a); break;
+    default: compress_variant<Store::F16>(cvar, sc, pl.stream, a); break;
   }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
@@ -950,8 +973,7 @@ int gemm_expand_variants() { return kNumShapes; }
 // Defaults: for the compressing contraction the work-group shape with the
 // tallest row tile that pads at most 1/8 of its rows (FP32: 64 or 32 of the K
 // complex rows; 16-bit: 128, 64 or 32 of the 2K real rows), else the shortest;
-// for the expanding one shape 0; and a split giving about 1008 (FP32) or 640
-// (16-bit) work-groups.
+// for the expanding one shape 0; and a split giving about 504 work-groups.
 int compress_shape_for_rows(int rows, bool f32) {
   const int n = f32 ? 2 : 3;
   const int order[3] = {0, 7, 6}, tile[3] = {f32 ? 64 : 128, f32 ? 32 : 64, 32};
@@ -971,26 +993,33 @@ void default_gemm_config(Plan& pl) {
     const Shape S = c == 0 ? kCompressLds[g.cvar] : kCompressLds16[g.cvar];  // the staged forms take every even P
     const int T = c == 0 ? 32 : 16;
     const long t = (long)tiles(pl.ny, S.wn * S.nt * T) * tiles(rows, S.wm * S.mt * T) * pl.B * pl.np;
-    // work-groups: measured best on the 224 x 224, 32-coil slice
-    const long target = c == 0 ? 1008 : 640;
+    // work-groups: measured best for E'^H E' on the 224 x 224, 32-coil slice
+    // (the phase-encode stage reads one partial of Z per split)
+    const long target = 504;
     int ks = (int)std::max<long>(1, (target + t - 1) / t);
     ks = std::min(std::min(ks, std::max(1, 2 * pl.ns / 128)), kMaxKsplit);
+    // a split whose k-chunks the staged form can address (large volumes)
+    const size_t esz = c == 0 ? 4 : 2;
+    while (ks < kMaxKsplit &&
+           !compress_span_fits((size_t)pl.ny * pl.nt * 2,
+                               chunk_coil_span(2 * pl.ns, compress_kchunk(2 * pl.ns, ks, st), ks, 2 * pl.P), esz))
+      ++ks;
     g.ksplit = ks;
   }
 }
 
 int launch_group_compress(const Plan& pl, Store st) {
-  StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS);
-  return gemm_compress(pl, st, pl.W, pl.ny, pl.Zp, pl.cfg(st).ksplit, pl.cfg(st).cvar);
+  StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS, true);
+  return gemm_compress(pl, sc, st, pl.W, pl.ny, pl.Zp, pl.cfg(st).ksplit, pl.cfg(st).cvar);
 }
 
 int launch_compress_data(const Plan& pl, const float2* ksp, float2* out) {
-  StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS);
-  return gemm_compress(pl, Store::F32, ksp, pl.ms, out, 1, pl.cfg(Store::F32).cvar);
+  StageScope sc(pl, GPJC_STAGE_GROUP_COMPRESS, true);
+  return gemm_compress(pl, sc, Store::F32, ksp, pl.ms, out, 1, pl.cfg(Store::F32).cvar);
 }
 
 int launch_group_expand(const Plan& pl, Store st) {
-  StageScope sc(pl, GPJC_STAGE_GROUP_EXPAND);
+  StageScope sc(pl, GPJC_STAGE_GROUP_EXPAND, true);
   ExpandArgs a;
   if (st == Store::F32) {
     a.Zt = pl.Zt;
@@ -1015,9 +1044,9 @@ int launch_group_expand(const Plan& pl, Store st) {
   a.np = pl.np;
   a.B = pl.B;
   switch (st) {
-    case Store::F32: expand_variant<Store::F32>(pl.cfg(st).evar, pl.stream, a); break;
-    case Store::BF16: expand_variant<Store::BF16>(pl.cfg(st).evar, pl.stream, a); break;
-    default: expand_variant<Store::F16>(pl.cfg(st).evar, pl.stream, a); break;
+    case Store::F32: expand_variant<Store::F32>(pl.cfg(st).evar, sc, pl.stream, a); break;
+    case Store::BF16: expand_variant<Store::BF16>(pl.cfg(st).evar, sc, pl.stream, a); break;
+    default: expand_variant<Store::F16>(pl.cfg(st).evar, sc, pl.stream, a); break;
   }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;

@@ -899,20 +899,20 @@ struct ReadoutFwd {
   template <int NX>
   struct L {
     static int run(const Plan& pl, const float2* img) {
-      StageScope sc(pl, GPJC_STAGE_READOUT_FWD);
+      StageScope sc(pl, GPJC_STAGE_READOUT_FWD, true);
       if (pl.f2_cb > 0) {
         const size_t lds = two_pass_lds_fwd(NX, pl.os, pl.f2_cb) * sizeof(float2);
         dim3 grid(pl.ny, (pl.nc + pl.f2_cb - 1) / pl.f2_cb, pl.B);
-        hipLaunchKernelGGL((k_readout_fwd2<NX, ST>), grid, dim3(pl.f2_threads), lds, pl.stream, img, pl.coils, pl.psfp,
-                           pl.twin, pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, pl.f2_cb);
+        sc.launch(k_readout_fwd2<NX, ST>, grid, dim3(pl.f2_threads), lds, pl.stream, img, pl.coils, pl.psfp, pl.twin,
+                  pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, pl.f2_cb);
         GPJC_HIP(hipGetLastError());
         return GPJC_OK;
       }
       const int rows = pl.f1_rows;
       const size_t lds = (size_t)(NX + 2 * rows * pl.os * fline(NX)) * sizeof(float2);
       dim3 grid((pl.ny + rows - 1) / rows, pl.nc, pl.B);
-      hipLaunchKernelGGL((k_readout_fwd<NX, ST>), grid, dim3(256), lds, pl.stream, img, pl.coils, pl.psfp, pl.twin,
-                         pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, 1.0f / pl.os, rows);
+      sc.launch(k_readout_fwd<NX, ST>, grid, dim3(256), lds, pl.stream, img, pl.coils, pl.psfp, pl.twin, pl.tw_x,
+                (void*)pl.W, pl.ny, pl.nc, pl.os, 1.0f / pl.os, rows);
       GPJC_HIP(hipGetLastError());
       return GPJC_OK;
     }
@@ -924,20 +924,19 @@ struct ReadoutAdj {
   template <int NX>
   struct L {
     static int run(const Plan& pl) {
-      StageScope sc(pl, GPJC_STAGE_READOUT_ADJ);
+      StageScope sc(pl, GPJC_STAGE_READOUT_ADJ, true);
       if (pl.f2_adj) {
         const size_t lds = two_pass_lds_adj(NX, pl.os, pl.f2_cb) * sizeof(float2);
         dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
-        hipLaunchKernelGGL((k_readout_adj2<NX, ST>), grid, dim3(pl.f2_threads), lds, pl.stream, (const void*)pl.W,
-                           pl.coils, pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, pl.f2_cb, pl.B);
+        sc.launch(k_readout_adj2<NX, ST>, grid, dim3(pl.f2_threads), lds, pl.stream, (const void*)pl.W, pl.coils,
+                  pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, pl.f2_cb, pl.B);
         GPJC_HIP(hipGetLastError());
         return GPJC_OK;
       }
       const size_t lds = (size_t)(NX + 2 * pl.f1h_cb * pl.os * fline(NX)) * sizeof(float2);
       dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
-      hipLaunchKernelGGL((k_readout_adj<NX, ST>), grid, dim3(256), lds, pl.stream, (const void*)pl.W, pl.coils,
-                         pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, 1.0f / pl.os, pl.f1h_cb, pl.f1h_cpc,
-                         pl.B);
+      sc.launch(k_readout_adj<NX, ST>, grid, dim3(256), lds, pl.stream, (const void*)pl.W, pl.coils, pl.psfp,
+                pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, 1.0f / pl.os, pl.f1h_cb, pl.f1h_cpc, pl.B);
       GPJC_HIP(hipGetLastError());
       return GPJC_OK;
     }
@@ -984,21 +983,22 @@ struct PeNormal {
   template <int NY>
   struct L {
     static int run(const Plan& pl) {
-      StageScope sc(pl, GPJC_STAGE_PE_NORMAL);
+      StageScope sc(pl, GPJC_STAGE_PE_NORMAL, true);
       const int nlines = pl.B * pl.np * pl.K;
       if constexpr (Split<NY>::N1 > 1 && Split<NY>::N2 > 1 && Split<NY>::N2 <= 32) {
         constexpr int lines = PeNormal2Geo<NY>::L;
         const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
-        hipLaunchKernelGGL((k_pe_normal2<NY, ST>), dim3((nlines + lines - 1) / lines), dim3(256), 0, pl.stream, pl.Zp,
-                           pl.cfg(ST).ksplit, zs, zt_for(pl, ST), pl.maskf, nlines, pl.K, pl.Kp, pl.tw_y);
+        sc.launch(k_pe_normal2<NY, ST>, dim3((nlines + lines - 1) / lines), dim3(256), 0, pl.stream,
+                  (const float2*)pl.Zp, pl.cfg(ST).ksplit, zs, zt_for(pl, ST), (const float*)pl.maskf, nlines, pl.K,
+                  pl.Kp, (const float2*)pl.tw_y);
         GPJC_HIP(hipGetLastError());
         return GPJC_OK;
       }
       const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
       const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
-      hipLaunchKernelGGL((k_pe_normal<NY, ST>), dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds,
-                         pl.stream, pl.Zp, pl.cfg(ST).ksplit, zs, zt_for(pl, ST), pl.maskf, nlines, pl.f3_lpb, pl.K,
-                         pl.Kp, pl.tw_y);
+      sc.launch(k_pe_normal<NY, ST>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream,
+                (const float2*)pl.Zp, pl.cfg(ST).ksplit, zs, zt_for(pl, ST), (const float*)pl.maskf, nlines,
+                pl.f3_lpb, pl.K, pl.Kp, (const float2*)pl.tw_y);
       GPJC_HIP(hipGetLastError());
       return GPJC_OK;
     }

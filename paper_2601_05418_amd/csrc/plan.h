@@ -1,5 +1,6 @@
 // Internal plan state and launcher prototypes shared by the HIP sources.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -127,20 +128,37 @@ struct Plan {
   size_t img_elems() const { return (size_t)B * ny * nx; }
 };
 
-// Brackets one launch with an event pair while timing is on.
+// Times one stage launch while timing is on.  A stage of one kernel launches
+// it through launch(), which hands the event pair to the kernel's own
+// dispatch (hipExtLaunchKernel records them at the kernel's start and end,
+// with no marker packets around it); a stage of several kernels is bracketed
+// by event records before and after.
 struct StageScope {
   const Plan& pl;
   int slot = -1;
-  StageScope(const Plan& p, int st) : pl(p) {
+  bool single = false, consumed = false;
+  StageScope(const Plan& p, int st, bool one_kernel = false) : pl(p), single(one_kernel) {
     Timing& t = p.timing;
     if (t.on && ((t.mask >> st) & 1u) && t.used < (int)t.stage.size()) {
       slot = t.used++;
       t.stage[slot] = st;
-      (void)hipEventRecord(t.ev[2 * slot], p.stream);
+      if (!single) (void)hipEventRecord(t.ev[2 * slot], p.stream);
+    }
+  }
+  template <typename F, typename... A>
+  void launch(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, A... args) {
+    if (slot >= 0 && single && !consumed) {
+      hipExtLaunchKernelGGL(kernel, grid, block, lds, s, pl.timing.ev[2 * slot], pl.timing.ev[2 * slot + 1], 0,
+                            args...);
+      consumed = true;
+    } else {
+      kernel<<<grid, block, lds, s>>>(args...);
     }
   }
   ~StageScope() {
-    if (slot >= 0) (void)hipEventRecord(pl.timing.ev[2 * slot + 1], pl.stream);
+    if (slot < 0) return;
+    if (single && !consumed) (void)hipEventRecord(pl.timing.ev[2 * slot], pl.stream);
+    if (!single || !consumed) (void)hipEventRecord(pl.timing.ev[2 * slot + 1], pl.stream);
   }
 };
 
@@ -191,11 +209,31 @@ int run_calibrate_static(Plan& pl, const uint8_t* roi, const float2* noise_cov, 
 
 // ---- solvers (solver.hip) ----
 int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid);
-// CG in parts (a batch captures cg_iteration once and replays it):
+// CG in parts (a batch captures one iteration once and replays it):
 int cg_setup(Plan& pl, Store st, bool refine, const float2* y, const float2* x0);
 int cg_iteration(const Plan& pl, Store st, bool refresh);
 int cg_finish(const Plan& pl, float2* x, int iters, double* h_resid, int* h_flag);
 bool cg_refresh_at(int it, int iters, int refine_every, Store st);
+// The operator part of an iteration: A p (phase 0) or the refresh's FP32 A x
+// (phase 1), leaving partial images in pl.part.
+int cg_op_part(const Plan& pl, Store st, int phase);
+// One slice's CG vectors for the batch's work-list kernels.
+struct CgSlice {
+  const float2* part;
+  const float2* b;
+  float2 *x, *r, *p, *q;
+  double* red;   // [pq partials][two rr slots]
+  int* flag;     // numeric flag; flag[1] is the iteration count
+  double* hist;
+  size_t n;
+  int nchunk;
+};
+CgSlice cg_slice_of(const Plan& pl);
+// Work-list steps over every slice of a batch (same arithmetic and order as
+// the per-plan kernels): after phase 0, Q then UPDATE, then DIR; a refresh
+// iteration runs phase 1 after UPDATE, then START and NORM.
+enum CgListOp { kCgListQ = 0, kCgListUpdate = 1, kCgListDir = 2, kCgListStart = 3, kCgListNorm = 4 };
+int launch_cg_list(const CgSlice* d_list, int nslice, int op, int grid, hipStream_t s);
 
 // ---- GEMM tile autotuning (tune.hip) ----
 int autotune(Plan& pl, Store st, const char* cache_path, int* h_choice);

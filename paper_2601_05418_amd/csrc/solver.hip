@@ -81,66 +81,67 @@ __global__ void k_cg_reset(int* __restrict__ flag, int* __restrict__ iter) {
   }
 }
 
+// The CG vector kernels are written as bodies over one block index blk of
+// a fixed grid of nb blocks, so that the per-plan kernels (blk = blockIdx.x)
+// and the batch's work-list kernels (any block taking item (slice, blk))
+// perform identical arithmetic in identical order.
+
 // r = b - A x (A x given as partial images), p = r, partial <r, r> into slot t.
-__global__ __launch_bounds__(256) void k_cg_start(const float2* __restrict__ part, int nchunk,
-                                                  const float2* __restrict__ bvec, float2* __restrict__ r,
-                                                  float2* __restrict__ p, double* __restrict__ red_rr, int nb,
-                                                  const int* __restrict__ iter, size_t n) {
-  __shared__ double sh[8];
+__device__ inline void cg_start_body(const float2* __restrict__ part, int nchunk, const float2* __restrict__ bvec,
+                                     float2* __restrict__ r, float2* __restrict__ p, double* __restrict__ red_rr,
+                                     int nb, const int* __restrict__ iter, size_t n, int blk, double* sh) {
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)blk * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
     const float2 v = csub(bvec[i], sum_chunks(part, nchunk, n, i));
     r[i] = v;
     p[i] = v;
     acc += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) rr_slot(red_rr, nb, *iter)[blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_slot(red_rr, nb, *iter)[blk] = s;
 }
 
-// hist[t] = sqrt(sum of slot t's partials); single block.
-__global__ void k_store_norm(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
-                             double* __restrict__ hist) {
-  __shared__ double sh[8];
+// hist[t] = sqrt(sum of slot t's partials); one block.
+__device__ inline void store_norm_body(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
+                                       double* __restrict__ hist, double* sh) {
   const int t = *iter;
   const double s = sum_partials(red_rr + (t & 1) * nb, nb, sh);
   if (threadIdx.x == 0) hist[t] = sqrt(s);
 }
 
-// q = A p (from partials), partial Re <p, q>; advances the iteration count.
-__global__ __launch_bounds__(256) void k_cg_q(const float2* __restrict__ part, int nchunk, const float2* __restrict__ p,
-                                              float2* __restrict__ q, double* __restrict__ red_pq, int* __restrict__ iter,
-                                              size_t n) {
-  __shared__ double sh[8];
+// q = A p (from partials), partial Re <p, q>; block 0 advances the iteration
+// count (no other block of the same launch reads it).
+__device__ inline void cg_q_body(const float2* __restrict__ part, int nchunk, const float2* __restrict__ p,
+                                 float2* __restrict__ q, double* __restrict__ red_pq, int* __restrict__ iter, int nb,
+                                 size_t n, int blk, double* sh) {
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)blk * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
     const float2 v = sum_chunks(part, nchunk, n, i);
     q[i] = v;
     const float2 pv = p[i];
     acc += (double)pv.x * v.x + (double)pv.y * v.y;
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) red_pq[blockIdx.x] = s;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *iter += 1;  // no other block of this kernel reads it
+  if (threadIdx.x == 0) red_pq[blk] = s;
+  if (blk == 0 && threadIdx.x == 0) *iter += 1;
 }
 
 // alpha = rr / pq; x += alpha p; r -= alpha q; partial <r, r> into slot t
 // (the old residual is in slot t - 1).
-__global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ red_pq, double* __restrict__ red_rr,
-                                                   int nb, const int* __restrict__ iter, float2* __restrict__ x,
-                                                   float2* __restrict__ r, const float2* __restrict__ p,
-                                                   const float2* __restrict__ q, size_t n, int* __restrict__ flag) {
-  __shared__ double sh[8];
+__device__ inline void cg_update_body(const double* __restrict__ red_pq, double* __restrict__ red_rr, int nb,
+                                      const int* __restrict__ iter, float2* __restrict__ x, float2* __restrict__ r,
+                                      const float2* __restrict__ p, const float2* __restrict__ q, size_t n,
+                                      int* __restrict__ flag, int blk, double* sh) {
   const int t = *iter;
   const double pq = sum_partials(red_pq, nb, sh);
   const double rr = sum_partials(rr_slot(red_rr, nb, t - 1), nb, sh);
   if (!isfinite(pq) || !isfinite(rr)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+    if (blk == 0 && threadIdx.x == 0) *flag = 1;
   }
   const double alpha = (pq > 0.0 && rr > 0.0) ? rr / pq : 0.0;
   const float a = (float)alpha;
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)blk * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
     const float2 pv = p[i], qv = q[i];
     float2 xv = x[i], rv = r[i];
     xv = make_float2(fmaf(a, pv.x, xv.x), fmaf(a, pv.y, xv.y));
@@ -150,23 +151,80 @@ __global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ re
     acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) rr_slot(red_rr, nb, t)[blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_slot(red_rr, nb, t)[blk] = s;
 }
 
 // beta = rr_t / rr_{t-1}; p = r + beta p; hist[t] = ||r||.
-__global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
-                                                const float2* __restrict__ r, float2* __restrict__ p, size_t n,
-                                                double* __restrict__ hist) {
-  __shared__ double sh[8];
+__device__ inline void cg_dir_body(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
+                                   const float2* __restrict__ r, float2* __restrict__ p, size_t n,
+                                   double* __restrict__ hist, int blk, double* sh) {
   const int t = *iter;
   const double rn = sum_partials(red_rr + (t & 1) * nb, nb, sh);
   const double ro = sum_partials(red_rr + ((t - 1) & 1) * nb, nb, sh);
   const float beta = (float)((ro > 0.0) ? rn / ro : 0.0);
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)blk * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
     const float2 rv = r[i], pv = p[i];
     p[i] = make_float2(fmaf(beta, pv.x, rv.x), fmaf(beta, pv.y, rv.y));
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) hist[t] = sqrt(rn);
+  if (blk == 0 && threadIdx.x == 0) hist[t] = sqrt(rn);
+}
+
+__global__ __launch_bounds__(256) void k_cg_start(const float2* __restrict__ part, int nchunk,
+                                                  const float2* __restrict__ bvec, float2* __restrict__ r,
+                                                  float2* __restrict__ p, double* __restrict__ red_rr, int nb,
+                                                  const int* __restrict__ iter, size_t n) {
+  __shared__ double sh[8];
+  cg_start_body(part, nchunk, bvec, r, p, red_rr, nb, iter, n, blockIdx.x, sh);
+}
+__global__ void k_store_norm(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
+                             double* __restrict__ hist) {
+  __shared__ double sh[8];
+  store_norm_body(red_rr, nb, iter, hist, sh);
+}
+__global__ __launch_bounds__(256) void k_cg_q(const float2* __restrict__ part, int nchunk, const float2* __restrict__ p,
+                                              float2* __restrict__ q, double* __restrict__ red_pq, int* __restrict__ iter,
+                                              size_t n) {
+  __shared__ double sh[8];
+  cg_q_body(part, nchunk, p, q, red_pq, iter, gridDim.x, n, blockIdx.x, sh);
+}
+__global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ red_pq, double* __restrict__ red_rr,
+                                                   int nb, const int* __restrict__ iter, float2* __restrict__ x,
+                                                   float2* __restrict__ r, const float2* __restrict__ p,
+                                                   const float2* __restrict__ q, size_t n, int* __restrict__ flag) {
+  __shared__ double sh[8];
+  cg_update_body(red_pq, red_rr, nb, iter, x, r, p, q, n, flag, blockIdx.x, sh);
+}
+__global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ red_rr, int nb, const int* __restrict__ iter,
+                                                const float2* __restrict__ r, float2* __restrict__ p, size_t n,
+                                                double* __restrict__ hist) {
+  __shared__ double sh[8];
+  cg_dir_body(red_rr, nb, iter, r, p, n, hist, blockIdx.x, sh);
+}
+
+// Work-list forms for a batch: the items are (slice, block) pairs, slice
+// major, taken by a persistent grid in strides of its size.  Every item is
+// one block of the per-plan kernel above on that slice's vectors, so each
+// slice's reductions keep their fixed order and a batched solve equals the
+// separate ones bit for bit.  The store-norm step has one item per slice.
+__global__ __launch_bounds__(256) void k_cg_list(const CgSlice* __restrict__ sl, int nslice, int op) {
+  __shared__ double sh[8];
+  const int nb = kRedBlocks;
+  const int items = op == kCgListNorm ? nslice : nslice * nb;
+  for (int w = blockIdx.x; w < items; w += gridDim.x) {
+    const int si = op == kCgListNorm ? w : w / nb;
+    const int blk = op == kCgListNorm ? 0 : w - si * nb;
+    const CgSlice d = sl[si];
+    double* red_pq = d.red;
+    double* red_rr = d.red + nb;
+    int* iter = d.flag + 1;
+    switch (op) {
+      case kCgListQ: cg_q_body(d.part, d.nchunk, d.p, d.q, red_pq, iter, nb, d.n, blk, sh); break;
+      case kCgListUpdate: cg_update_body(red_pq, red_rr, nb, iter, d.x, d.r, d.p, d.q, d.n, d.flag, blk, sh); break;
+      case kCgListDir: cg_dir_body(red_rr, nb, iter, d.r, d.p, d.n, d.hist, blk, sh); break;
+      case kCgListStart: cg_start_body(d.part, d.nchunk, d.b, d.r, d.p, red_rr, nb, iter, d.n, blk, sh); break;
+      default: store_norm_body(red_rr, nb, iter, d.hist, sh); break;
+    }
+  }
 }
 
 static int fill_zero(const Plan& pl, float2* v, size_t n) {
@@ -201,6 +259,33 @@ int cg_setup(Plan& pl, Store st, bool refine, const float2* y, const float2* x0)
   hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, pl.stream, pl.part, pl.f1h_nchunk, pl.vb, pl.vr, pl.vp,
                      pl.red + nb, nb, iter, n);
   hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(256), 0, pl.stream, pl.red + nb, nb, iter, pl.hist);
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int cg_op_part(const Plan& pl, Store st, int phase) {
+  return phase == 0 ? op_normal_part(pl, st, pl.vp) : op_normal_part(pl, Store::F32, pl.vx);
+}
+
+CgSlice cg_slice_of(const Plan& pl) {
+  CgSlice d;
+  d.part = pl.part;
+  d.b = pl.vb;
+  d.x = pl.vx;
+  d.r = pl.vr;
+  d.p = pl.vp;
+  d.q = pl.vq;
+  d.red = pl.red;
+  d.flag = pl.flag;
+  d.hist = pl.hist;
+  d.n = pl.img_elems();
+  d.nchunk = pl.f1h_nchunk;
+  return d;
+}
+
+int launch_cg_list(const CgSlice* d_list, int nslice, int op, int grid, hipStream_t s) {
+  const int items = op == kCgListNorm ? nslice : nslice * kRedBlocks;
+  hipLaunchKernelGGL(k_cg_list, dim3(std::max(1, std::min(grid, items))), dim3(256), 0, s, d_list, nslice, op);
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
 }

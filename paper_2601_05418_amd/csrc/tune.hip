@@ -58,7 +58,7 @@ void load_file(const char* path) {
     std::istringstream in(line);
     std::string tag, key;
     Choice c;
-    if (in >> tag >> key >> c.cvar >> c.evar >> c.ksplit && tag == "gpjc-tune-v1") {
+    if (in >> tag >> key >> c.cvar >> c.evar >> c.ksplit && tag == "gpjc-tune-v2") {
       if (c.cvar >= 0 && c.cvar < gemm_compress_variants() && c.evar >= 0 && c.evar < gemm_expand_variants() &&
           c.ksplit >= 1 && c.ksplit <= kMaxKsplit)
         g_cache[key] = c;
@@ -69,7 +69,7 @@ void load_file(const char* path) {
 void append_file(const char* path, const std::string& key, const Choice& c, float us_c, float us_e) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << "gpjc-tune-v1 " << key << " " << c.cvar << " " << c.evar << " " << c.ksplit << "  # " << us_c << " us "
+  f << "gpjc-tune-v2 " << key << " " << c.cvar << " " << c.evar << " " << c.ksplit << "  # " << us_c << " us "
     << us_e << " us\n";
 }
 
@@ -113,12 +113,22 @@ int measure(Plan& pl, Store st, Choice* out, float* us_c, float* us_e) {
   Choice best{keep.cvar, keep.evar, keep.ksplit};
   float bc = 1e30f, be = 1e30f;
   const int kd = 2 * pl.ns;
+  // The split is timed together with the phase-encode stage, which reads
+  // back one partial of Z per split.
+  const int splits[] = {1, 2, 3, 4, 6, 8};
   for (int v = 0; status == GPJC_OK && v < gemm_compress_variants(); ++v)
-    for (int ks = 1; status == GPJC_OK && ks <= kMaxKsplit && (ks == 1 || kd / ks >= 64); ks *= 2) {
+    for (int ks : splits) {
+      if (status != GPJC_OK || ks > kMaxKsplit || (ks > 1 && kd / ks < 64)) continue;
       cfg.cvar = v;
       cfg.ksplit = ks;
       float us = 0.f;
-      status = time_us(pl, ev.a, ev.b, [&] { return launch_group_compress(pl, st); }, &us);
+      status = time_us(
+          pl, ev.a, ev.b,
+          [&] {
+            const int s = launch_group_compress(pl, st);
+            return s == GPJC_OK ? launch_pe_normal(pl, st) : s;
+          },
+          &us);
       if (status == GPJC_OK && us < bc) {
         bc = us;
         best.cvar = v;

@@ -155,11 +155,11 @@ def test_autotune_cache(gpu_lib, tmp_path):
     assert (cfg["compress"], cfg["expand"], cfg["ksplit"]) == (c1["compress"], c1["expand"], c1["ksplit"])
     c2 = p2.autotune("fp32", path)
     assert c2["cached"] and (c2["compress"], c2["expand"], c2["ksplit"]) == (c1["compress"], c1["expand"], c1["ksplit"])
-    lines = [l for l in open(path) if l.startswith("gpjc-tune-v1 ")]
+    lines = [l for l in open(path) if l.startswith("gpjc-tune-v2 ")]
     assert len(lines) == 1 and "fp32/" in lines[0]
     cb = p1.autotune("bf16", path)  # another bucket
     assert not cb["cached"]
-    assert len([l for l in open(path) if l.startswith("gpjc-tune-v1 ")]) == 2
+    assert len([l for l in open(path) if l.startswith("gpjc-tune-v2 ")]) == 2
     # the tuned operator still meets the FP32 bound
     ops = H.oracle_ops(sl, a)
     x = H.round64(H.crandn(np.random.default_rng(8), (sl.geom.ny, sl.geom.nx)))
