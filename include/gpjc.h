@@ -141,15 +141,18 @@ int gpjc_set_stream(gpjc_plan* plan, void* hip_stream);
 
 /* Calibrate the compression bank (Eqs. 6-12): per group, FP64 Gram matrix of
  * the composite maps over the ROI (d_roi [ny][nx] uint8, NULL = all pixels
- * with a nonzero vector), Jacobi eigen-decomposition, descending order, each
+ * with a nonzero vector), Hermitian eigen-decomposition (Householder
+ * tridiagonalisation, bisection for every eigenvalue, inverse iteration for
+ * the K leading eigenvectors), descending order, each
  * eigenvector phase-normalised (largest-magnitude entry real positive), first
  * K rows of U^H, times T (x) I_P with T = Q^{-1}, Psi = Q Q^H from
  * d_noise_cov [nc][nc] c64 (NULL = identity).  Outputs (optional):
  * h_eigvals [G][nc*P] descending, d_A_out [G][K][nc][P] c128.
- * Synchronises.  Compressed plans only.  GPJC_E_NUMERIC if the Gram is not
- * finite, the noise covariance is not positive definite, or the Jacobi
- * sweeps do not reach off(H) <= 1e-13 ||H||_F within the sweep cap (40; the
- * environment variable GPJC_JACOBI_SWEEP_CAP = 1..39 lowers it). */
+ * Synchronises.  Compressed plans only; Ns = nc*P <= 2048.  GPJC_E_NUMERIC
+ * if the Gram is not finite, the noise covariance is not positive definite,
+ * or a kept eigenvector fails its residual check ||T y - lambda y|| <=
+ * 1e-9 ||T|| after the inverse iteration (3 steps; the environment variable
+ * GPJC_INVIT_ITERS = 0..8 sets the count). */
 int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov,
                    double* h_eigvals, gpjc_c128* d_A_out);
 

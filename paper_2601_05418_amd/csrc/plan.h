@@ -200,6 +200,20 @@ int op_adj_columns(const Plan& pl, Store st);                      // Z^T -> pl.
 int regular_accel(const Plan& pl);  // R of a regular mask without calibration lines, else 0
 int run_lsqr(Plan& pl, Store st, const float2* y, float2* x, int iters, double* h_resid);
 
+// ---- Hermitian eigensolver of the calibration (eigen.hip) ----
+// Workspaces of tri_eigen for G matrices of size n and K wanted vectors.
+struct TriEigBufs {
+  double *d, *tau, *f, *f2, *eig, *bounds;  // [G][n] each (bounds [G][3]); eig: every eigenvalue, descending
+  double2 *e, *vb, *wb, *pb, *cb, *ph;      // [G][n] each (vb [2][G][n])
+  double *lm, *u0, *u1, *u2, *x;            // [G][n][K] each
+  unsigned char* sw;                        // [G][n][K]
+  double2* U;                               // [G][K][n]: eigenvectors of the K largest eigenvalues
+};
+// Eigenvalues and the K leading eigenvectors of G Hermitian n x n matrices
+// (H: [G][ld][ld], overwritten).  *flag is set when an eigenvector fails its
+// residual check.  n <= 2048.
+int tri_eigen(hipStream_t st, double2* H, int ld, int n, int G, int K, const TriEigBufs& b, int* flag);
+
 // ---- calibration (calib.hip) ----
 int run_calibrate(Plan& pl, const uint8_t* roi, const float2* noise_cov, double* h_eig, double2* A_out);
 // The same calibration with its workspaces in the library's static device

@@ -123,8 +123,8 @@ def test_calibrate_highfield_sampled_groups(gpu_lib):
 
 
 def test_calibrate_ns512_decayed_couplings(gpu_lib):
-    """Ns = 512 (32 Jacobi blocks): couplings decay far enough during the
-    sweeps that |c|^2 underflows; every rotation must stay unitary."""
+    """Ns = 512: two column chunks per thread in the tridiagonal reduction,
+    and a graded spectrum whose small eigenvalues sit in one wide cluster."""
     sl = H.rounded_slice(synth._make_rect(0, nx=64, ny=64, nc=16, os_=4, patch_len=32, k=8, accel=4, acs=8,
                                           cycles=5, phase_max=3.0))
     plan, eig, bank, a_ref, lam_ref, groups = calibrate_both(sl, groups=[0, 3, 7])

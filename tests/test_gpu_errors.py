@@ -2,7 +2,8 @@
 normal end, and the library reports the condition through its status code.
 
 - NaN in the data -> GPJC_E_NUMERIC from CG and from FISTA;
-- a Jacobi sweep cap too low to converge -> GPJC_E_NUMERIC from calibration;
+- an eigensolver held to zero inverse-iteration steps (its eigenvectors then
+  fail the residual check) -> GPJC_E_NUMERIC from calibration;
 - a group whose member patches see different modulation (Section 2.3: one
   matrix serves a group only if its patches are encoded alike) ->
   GPJC_E_INVAL at plan creation;
@@ -54,15 +55,15 @@ def test_nan_data_is_reported_by_cg_and_fista(gpu_lib):
     plan.recon_fista(dev(yf[None]), 5, 1e-3, 2.0)
 
 
-def test_jacobi_sweep_cap_is_reported(gpu_lib, monkeypatch):
+def test_eigensolver_residual_check_is_reported(gpu_lib, monkeypatch):
     sl = H.rounded_slice(synth.small_slice(0))
     plan = gpjc.Plan.from_slice(sl)
-    monkeypatch.setenv("GPJC_JACOBI_SWEEP_CAP", "1")
+    monkeypatch.setenv("GPJC_INVIT_ITERS", "0")
     with pytest.raises(gpjc.GpjcError) as e:
         plan.calibrate()
     assert e.value.status == gpjc.GPJC_E_NUMERIC
-    assert "sweep cap" in str(e.value)
-    monkeypatch.delenv("GPJC_JACOBI_SWEEP_CAP")
+    assert "residual check" in str(e.value)
+    monkeypatch.delenv("GPJC_INVIT_ITERS")
     eig, _ = plan.calibrate(want_eigvals=True)
     ref = H.oracle_bank(sl)[1]
     assert np.max(np.abs(eig - ref)) <= 1e-10 * ref.max()
