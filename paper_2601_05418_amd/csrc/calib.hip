@@ -466,6 +466,8 @@ int alloc_calib(Scratch& s, const Plan& pl, bool whiten, CalibBufs& b) {
   GPJC_TRY(s.alloc(&t.pb, gn));
   GPJC_TRY(s.alloc(&t.cb, gn));
   GPJC_TRY(s.alloc(&t.ph, gn));
+  GPJC_TRY(s.alloc(&t.pd, gn));
+  GPJC_TRY(s.alloc(&t.pt, gn * ((ns + 15) / 16)));
   GPJC_TRY(s.alloc(&t.lm, gk));
   GPJC_TRY(s.alloc(&t.u0, gk));
   GPJC_TRY(s.alloc(&t.u1, gk));

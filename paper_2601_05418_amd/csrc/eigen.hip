@@ -145,13 +145,17 @@ __global__ __launch_bounds__(kTT) void k_trd_step(double2* __restrict__ H, int l
 
 constexpr int kTrdRows = 16;  // rows of the trailing block per work-group
 
-// Rows [k+1 + 16 b, +16) of the trailing block of matrix g: apply step k - 1's
-// update (k >= 1), form p_i = tau_k sum_j A22[i][j] v_j, and copy the block's
-// first column (column k + 1) to cb.  C = columns per thread (n <= 256 C).
+// Rows [k+1 + 16 b, +16) of the trailing block of matrix g, lower triangle only
+// (j <= i; the block is Hermitian): apply step k - 1's update (k >= 1) and
+// form the two halves of the product A22 v_k,
+//   direct    pd[i]    = sum_{j <= i} A22[i][j] v_j            (row i),
+//   mirrored  pt[b][j] = sum_{i in block b, i > j} conj(A22[i][j]) v_i,
+// and copy the block's first column (column k + 1) to cb.  The lower triangle
+// is read and written once per step.  C = columns per thread (n <= 256 C).
 template <int C>
 __global__ __launch_bounds__(kTT) void k_trd_pass(double2* __restrict__ H, int ld, int n, int k,
-                                                  const double* __restrict__ tau, const double2* __restrict__ vb,
-                                                  const double2* __restrict__ wb, double2* __restrict__ pb,
+                                                  const double2* __restrict__ vb, const double2* __restrict__ wb,
+                                                  double2* __restrict__ pd, double2* __restrict__ pt,
                                                   double2* __restrict__ cb) {
   __shared__ double2 red[4][kTrdRows];
   const int g = blockIdx.y, G = gridDim.y, tid = threadIdx.x;
@@ -162,54 +166,113 @@ __global__ __launch_bounds__(kTT) void k_trd_pass(double2* __restrict__ H, int l
   const double2* w = wb + gn;
   const bool upd = k >= 1;
   const int j0 = k + 1;
-  double2 vj[C], vpj[C], wj[C];
+  // the longest rows first (block b = last .. 0), so the heaviest work-groups
+  // are not the last ones dispatched
+  const int blk = gridDim.x - 1 - blockIdx.x;
+  const int i0 = j0 + blk * kTrdRows;
+  const int iend = min(n, i0 + kTrdRows);  // rows [i0, iend); columns j < iend
+  double2 vj[C], vpj[C], wj[C], tacc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int j = j0 + tid + kTT * c;
-    const bool in = j < n;
+    const bool in = j < iend;
     vj[c] = in ? v[j] : make_double2(0.0, 0.0);
     vpj[c] = in && upd ? vp[j] : make_double2(0.0, 0.0);
     wj[c] = in && upd ? w[j] : make_double2(0.0, 0.0);
+    tacc[c] = make_double2(0.0, 0.0);
   }
-  const int i0 = j0 + blockIdx.x * kTrdRows;
-  double2 acc[kTrdRows];
+  // Rows go in pairs: the next pair's loads are issued before the current
+  // pair's stores, so waiting for them never waits for the stores.
+  constexpr int RG = 2;
+  double2 cur[RG][C], nxt[RG][C];
+  auto load = [&](int r0, double2(&buf)[RG][C]) {
 #pragma unroll
-  for (int r = 0; r < kTrdRows; ++r) {
-    acc[r] = make_double2(0.0, 0.0);
-    const int i = i0 + r;
-    if (i >= n) continue;
-    double2* row = A + (size_t)i * ld;
-    const double2 vpi = upd ? vp[i] : make_double2(0.0, 0.0), wi = upd ? w[i] : make_double2(0.0, 0.0);
+    for (int rr = 0; rr < RG; ++rr) {
+      const int i = i0 + r0 + rr;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int j = j0 + tid + kTT * c;
-      if (j < n) {
-        double2 a = row[j];
-        if (upd) {
-          a = zsub(a, zadd(zmulc(vpi, wj[c]), zmulc(wi, vpj[c])));
-          row[j] = a;
-        }
-        if (c == 0 && tid == 0) cb[gn + i] = a;  // column k + 1, for the next step
-        acc[r] = zadd(acc[r], zmul(a, vj[c]));
+      for (int c = 0; c < C; ++c) {
+        const int j = j0 + tid + kTT * c;
+        buf[rr][c] = (i < iend && j <= i) ? A[(size_t)i * ld + j] : make_double2(0.0, 0.0);
       }
     }
-  }
+  };
+  load(0, cur);
   const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
-  for (int r = 0; r < kTrdRows; ++r) {
-    double x = acc[r].x, y = acc[r].y;
+  for (int r0 = 0; r0 < kTrdRows; r0 += RG) {
+    if (r0 + RG < kTrdRows) load(r0 + RG, nxt);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      x += __shfl_down(x, o, 64);
-      y += __shfl_down(y, o, 64);
+    for (int rr = 0; rr < RG; ++rr) {
+      const int r = r0 + rr, i = i0 + r;
+      double2 acc = make_double2(0.0, 0.0);
+      if (i < iend) {
+        const double2 vi = v[i];
+        const double2 vpi = upd ? vp[i] : make_double2(0.0, 0.0), wi = upd ? w[i] : make_double2(0.0, 0.0);
+        double2* row = A + (size_t)i * ld;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int j = j0 + tid + kTT * c;
+          if (j <= i) {
+            double2 a = cur[rr][c];
+            if (upd) {
+              a = zsub(a, zadd(zmulc(vpi, wj[c]), zmulc(wi, vpj[c])));
+              row[j] = a;
+            }
+            if (c == 0 && tid == 0) cb[gn + i] = a;  // column k + 1, for the next step
+            acc = zadd(acc, zmul(a, vj[c]));
+            if (j < i) tacc[c] = zadd(tacc[c], zcmul(a, vi));
+          }
+        }
+      }
+      double x = acc.x, y = acc.y;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_down(x, o, 64);
+        y += __shfl_down(y, o, 64);
+      }
+      if (lane == 0) red[wv][r] = make_double2(x, y);
     }
-    if (lane == 0) red[wv][r] = make_double2(x, y);
+#pragma unroll
+    for (int rr = 0; rr < RG; ++rr)
+#pragma unroll
+      for (int c = 0; c < C; ++c) cur[rr][c] = nxt[rr][c];
+  }
+  // mirrored partials of this block: pt[g][blk][j]
+  const int nbk = (n + kTrdRows - 1) / kTrdRows;
+  double2* ptb = pt + ((size_t)g * nbk + blk) * n;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = j0 + tid + kTT * c;
+    if (j < iend) ptb[j] = tacc[c];
   }
   __syncthreads();
-  if (tid < kTrdRows && i0 + tid < n) {
-    const double2 s = zadd(zadd(red[0][tid], red[1][tid]), zadd(red[2][tid], red[3][tid]));
-    pb[gn + i0 + tid] = zscale(s, tau[gn + k]);
+  if (tid < kTrdRows && i0 + tid < iend)
+    pd[gn + i0 + tid] = zadd(zadd(red[0][tid], red[1][tid]), zadd(red[2][tid], red[3][tid]));
+}
+
+// p_j = tau_k (pd[j] + sum over the row blocks at or below j's of pt[b][j]),
+// in block order.
+__global__ __launch_bounds__(kTT) void k_trd_psum(int n, int k, const double* __restrict__ tau,
+                                                  const double2* __restrict__ pd, const double2* __restrict__ pt,
+                                                  double2* __restrict__ pb) {
+  const int g = blockIdx.y;
+  const int j0 = k + 1, m = n - j0;
+  const int j = j0 + blockIdx.x * kTT + threadIdx.x;
+  if (j >= n) return;
+  const size_t gn = (size_t)g * n;
+  const int nbk = (n + kTrdRows - 1) / kTrdRows;
+  const int nb = (m + kTrdRows - 1) / kTrdRows;
+  double2 s = pd[gn + j];
+  const double2* col = pt + (size_t)g * nbk * n + j;
+  // eight partials' loads in flight at a time, summed in block order
+  for (int b = (j - j0) / kTrdRows; b < nb; b += 8) {
+    double2 t[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) t[h] = b + h < nb ? col[(size_t)(b + h) * n] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) s = zadd(s, t[h]);
   }
+  pb[gn + j] = zscale(s, tau[gn + k]);
 }
 
 // ---- 2. real symmetric form, bounds ---------------------------------------------
@@ -479,68 +542,92 @@ __global__ __launch_bounds__(kTT) void k_invit_orth(int n, int K, const double* 
 
 // ---- 5. back-transformation ------------------------------------------------------------
 
-// VB vectors of matrix g per work-group, held in LDS: z = D y, then
-// z <- P_k z for k = n-2 .. 0, P_k z = z - tau_k v_k (v_k^H z) on indices > k,
-// v_k read from row k of H.  Writes U[g][r][.] (the eigenvector of the
-// (r + 1)-th largest eigenvalue).
-__global__ __launch_bounds__(kTT) void k_tri_back(const double2* __restrict__ H, int ld, int n, int K, int VB,
+// VB vectors of matrix g per work-group, in registers (thread tid holds
+// elements tid + 256 q, q < Q): z = D y, then z <- P_k z for k = n-2 .. 0,
+// P_k z = z - tau_k v_k (v_k^H z) on indices > k, v_k read from row k of H
+// (the next row loaded while the current one is applied).  One barrier per
+// reflector (the reduction slots alternate).  Writes U[g][r][.], the
+// eigenvector of the (r + 1)-th largest eigenvalue.
+template <int Q, int VB>
+__global__ __launch_bounds__(kTT) void k_tri_back(const double2* __restrict__ H, int ld, int n, int K,
                                                   const double* __restrict__ tau, const double2* __restrict__ ph,
                                                   const double* __restrict__ y, double2* __restrict__ U) {
-  extern __shared__ double2 zs[];  // [VB][n]
-  __shared__ double2 red[4][8];
+  __shared__ double2 red[2][4][VB];
   const int g = blockIdx.y, tid = threadIdx.x;
   const int r0 = blockIdx.x * VB;
   const int nv = min(VB, K - r0);
   const size_t gn = (size_t)g * n;
-  for (int c = 0; c < nv; ++c)
-    for (int i = tid; i < n; i += kTT) zs[c * n + i] = zscale(ph[gn + i], y[vidx(g, i, r0 + c, n, K)]);
-  __syncthreads();
+  double2 z[VB][Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = tid + kTT * q;
+    const double2 p = i < n ? ph[gn + i] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < VB; ++c) z[c][q] = (i < n && c < nv) ? zscale(p, y[vidx(g, i, r0 + c, n, K)]) : p;
+  }
   const double2* A = H + (size_t)g * ld * ld;
   const int lane = tid & 63, wv = tid >> 6;
+  double2 vn[Q];
+  auto load_row = [&](int k, double2(&v)[Q]) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = tid + kTT * q;
+      v[q] = (k >= 0 && i > k && i < n) ? A[(size_t)k * ld + i] : make_double2(0.0, 0.0);
+    }
+  };
+  load_row(n - 2, vn);
+  int slot = 0;
   for (int k = n - 2; k >= 0; --k) {
+    double2 v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = vn[q];
+    load_row(k - 1, vn);
     const double tk = tau[gn + k];
     if (tk == 0.0) continue;  // uniform across the block
-    double2 s[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) s[c] = make_double2(0.0, 0.0);
-    for (int i = k + 1 + tid; i < n; i += kTT) {
-      const double2 v = A[(size_t)k * ld + i];
+    for (int c = 0; c < VB; ++c) {
+      double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < nv) s[c] = zadd(s[c], zcmul(v, zs[c * n + i]));
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      double a = s[c].x, b = s[c].y;
+      for (int q = 0; q < Q; ++q) s = zadd(s, zcmul(v[q], z[c][q]));
+      double a = s.x, b = s.y;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_down(a, o, 64);
         b += __shfl_down(b, o, 64);
       }
-      if (lane == 0) red[wv][c] = make_double2(a, b);
+      if (lane == 0) red[slot][wv][c] = make_double2(a, b);
     }
     __syncthreads();
-    double2 sc[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-      sc[c] = zscale(zadd(zadd(red[0][c], red[1][c]), zadd(red[2][c], red[3][c])), tk);
-    for (int i = k + 1 + tid; i < n; i += kTT) {
-      const double2 v = A[(size_t)k * ld + i];
+    for (int c = 0; c < VB; ++c) {
+      const double2 sc =
+          zscale(zadd(zadd(red[slot][0][c], red[slot][1][c]), zadd(red[slot][2][c], red[slot][3][c])), tk);
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < nv) zs[c * n + i] = zsub(zs[c * n + i], zmul(v, sc[c]));
+      for (int q = 0; q < Q; ++q) z[c][q] = zsub(z[c][q], zmul(v[q], sc));
     }
-    __syncthreads();
+    slot ^= 1;
   }
-  for (int c = 0; c < nv; ++c)
-    for (int i = tid; i < n; i += kTT) U[((size_t)g * K + r0 + c) * n + i] = zs[c * n + i];
+#pragma unroll
+  for (int c = 0; c < VB; ++c)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = tid + kTT * q;
+      if (c < nv && i < n) U[((size_t)g * K + r0 + c) * n + i] = z[c][q];
+    }
+}
+
+template <int Q, int VB>
+void launch_back(hipStream_t st, const double2* H, int ld, int n, int G, int K, const TriEigBufs& b) {
+  hipLaunchKernelGGL((k_tri_back<Q, VB>), dim3((K + VB - 1) / VB, G), dim3(kTT), 0, st, H, ld, n, K, b.tau, b.ph,
+                     b.x, b.U);
 }
 
 template <int C>
 void launch_pass(hipStream_t st, double2* H, int ld, int n, int k, int G, const TriEigBufs& b) {
   const int m = n - k - 1;
-  const dim3 grid((m + kTrdRows - 1) / kTrdRows, G);
-  hipLaunchKernelGGL(k_trd_pass<C>, grid, dim3(kTT), 0, st, H, ld, n, k, b.tau, b.vb, b.wb, b.pb, b.cb);
+  hipLaunchKernelGGL(k_trd_pass<C>, dim3((m + kTrdRows - 1) / kTrdRows, G), dim3(kTT), 0, st, H, ld, n, k, b.vb,
+                     b.wb, b.pd, b.pt, b.cb);
+  hipLaunchKernelGGL(k_trd_psum, dim3((m + kTT - 1) / kTT, G), dim3(kTT), 0, st, n, k, b.tau, b.pd, b.pt, b.pb);
 }
 
 }  // namespace
@@ -585,9 +672,18 @@ int tri_eigen(hipStream_t st, double2* H, int ld, int n, int G, int K, const Tri
                        it == std::max(iters, 1) - 1 ? 1 : 0, flag);
   }
   GPJC_HIP(hipGetLastError());
-  const int VB = std::max(1, std::min(8, (int)(65536 / (sizeof(double2) * (size_t)n))));  // LDS <= 64 KiB
-  hipLaunchKernelGGL(k_tri_back, dim3((K + VB - 1) / VB, G), dim3(kTT), sizeof(double2) * (size_t)VB * n, st, H, ld,
-                     n, K, VB, b.tau, b.ph, b.x, b.U);
+  // back-transformation: elements per thread Q = ceil(n / 256), 8 vectors per
+  // work-group up to n = 1024, 4 above
+  switch ((n + kTT - 1) / kTT) {
+    case 1: launch_back<1, 8>(st, H, ld, n, G, K, b); break;
+    case 2: launch_back<2, 8>(st, H, ld, n, G, K, b); break;
+    case 3: launch_back<3, 8>(st, H, ld, n, G, K, b); break;
+    case 4: launch_back<4, 8>(st, H, ld, n, G, K, b); break;
+    case 5: launch_back<5, 4>(st, H, ld, n, G, K, b); break;
+    case 6: launch_back<6, 4>(st, H, ld, n, G, K, b); break;
+    case 7: launch_back<7, 4>(st, H, ld, n, G, K, b); break;
+    default: launch_back<8, 4>(st, H, ld, n, G, K, b); break;
+  }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
 }

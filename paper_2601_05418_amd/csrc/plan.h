@@ -204,7 +204,8 @@ int run_lsqr(Plan& pl, Store st, const float2* y, float2* x, int iters, double* 
 // Workspaces of tri_eigen for G matrices of size n and K wanted vectors.
 struct TriEigBufs {
   double *d, *tau, *f, *f2, *eig, *bounds;  // [G][n] each (bounds [G][3]); eig: every eigenvalue, descending
-  double2 *e, *vb, *wb, *pb, *cb, *ph;      // [G][n] each (vb [2][G][n])
+  double2 *e, *vb, *wb, *pb, *cb, *ph, *pd; // [G][n] each (vb [2][G][n])
+  double2* pt;                              // [G][ceil(n / 16)][n]
   double *lm, *u0, *u1, *u2, *x;            // [G][n][K] each
   unsigned char* sw;                        // [G][n][K]
   double2* U;                               // [G][K][n]: eigenvectors of the K largest eigenvalues
