@@ -35,16 +35,73 @@ __host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y
 // -i * a
 __host__ __device__ inline float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
-// Transform lengths the readout and phase-encode kernels are instantiated for.
-#define GPJC_FFT_SIZES(X) \
-  X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128) X(160) X(192) X(224) X(256) X(320) X(384) X(448) X(512)
+// Transform lengths the readout and phase-encode kernels are instantiated for
+// (with 180, 230 and 280: the matrix sizes of the paper's scans).
+#define GPJC_FFT_SIZES(X)                                                                                 \
+  X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128) X(160) X(180) X(192) X(224) X(230) X(256) X(280) X(320) \
+      X(384) X(448) X(512)
+
+// Largest odd prime factor the DFT kernels take.
+constexpr int kMaxOddRadix = 31;
+// ---------------------------------------------------------------------------
+// Compile-time sine / cosine of 2 pi m / n (double, |error| ~ 1e-16).
+// ---------------------------------------------------------------------------
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kHalfPi = 1.5707963267948966192313216916398;
+constexpr double kPi = 3.1415926535897932384626433832795;
+
+// Taylor series on |x| <= pi / 4.
+constexpr double sin_series(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 12; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cos_series(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 12; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+// sin and cos of 2 pi m / n for integers m, n > 0, reduced by quadrant with
+// exact integer arithmetic (4 m mod n picks the quadrant).
+constexpr double sin2pi(long m, long n) {
+  m %= n;
+  if (m < 0) m += n;
+  const long q = (4 * m) / n;                          // quadrant 0..3
+  const double r = kTwoPi * (double)(4 * m - q * n) / (4.0 * (double)n);  // in [0, pi/2)
+  const double s = r <= kHalfPi / 2 ? sin_series(r) : cos_series(kHalfPi - r);
+  const double c = r <= kHalfPi / 2 ? cos_series(r) : sin_series(kHalfPi - r);
+  return q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+}
+constexpr double cos2pi(long m, long n) {
+  m %= n;
+  if (m < 0) m += n;
+  const long q = (4 * m) / n;
+  const double r = kTwoPi * (double)(4 * m - q * n) / (4.0 * (double)n);
+  const double s = r <= kHalfPi / 2 ? sin_series(r) : cos_series(kHalfPi - r);
+  const double c = r <= kHalfPi / 2 ? cos_series(r) : sin_series(kHalfPi - r);
+  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+
 
 // ---------------------------------------------------------------------------
-// Compile-time radix plan: greedy 8, 4, 2, then 7, 5, 3.
+// Compile-time radix plan: greedy 8, 4, 2, then 7, 5, 3, then odd primes up to 31.
 // ---------------------------------------------------------------------------
 constexpr int next_radix(int n) {
-  return (n % 8 == 0) ? 8 : (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2
-       : (n % 7 == 0) ? 7 : (n % 5 == 0) ? 5 : (n % 3 == 0) ? 3 : -1;
+  if (n % 8 == 0) return 8;
+  if (n % 4 == 0) return 4;
+  if (n % 2 == 0) return 2;
+  if (n % 7 == 0) return 7;
+  if (n % 5 == 0) return 5;
+  if (n % 3 == 0) return 3;
+  for (int p = 11; p <= kMaxOddRadix; p += 2)
+    if (n % p == 0) return p;  // the smallest remaining factor is prime
+  return -1;
 }
 constexpr int radix_count(int n) {
   int c = 0;
@@ -71,20 +128,22 @@ constexpr bool fft_length_ok(int n) { return n >= 2 && radix_count(n) > 0; }
 // ---------------------------------------------------------------------------
 // Small forward DFTs in registers.
 // ---------------------------------------------------------------------------
-template <int R> struct OddRoots;  // cos / sin of 2 pi m / R, m = 1 .. (R-1)/2
-template <> struct OddRoots<3> {
-  static constexpr float c[1] = {-0.5f};
-  static constexpr float s[1] = {0.86602540378443864676f};
-};
-template <> struct OddRoots<5> {
-  static constexpr float c[2] = {0.30901699437494742410f, -0.80901699437494742410f};
-  static constexpr float s[2] = {0.95105651629515357212f, 0.58778525229247312917f};
-};
-template <> struct OddRoots<7> {
-  static constexpr float c[3] = {0.62348980185873353053f, -0.22252093395631440429f,
-                                 -0.90096886790241912624f};
-  static constexpr float s[3] = {0.78183148246802980871f, 0.97492791218182360702f,
-                                 0.43388373911755812048f};
+// cos / sin of 2 pi m / R, m = 1 .. (R-1)/2, for an odd R (compile-time series,
+// rounded once).
+template <int R>
+struct OddRoots {
+  struct Tab {
+    float c[(R - 1) / 2], s[(R - 1) / 2];
+  };
+  static constexpr Tab make() {
+    Tab t{};
+    for (int m = 1; m <= (R - 1) / 2; ++m) {
+      t.c[m - 1] = (float)cos2pi(m, R);
+      t.s[m - 1] = (float)sin2pi(m, R);
+    }
+    return t;
+  }
+  static constexpr Tab tab = make();
 };
 
 template <int R>
@@ -137,8 +196,8 @@ __host__ __device__ inline void dft_fwd(float2* v) {
       for (int r = 1; r <= H; ++r) {
         const int m = (r * k) % R;  // angle index in [0, R)
         const int mm = m <= H ? m : R - m;
-        const float cs = OddRoots<R>::c[mm - 1];
-        const float sn = m <= H ? OddRoots<R>::s[mm - 1] : -OddRoots<R>::s[mm - 1];
+        const float cs = OddRoots<R>::tab.c[mm - 1];
+        const float sn = m <= H ? OddRoots<R>::tab.s[mm - 1] : -OddRoots<R>::tab.s[mm - 1];
         a = cadd(a, cscale(sp[r - 1], cs));
         b = cadd(b, cscale(dm[r - 1], sn));
       }

@@ -17,51 +17,6 @@
 
 namespace gpjc {
 
-// ---------------------------------------------------------------------------
-// Compile-time sine / cosine of 2 pi m / n (double, |error| ~ 1e-16).
-// ---------------------------------------------------------------------------
-constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr double kHalfPi = 1.5707963267948966192313216916398;
-constexpr double kPi = 3.1415926535897932384626433832795;
-
-// Taylor series on |x| <= pi / 4.
-constexpr double sin_series(double x) {
-  double term = x, sum = x;
-  for (int k = 1; k < 12; ++k) {
-    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
-    sum += term;
-  }
-  return sum;
-}
-constexpr double cos_series(double x) {
-  double term = 1.0, sum = 1.0;
-  for (int k = 1; k < 12; ++k) {
-    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
-    sum += term;
-  }
-  return sum;
-}
-// sin and cos of 2 pi m / n for integers m, n > 0, reduced by quadrant with
-// exact integer arithmetic (4 m mod n picks the quadrant).
-constexpr double sin2pi(long m, long n) {
-  m %= n;
-  if (m < 0) m += n;
-  const long q = (4 * m) / n;                          // quadrant 0..3
-  const double r = kTwoPi * (double)(4 * m - q * n) / (4.0 * (double)n);  // in [0, pi/2)
-  const double s = r <= kHalfPi / 2 ? sin_series(r) : cos_series(kHalfPi - r);
-  const double c = r <= kHalfPi / 2 ? cos_series(r) : sin_series(kHalfPi - r);
-  return q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
-}
-constexpr double cos2pi(long m, long n) {
-  m %= n;
-  if (m < 0) m += n;
-  const long q = (4 * m) / n;
-  const double r = kTwoPi * (double)(4 * m - q * n) / (4.0 * (double)n);
-  const double s = r <= kHalfPi / 2 ? sin_series(r) : cos_series(kHalfPi - r);
-  const double c = r <= kHalfPi / 2 ? cos_series(r) : sin_series(kHalfPi - r);
-  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
-}
-
 // exp(-2 pi i m / n) as float2, for constant m, n.
 template <long M, long N>
 __host__ __device__ constexpr float2 root() {
@@ -93,7 +48,11 @@ constexpr int first_factor(int r) {
   return (r % 4 == 0 && r != 4 && r != 8) ? 4 : (r % 2 == 0 && r != 2 && r != 4 && r != 8) ? 2
        : (r % 3 == 0 && r != 3) ? 3 : (r % 5 == 0 && r != 5) ? 5 : (r % 7 == 0 && r != 7) ? 7 : r;
 }
-constexpr bool base_dft(int r) { return r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8; }
+// Sizes taken by one base DFT: 2, 4, 8, and odd primes up to 31 (the odd form
+// of dft_fwd); larger sizes are split by first_factor.
+constexpr bool base_dft(int r) {
+  return r == 1 || r == 2 || r == 4 || r == 8 || (r % 2 == 1 && r <= kMaxOddRadix && first_factor(r) == r);
+}
 
 template <int R>
 __host__ __device__ inline void rdft(float2* v);
@@ -140,12 +99,29 @@ __host__ __device__ inline void rdft(float2* v) {
 // Two-pass split of the line lengths the library builds: N = N1 * N2 with
 // N1 the first pass (16 where possible) and N2 <= 32.
 // ---------------------------------------------------------------------------
-constexpr int split_n1(int n) { return n % 16 == 0 && n / 16 > 1 ? 16 : n % 8 == 0 && n / 8 > 1 ? 8 : n % 4 == 0 ? 4 : 1; }
+// N1 is 16, 8 or 4 where that leaves N2 <= 32; otherwise the largest divisor
+// N1 <= 16 with 1 < N2 <= 32 whose factors the register DFTs take (1: none,
+// and the Stockham forms serve the length).
+constexpr bool reg_dft_ok(int r) {
+  while (r > 1) {
+    const int f = first_factor(r);
+    if (f > kMaxOddRadix) return false;
+    r /= f;
+  }
+  return true;
+}
+constexpr int split_n1(int n) {
+  const int first = n % 16 == 0 && n / 16 > 1 ? 16 : n % 8 == 0 && n / 8 > 1 ? 8 : n % 4 == 0 ? 4 : 1;
+  if (first > 1 && n / first <= 32) return first;
+  for (int d = 16; d >= 2; --d)
+    if (n % d == 0 && n / d > 1 && n / d <= 32 && reg_dft_ok(d) && reg_dft_ok(n / d)) return d;
+  return 1;
+}
 template <int N>
 struct Split {
   static constexpr int N1 = split_n1(N);
   static constexpr int N2 = N / N1;
-  static_assert(N1 > 1 && N2 > 1 && N2 <= 32, "no two-pass split for this length");
+  static constexpr bool ok = N1 > 1 && N2 > 1 && N2 <= 32;
 };
 
 }  // namespace gpjc

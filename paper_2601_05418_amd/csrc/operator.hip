@@ -900,13 +900,15 @@ struct ReadoutFwd {
   struct L {
     static int run(const Plan& pl, const float2* img) {
       StageScope sc(pl, GPJC_STAGE_READOUT_FWD, true);
-      if (pl.f2_cb > 0) {
-        const size_t lds = two_pass_lds_fwd(NX, pl.os, pl.f2_cb) * sizeof(float2);
-        dim3 grid(pl.ny, (pl.nc + pl.f2_cb - 1) / pl.f2_cb, pl.B);
-        sc.launch(k_readout_fwd2<NX, ST>, grid, dim3(pl.f2_threads), lds, pl.stream, img, pl.coils, pl.psfp, pl.twin,
-                  pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, pl.f2_cb);
-        GPJC_HIP(hipGetLastError());
-        return GPJC_OK;
+      if constexpr (Split<NX>::ok) {
+        if (pl.f2_cb > 0) {
+          const size_t lds = two_pass_lds_fwd(NX, pl.os, pl.f2_cb) * sizeof(float2);
+          dim3 grid(pl.ny, (pl.nc + pl.f2_cb - 1) / pl.f2_cb, pl.B);
+          sc.launch(k_readout_fwd2<NX, ST>, grid, dim3(pl.f2_threads), lds, pl.stream, img, pl.coils, pl.psfp,
+                    pl.twin, pl.tw_x, (void*)pl.W, pl.ny, pl.nc, pl.os, pl.f2_cb);
+          GPJC_HIP(hipGetLastError());
+          return GPJC_OK;
+        }
       }
       const int rows = pl.f1_rows;
       const size_t lds = (size_t)(NX + 2 * rows * pl.os * fline(NX)) * sizeof(float2);
@@ -925,13 +927,15 @@ struct ReadoutAdj {
   struct L {
     static int run(const Plan& pl) {
       StageScope sc(pl, GPJC_STAGE_READOUT_ADJ, true);
-      if (pl.f2_adj) {
-        const size_t lds = two_pass_lds_adj(NX, pl.os, pl.f2_cb) * sizeof(float2);
-        dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
-        sc.launch(k_readout_adj2<NX, ST>, grid, dim3(pl.f2_threads), lds, pl.stream, (const void*)pl.W, pl.coils,
-                  pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, pl.f2_cb, pl.B);
-        GPJC_HIP(hipGetLastError());
-        return GPJC_OK;
+      if constexpr (Split<NX>::ok) {
+        if (pl.f2_adj) {
+          const size_t lds = two_pass_lds_adj(NX, pl.os, pl.f2_cb) * sizeof(float2);
+          dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
+          sc.launch(k_readout_adj2<NX, ST>, grid, dim3(pl.f2_threads), lds, pl.stream, (const void*)pl.W, pl.coils,
+                    pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, pl.f2_cb, pl.B);
+          GPJC_HIP(hipGetLastError());
+          return GPJC_OK;
+        }
       }
       const size_t lds = (size_t)(NX + 2 * pl.f1h_cb * pl.os * fline(NX)) * sizeof(float2);
       dim3 grid(pl.ny, pl.f1h_nchunk, pl.B);
@@ -985,7 +989,7 @@ struct PeNormal {
     static int run(const Plan& pl) {
       StageScope sc(pl, GPJC_STAGE_PE_NORMAL, true);
       const int nlines = pl.B * pl.np * pl.K;
-      if constexpr (Split<NY>::N1 > 1 && Split<NY>::N2 > 1 && Split<NY>::N2 <= 32) {
+      if constexpr (Split<NY>::ok) {
         constexpr int lines = PeNormal2Geo<NY>::L;
         const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
         sc.launch(k_pe_normal2<NY, ST>, dim3((nlines + lines - 1) / lines), dim3(256), 0, pl.stream,
@@ -1011,7 +1015,7 @@ struct PeCols {
   struct L {
     static int run(const Plan& pl, int mode, const float2* in_s, float2* out_s) {
       StageScope sc(pl, GPJC_STAGE_PE_COLS);
-      if constexpr (ST == Store::F32 && Split<NY>::N1 > 1 && Split<NY>::N2 > 1 && Split<NY>::N2 <= 32) {
+      if constexpr (ST == Store::F32 && Split<NY>::ok) {
         if (mode == 2) {
           constexpr int L = PeCols2Geo<NY>::L;
           hipLaunchKernelGGL((k_pe_cols_normal2<NY>), dim3((pl.nt + L - 1) / L, pl.B * pl.nc), dim3(256), 0,

@@ -63,6 +63,11 @@ int main() {
   worst = std::fmax(worst, check<384>(rng));
   worst = std::fmax(worst, check<448>(rng));
   worst = std::fmax(worst, check<512>(rng));
+  worst = std::fmax(worst, check<180>(rng));
+  worst = std::fmax(worst, check<230>(rng));
+  worst = std::fmax(worst, check<280>(rng));
+  worst = std::fmax(worst, check<1440>(rng));
+  worst = std::fmax(worst, check<920>(rng));
   std::printf("worst %.3e\n", worst);
   return worst < 2e-6 ? 0 : 1;
 }

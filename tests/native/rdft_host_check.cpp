@@ -63,8 +63,11 @@ int main() {
   check_reg<2>(); check_reg<3>(); check_reg<4>(); check_reg<5>(); check_reg<6>(); check_reg<7>(); check_reg<8>();
   check_reg<10>(); check_reg<12>(); check_reg<14>(); check_reg<16>(); check_reg<20>(); check_reg<24>();
   check_reg<28>(); check_reg<32>();
+  check_reg<11>(); check_reg<13>(); check_reg<15>(); check_reg<18>(); check_reg<22>(); check_reg<23>();
+  check_reg<30>(); check_reg<31>();
   check_split<16>(); check_split<32>(); check_split<48>(); check_split<64>(); check_split<80>(); check_split<96>();
   check_split<112>(); check_split<128>(); check_split<160>(); check_split<192>(); check_split<224>();
   check_split<256>(); check_split<320>(); check_split<384>(); check_split<448>(); check_split<512>();
+  check_split<180>(); check_split<230>(); check_split<280>();
   return 0;
 }

@@ -313,3 +313,47 @@ def test_highfield_normal_full_size(gpu_lib):
     ops = H.oracle_ops(sl, a)
     x = H.round64(sl.image)[None]
     check(host(plan.normal(dev(x)))[0], ops["nrm"](x[0]))
+
+
+# The matrix sizes of the paper's scans: lengths of the form 2^a 3^b 5^c
+# (180 = 15 x 12 and 280 = 14 x 20 in the two-pass readout and phase-encode
+# kernels) and one with the prime factor 23 (230 = 10 x 23).
+PAPER_SIZES = {
+    # 180 x 180, 4 coils, os 8 (1440 samples), 45 patches of 32, K = 16
+    "n180": lambda: synth._make_rect(3, nx=180, ny=180, nc=4, os_=8, patch_len=32, k=16, accel=4, acs=16, cycles=7,
+                                     phase_max=4.0),
+    # 230 x 230, 4 coils, os 4 (920 samples), 23 patches of 40, K = 20
+    "n230": lambda: synth._make_rect(4, nx=230, ny=230, nc=4, os_=4, patch_len=40, k=20, accel=4, acs=16, cycles=5,
+                                     phase_max=4.0),
+    # 280 x 280, 4 coils, os 6 (1680 samples), 35 patches of 48, K = 24
+    "n280": lambda: synth._make_rect(5, nx=280, ny=280, nc=4, os_=6, patch_len=48, k=24, accel=4, acs=16, cycles=7,
+                                     phase_max=4.0),
+}
+
+
+@pytest.mark.parametrize("case", list(PAPER_SIZES))
+def test_paper_matrix_sizes(gpu_lib, case):
+    """Compressed forward, adjoint and normal operator, the uncompressed
+    normal operator, and the BF16 / FP16 normal operator (2e-3 / 5e-4) at the
+    paper's matrix sizes, against the oracle."""
+    sl = H.rounded_slice(PAPER_SIZES[case]())
+    g = sl.geom
+    a = H.random_bank(g, seed=23)
+    plan = gpjc.Plan.from_slice(sl)
+    plan.set_compression(torch.as_tensor(a).cuda())
+    ops = H.oracle_ops(sl, a)
+    rng = np.random.default_rng(29)
+    x = H.round64(H.crandn(rng, (1, g.ny, g.nx)))
+    check(host(plan.forward(dev(x)))[0], ops["fwd"](x[0]))
+    y = H.round64(H.crandn(rng, plan.data_shape()))
+    check(host(plan.adjoint(dev(y)))[0], ops["adj"](y[0]))
+    ref = ops["nrm"](x[0])
+    check(host(plan.normal(dev(x)))[0], ref)
+    # 16-bit operands on the phantom (random complex images with a random
+    # bank put more weight in the small samples that 16-bit storage loses)
+    ph = sl.image[None]
+    ref_ph = ops["nrm"](ph[0])
+    assert H.rel_l2(host(plan.normal(dev(ph), prec="bf16"))[0], ref_ph) <= 2e-3
+    assert H.rel_l2(host(plan.normal(dev(ph), prec="fp16"))[0], ref_ph) <= 5e-4
+    unc = gpjc.Plan.from_slice(sl, compressed=False)
+    check(host(unc.normal(dev(x)))[0], ops["nrm_full"](x[0]))
