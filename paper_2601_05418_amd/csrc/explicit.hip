@@ -106,36 +106,17 @@ __global__ __launch_bounds__(256) void k_explicit_fwd(const float2* __restrict__
         ai[b] += m[0] * v[1] + m[1] * v[0] + m[2] * v[3] + m[3] * v[2];
       }
     }
-    // Reduce-scatter across the wave: V = 2 BC sums (re of each image, then
-    // im); each halving step sends half of a lane's sums to its partner, so
-    // after log2 V steps lane l holds sum (l >> S) & (V - 1) over the lanes
-    // that agree in its low S = 6 - log2 V bits, and S full steps finish it.
-    // 2 BC - 1 + S + 1 exchanges instead of 12 BC.
-    constexpr int V = 2 * BC, LV = V == 2 ? 1 : V == 4 ? 2 : V == 8 ? 3 : 4, S = 6 - LV;
-    float val[V];
 #pragma unroll
-    for (int b = 0; b < BC; ++b) {
-      val[b] = ar[b];
-      val[BC + b] = ai[b];
-    }
+    for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-    for (int st = 0; st < LV; ++st) {
-      const int h = V >> (st + 1), off = 32 >> st;
-      const bool low = (lane & off) == 0;  // keep the lower half of the current range
-#pragma unroll
-      for (int i = 0; i < h; ++i) {
-        const float send = low ? val[h + i] : val[i];
-        const float keep = low ? val[i] : val[h + i];
-        val[i] = keep + __shfl_xor(send, off, 64);
+      for (int b = 0; b < BC; ++b) {
+        ar[b] += __shfl_xor(ar[b], off, 64);
+        ai[b] += __shfl_xor(ai[b], off, 64);
       }
-    }
-    float t = val[0];
+    if (lane == 0)
 #pragma unroll
-    for (int off = (1 << S) >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-    const float im = __shfl(t, (lane + (BC << S)) & 63, 64);
-    const int idx = lane >> S;
-    if ((lane & ((1 << S) - 1)) == 0 && idx < BC && b0 + idx < B)
-      Z[((size_t)(b0 + idx) * rows + r) * ny + y] = make_float2(t, im);
+      for (int b = 0; b < BC; ++b)
+        if (b0 + b < B) Z[((size_t)(b0 + b) * rows + r) * ny + y] = make_float2(ar[b], ai[b]);
   }
 }
 
