@@ -45,7 +45,9 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(compile_one, sources()))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-o", tmp, *objs, "-ldl"]
+    # roctx ranges around the entry points (ROCm's tracing library)
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc))), "lib")
+    cmd = [hipcc, *FLAGS, "-o", tmp, *objs, "-ldl", "-L" + rocm_lib, "-Wl,-rpath," + rocm_lib, "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

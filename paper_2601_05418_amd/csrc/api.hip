@@ -335,6 +335,7 @@ extern "C" {
 
 int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_psf, void* hip_stream,
                      gpjc_plan** out) {
+  TraceRange trace("gpjc_plan_create");
   if (!out) return fail(GPJC_E_INVAL, "out is NULL");
   *out = nullptr;
   GPJC_TRY(validate_geom(geom));
@@ -356,6 +357,7 @@ int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_
 
 int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, const gpjc_c64* d_coils,
                         const gpjc_c64* d_psf, void* hip_stream, gpjc_plan** out) {
+  TraceRange trace("gpjc_plan_create_3d");
   if (!out) return fail(GPJC_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!geom) return fail(GPJC_E_INVAL, "geom is NULL");
@@ -401,6 +403,7 @@ int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, con
 
 int gpjc_plan_create_bmap(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_c64* d_bmod, void* hip_stream,
                           gpjc_plan** out) {
+  TraceRange trace("gpjc_plan_create_bmap");
   if (!out) return fail(GPJC_E_INVAL, "out is NULL");
   *out = nullptr;
   GPJC_TRY(validate_geom(geom));
@@ -438,6 +441,7 @@ int gpjc_set_stream(gpjc_plan* plan, void* hip_stream) {
 
 int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov, double* h_eigvals,
                    gpjc_c128* d_A_out) {
+  TraceRange trace("gpjc_calibrate");
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "calibration needs a compressed plan");
   return finish(*plan, run_calibrate(*plan, d_roi, reinterpret_cast<const float2*>(d_noise_cov), h_eigvals,
@@ -446,6 +450,7 @@ int gpjc_calibrate(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_nois
 
 int gpjc_calibrate_static(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64* d_noise_cov, double* h_eigvals,
                           gpjc_c128* d_A_out) {
+  TraceRange trace("gpjc_calibrate_static");
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "calibration needs a compressed plan");
   return finish(*plan, run_calibrate_static(*plan, d_roi, reinterpret_cast<const float2*>(d_noise_cov), h_eigvals,
@@ -453,6 +458,7 @@ int gpjc_calibrate_static(gpjc_plan* plan, const uint8_t* d_roi, const gpjc_c64*
 }
 
 int gpjc_set_compression(gpjc_plan* plan, const gpjc_c128* d_A) {
+  TraceRange trace("gpjc_set_compression");
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "compression bank needs a compressed plan");
   if (!d_A || !aligned(d_A, 16)) return fail(GPJC_E_INVAL, "bank pointer NULL or not 16-byte aligned");
@@ -465,6 +471,7 @@ int gpjc_set_compression(gpjc_plan* plan, const gpjc_c128* d_A) {
 }
 
 int gpjc_compress(const gpjc_plan* plan, const gpjc_c64* d_ksp, gpjc_c64* d_out) {
+  TraceRange trace("gpjc_compress");
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "gpjc_compress needs a compressed plan");
   if (!d_ksp || !d_out) return fail(GPJC_E_INVAL, "NULL buffer");
@@ -475,6 +482,7 @@ int gpjc_compress(const gpjc_plan* plan, const gpjc_c64* d_ksp, gpjc_c64* d_out)
 }
 
 int gpjc_forward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gpjc_c64* d_out) {
+  TraceRange trace("gpjc_forward");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -485,6 +493,7 @@ int gpjc_forward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, g
 }
 
 int gpjc_adjoint(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_in, gpjc_c64* d_img) {
+  TraceRange trace("gpjc_adjoint");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -496,6 +505,7 @@ int gpjc_adjoint(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_in, gp
 }
 
 int gpjc_normal(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gpjc_c64* d_out) {
+  TraceRange trace("gpjc_normal");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -508,6 +518,7 @@ int gpjc_normal(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_img, gp
 
 int gpjc_gd_step(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x, const gpjc_c64* d_b,
                  const float* d_alpha, gpjc_c64* d_x_out, gpjc_c64* d_r_out) {
+  TraceRange trace("gpjc_gd_step");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -522,6 +533,7 @@ int gpjc_gd_step(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x, con
 
 int gpjc_gd_step_backward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_g, const float* d_alpha,
                           const gpjc_c64* d_r, gpjc_c64* d_gx_out, gpjc_c64* d_gb_out, float* d_galpha_out) {
+  TraceRange trace("gpjc_gd_step_backward");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -538,6 +550,7 @@ int gpjc_gd_step_backward(const gpjc_plan* plan, gpjc_prec prec, const gpjc_c64*
 
 int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, int refine_every,
                   double* h_resid) {
+  TraceRange trace("gpjc_recon_cg");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -551,11 +564,13 @@ int gpjc_recon_cg(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64
 
 int gpjc_recon_fista(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, double lambda,
                      double lipschitz, int haar_levels, double* h_obj) {
+  TraceRange trace("gpjc_recon_fista");
   return gpjc_recon_fista_tv(plan, prec, d_y, d_x, iters, lambda, 0.0, 1.0, lipschitz, haar_levels, h_obj);
 }
 
 int gpjc_recon_fista_tv(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters, double lambda,
                         double lambda_tv, double tv_eps, double lipschitz, int haar_levels, double* h_obj) {
+  TraceRange trace("gpjc_recon_fista_tv");
   if (!(lambda_tv >= 0.0) || !std::isfinite(lambda_tv)) return fail(GPJC_E_INVAL, "lambda_tv must be >= 0");
   if (!(tv_eps > 0.0) || !std::isfinite(tv_eps)) return fail(GPJC_E_INVAL, "tv_eps must be positive");
   if (plan && plan->nz > 1 && lambda_tv != 0.0)
@@ -580,6 +595,7 @@ int gpjc_recon_fista_tv(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gp
 
 int gpjc_recon_lsqr(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c64* d_x, int iters,
                     double* h_resid) {
+  TraceRange trace("gpjc_recon_lsqr");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -596,6 +612,7 @@ int gpjc_recon_lsqr(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_y, gpjc_c
 }
 
 int gpjc_power_iteration(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x0, int iters, double* h_lambda) {
+  TraceRange trace("gpjc_power_iteration");
   GPJC_TRY(check_plan(plan));
   Store st;
   GPJC_TRY(check_prec(*plan, prec, &st));
@@ -606,6 +623,7 @@ int gpjc_power_iteration(gpjc_plan* plan, gpjc_prec prec, const gpjc_c64* d_x0, 
 }
 
 int gpjc_wavelet_absmax(gpjc_plan* plan, const gpjc_c64* d_img, int haar_levels, double* h_out) {
+  TraceRange trace("gpjc_wavelet_absmax");
   GPJC_TRY(check_plan(plan));
   if (!d_img || !aligned(d_img, 8) || !h_out) return fail(GPJC_E_INVAL, "NULL or misaligned buffer");
   if (haar_levels < 1 || haar_levels > 3) return fail(GPJC_E_UNSUPPORTED, "haar_levels must be 1, 2 or 3");

@@ -225,6 +225,7 @@ int gpjc_batch_lanes(const gpjc_batch* batch, int* h_lane_of) {
 
 int gpjc_batch_recon_cg(gpjc_batch* batch, gpjc_prec prec, const gpjc_c64* const* d_y, gpjc_c64* const* d_x,
                         int iters, int refine_every, double* h_resid) {
+  TraceRange trace("gpjc_batch_recon_cg");
   if (!batch) return fail(GPJC_E_INVAL, "batch is NULL");
   if (!d_y || !d_x) return fail(GPJC_E_INVAL, "pointer arrays are NULL");
   if (refine_every < 0) return fail(GPJC_E_INVAL, "refine_every must be >= 0");
@@ -281,6 +282,7 @@ int gpjc_batch_recon_cg(gpjc_batch* batch, gpjc_prec prec, const gpjc_c64* const
 }
 
 int gpjc_autotune(gpjc_plan* plan, gpjc_prec prec, const char* cache_path, int* h_choice) {
+  TraceRange trace("gpjc_autotune");
   if (!plan) return fail(GPJC_E_INVAL, "plan is NULL");
   if (plan->general) return fail(GPJC_E_UNSUPPORTED, "modulation-map plans have no group contraction to tune");
   Store st = Store::F32;
@@ -290,6 +292,7 @@ int gpjc_autotune(gpjc_plan* plan, gpjc_prec prec, const char* cache_path, int* 
 }
 
 int gpjc_batch_autotune(gpjc_batch* batch, gpjc_prec prec, const char* cache_path) {
+  TraceRange trace("gpjc_batch_autotune");
   if (!batch) return fail(GPJC_E_INVAL, "batch is NULL");
   for (gpjc_plan* p : batch->plans) GPJC_TRY(gpjc_autotune(p, prec, cache_path, nullptr));
   return GPJC_OK;

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <string>
@@ -160,6 +161,15 @@ struct StageScope {
     if (single && !consumed) (void)hipEventRecord(pl.timing.ev[2 * slot], pl.stream);
     if (!single || !consumed) (void)hipEventRecord(pl.timing.ev[2 * slot + 1], pl.stream);
   }
+};
+
+// A named range around one library call, for tracing tools (rocprofv3
+// --marker-trace shows it; without a tool attached it costs a function call).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
 };
 
 // Argument checks shared by the entry points (api.hip).
