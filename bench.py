@@ -31,7 +31,8 @@ METRIC = "compressed E^H E applications/s and s/slice recon vs plain FP32, at <=
 ITERS = 50
 LEVELS = 3
 
-PEAKS = {"hbm": 8.0e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15}
+PEAKS = {"hbm": 8.0e12, "fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x6": 2.5e15}
+DTYPES = {"fp32": "f32", "bf16": "bf16", "fp16": "f16", "bf16x6": "f32 (bf16x6 contractions)"}
 
 # Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
 # plain copy) for the FP32 operator on this workload, with the hash of the
@@ -53,10 +54,16 @@ def log(msg):
 def stage_work(g, stage, prec, ksplit_read=1):
     """Algorithmic work of one launch of a stage: (bound, amount, unit)."""
     B, nx, ny, nc, nt = 1, g.nx, g.ny, g.nc, g.nt
-    wbytes = 8 if prec == "fp32" else 4
+    wbytes = 8 if prec in ("fp32", "bf16x6") else 4
     if stage in ("group_compress", "group_expand"):
         if prec == "fp32":  # arithmetic intensity ~50 flop/B, above the FP32 MFMA ridge (~20)
             return "mfma", 8.0 * B * g.k * nc * nt * ny, "flop"
+        if prec == "bf16x6":
+            # FP32 W once, one FP32 row of each expanded bank pair once, Z once in FP32;
+            # the six BF16 products issue 6 x 8 flops per complex multiply-add, about
+            # 0.9 of the HBM time at the BF16 peak: HBM-bound
+            bank = 4.0 * g.n_groups * g.k * 2 * g.ns
+            return "hbm", 8.0 * B * nc * ny * nt + bank + 8.0 * B * g.n_patches * g.k * ny, "byte"
         # 16-bit operands: ~90 flop/B, far below the BF16/FP16 ridge (~300): HBM-bound.
         # W (16-bit) once, the 16-bit real-form bank once, Z in FP32 (compress) / 16-bit (expand).
         bank = 2.0 * g.n_groups * (2 * g.k) * (2 * g.ns)
@@ -465,7 +472,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp16", "bf16x6"])
     ap.add_argument("--periodic", action="store_true", help="map the 42 patches onto the 6 of one wave period")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -621,7 +628,7 @@ def main():
     # the same operator with 16-bit operands (FP32 accumulation), and the
     # uncompressed FP32 operator on the same slice
     variants = {args.prec: op_rate}
-    for pr in ("fp32", "bf16", "fp16"):
+    for pr in ("fp32", "bf16", "fp16", "bf16x6"):
         if pr != args.prec:
             variants[pr] = op_rate_of(plan, pr)
     unc = gpjc.Plan.from_slice(sl, compressed=False)
@@ -645,6 +652,29 @@ def main():
               "speedup_of_compressed": dt_u / (ms_per_step / 1e3)}
     unc.close()
     log(f"uncompressed FP32 FISTA-{ITERS}: {dt_u * 1e3:.3f} ms per slice")
+    # The same reconstruction with the contractions in BF16X6 (FP32 storage,
+    # FP32-accurate split-BF16 products), timed the same way
+    split_run = None
+    if args.prec == "fp32":
+        xs = torch.empty_like(x)
+        for _ in range(max(1, args.warmup)):
+            plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec="bf16x6", out=xs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            plan.recon_fista(y, ITERS, lam, lip, LEVELS, prec="bf16x6", out=xs)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t) / args.steps
+        split_run = {"s_per_slice": dt_s, "apps_per_s": ITERS / dt_s, "op_apps_per_s": variants["bf16x6"],
+                     "speedup_vs_fp32_compressed": (ms_per_step / 1e3) / dt_s,
+                     "speedup_vs_uncompressed_fp32": dt_u / dt_s}
+        if gold is not None:
+            xr = xs.cpu().numpy()[0].astype(np.complex128)
+            ref = gold["x"].astype(np.complex128)
+            mag = np.abs(ref)
+            split_run["fista50_nrmse_vs_stored_oracle"] = float(
+                np.sqrt(np.mean(np.abs(xr - ref) ** 2)) / (mag.max() - mag.min()))
+        log(f"BF16X6 FISTA-{ITERS}: {dt_s * 1e3:.3f} ms per slice")
 
     bound, work, kind = stage_work(g, dom, args.prec)
     avg_s = live[0] / live[1] / 1e3  # measured over the timed steps
@@ -678,7 +708,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[args.prec],
+        "dtype": DTYPES[args.prec],
         "data": "synthetic",
         "config": {
             "workload": f"2D high-field slice {g.nx}x{g.ny}, {g.nc} coils, os {g.os} ({g.nt} samples), "
@@ -692,7 +722,9 @@ def main():
         "op_apps_per_s_by_variant": variants,
         "uncompressed_fp32": uncomp,
         # the reduced-precision forms against the plain FP32 compressed operator
-        "op_speedup_vs_fp32": {k: variants[k] / variants["fp32"] for k in ("bf16", "fp16") if "fp32" in variants},
+        "op_speedup_vs_fp32": {k: variants[k] / variants["fp32"] for k in ("bf16", "fp16", "bf16x6")
+                               if "fp32" in variants},
+        "fp32_accurate_bf16x6": split_run,
         "calibrate_s": t_cal,
         "compress_s": t_comp,
         "stages": per_stage,

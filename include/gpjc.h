@@ -62,8 +62,15 @@ typedef struct { double re, im; } gpjc_c128;
  * contraction is carried as a hi + lo pair of 16-bit values (hi = rn(z),
  * lo = rn(z - hi)), so it adds almost no rounding of its own.  FFTs, coil
  * products and the phase-encode stage compute in FP32.  FP16 needs every stored value below 65504 in magnitude
- * (non-finite results surface as GPJC_E_NUMERIC in the solvers). */
-typedef enum { GPJC_FP32 = 0, GPJC_BF16 = 1, GPJC_FP16 = 2 } gpjc_prec;
+ * (non-finite results surface as GPJC_E_NUMERIC in the solvers).
+ * BF16X6: FP32 storage and FP32 accuracy, with both group contractions on the
+ * BF16 MFMA: every FP32 operand is split into three BF16 pieces (each the
+ * nearest-even BF16 of what the earlier pieces leave) and the six piece
+ * products whose orders sum to at most two are accumulated in FP32; what it
+ * drops is below 2^-26 of each product.  Any patch_len; plans without group
+ * contractions (uncompressed, modulation-map) run their FP32 path for it.
+ * Section 2.4, Eqs. 13-14, for the contractions themselves. */
+typedef enum { GPJC_FP32 = 0, GPJC_BF16 = 1, GPJC_FP16 = 2, GPJC_BF16X6 = 3 } gpjc_prec;
 
 enum {
   GPJC_OK = 0,

@@ -156,7 +156,7 @@ static void choose_launch(Plan& pl) {
     // the explicit adjoint leaves one partial image per chunk of rows (p, k);
     // the explicit forward writes Z whole, so the phase-encode stage reads one split
     pl.f1h_nchunk = explicit_chunks(pl.np * pl.K, pl.ny, pl.B);
-    pl.gemm[0].ksplit = 1;
+    for (Plan::GemmCfg& g : pl.gemm) g.ksplit = 1;
   }
 }
 
@@ -309,15 +309,23 @@ static int check_plan(const gpjc_plan* plan) {
   return GPJC_OK;
 }
 
+static bool known_prec(int prec) {
+  return prec == GPJC_FP32 || prec == GPJC_BF16 || prec == GPJC_FP16 || prec == GPJC_BF16X6;
+}
+static Store store_of_prec(int prec) {
+  return prec == GPJC_FP32 ? Store::F32 : prec == GPJC_BF16 ? Store::BF16 : prec == GPJC_FP16 ? Store::F16 : Store::BF16X6;
+}
+
+// BF16X6 is accepted by every plan: plans without group contractions (the
+// uncompressed and modulation-map operators) run their FP32 path for it.
 int check_prec(const Plan& pl, int prec, Store* st) {
-  if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
-  if (prec != GPJC_FP32 && !pl.compressed)
-    return fail(GPJC_E_UNSUPPORTED, "the uncompressed operator is FP32 only");
-  if (prec != GPJC_FP32 && pl.general)
+  if (!known_prec(prec)) return fail(GPJC_E_INVAL, "unknown precision");
+  const bool b16 = prec == GPJC_BF16 || prec == GPJC_FP16;
+  if (b16 && !pl.compressed) return fail(GPJC_E_UNSUPPORTED, "the uncompressed operator is FP32 only");
+  if (b16 && pl.general)
     return fail(GPJC_E_UNSUPPORTED, "the explicit readout model of a modulation-map plan is FP32 only");
-  if (prec != GPJC_FP32 && pl.P % 4)
-    return fail(GPJC_E_UNSUPPORTED, "16-bit contractions need patch_len divisible by 4");
-  *st = prec == GPJC_FP32 ? Store::F32 : prec == GPJC_BF16 ? Store::BF16 : Store::F16;
+  if (b16 && pl.P % 4) return fail(GPJC_E_UNSUPPORTED, "16-bit contractions need patch_len divisible by 4");
+  *st = store_of_prec(prec);
   return GPJC_OK;
 }
 
@@ -680,12 +688,12 @@ int gpjc_set_gemm_config(gpjc_plan* plan, gpjc_prec prec, int compress_variant, 
   GPJC_TRY(check_plan(plan));
   if (!plan->compressed) return fail(GPJC_E_INVAL, "GEMM configuration needs a compressed plan");
   if (plan->general) return fail(GPJC_E_UNSUPPORTED, "modulation-map plans have no group contraction to configure");
-  if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
+  if (!known_prec(prec)) return fail(GPJC_E_INVAL, "unknown precision");
   if (compress_variant < 0 || compress_variant >= gemm_compress_variants() || expand_variant < 0 ||
       expand_variant >= gemm_expand_variants())
     return fail(GPJC_E_INVAL, "unknown GEMM variant");
   if (ksplit < 1 || ksplit > kMaxKsplit) return fail(GPJC_E_INVAL, "ksplit out of range");
-  Plan::GemmCfg& c = plan->cfg(prec == GPJC_FP32 ? Store::F32 : Store::BF16);
+  Plan::GemmCfg& c = plan->cfg(store_of_prec(prec));
   c.cvar = compress_variant;
   c.evar = expand_variant;
   c.ksplit = ksplit;
@@ -696,8 +704,8 @@ int gpjc_set_gemm_config(gpjc_plan* plan, gpjc_prec prec, int compress_variant, 
 int gpjc_get_gemm_config(const gpjc_plan* plan, gpjc_prec prec, int* compress_variant, int* expand_variant,
                          int* ksplit, int* n_compress_variants, int* n_expand_variants) {
   GPJC_TRY(check_plan(plan));
-  if (prec != GPJC_FP32 && prec != GPJC_BF16 && prec != GPJC_FP16) return fail(GPJC_E_INVAL, "unknown precision");
-  const Plan::GemmCfg& c = plan->cfg(prec == GPJC_FP32 ? Store::F32 : Store::BF16);
+  if (!known_prec(prec)) return fail(GPJC_E_INVAL, "unknown precision");
+  const Plan::GemmCfg& c = plan->cfg(store_of_prec(prec));
   if (compress_variant) *compress_variant = c.cvar;
   if (expand_variant) *expand_variant = c.evar;
   if (ksplit) *ksplit = c.ksplit;

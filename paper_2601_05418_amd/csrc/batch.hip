@@ -241,7 +241,7 @@ int gpjc_batch_recon_cg(gpjc_batch* batch, gpjc_prec prec, const gpjc_c64* const
     if (reinterpret_cast<uintptr_t>(d_y[i]) % 8 || reinterpret_cast<uintptr_t>(d_x[i]) % 8)
       return fail(GPJC_E_INVAL, "slice " + std::to_string(i) + ": buffers must be 8-byte aligned");
   }
-  const bool refine = refine_every > 0 && st != Store::F32;
+  const bool refine = refine_every > 0 && is_16bit(st);
   // Work queued by the caller on the plans' own streams comes first.
   for (int i = 0; i < n; ++i) GPJC_HIP(hipStreamSynchronize(b.plans[i]->stream));
   std::vector<int> flags(n, 0);

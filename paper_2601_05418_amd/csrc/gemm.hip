@@ -15,6 +15,18 @@
 //   row of each pair is read, conj(A) (compressing) or A (expanding), and
 //   three real products t1, t2, t3 are combined at the end (block_mma).
 //
+// BF16X6 keeps FP32 storage and runs the contraction on the BF16 MFMA: each
+// FP32 operand is split, as it is staged into LDS, into three BF16 pieces
+// x = x0 + x1 + x2 (x0 the nearest BF16 to x, x1 the nearest to x - x0, x2
+// the nearest to what remains; the remainders are exact in FP32) and the six
+// piece products whose orders sum to at most two (00, 01, 10, 02, 11, 20) are
+// accumulated in FP32 (the split-operand emulation of a wider product by
+// narrow ones, as in Ootomo and Yokota, 2022, and Henry et al., 2019).  The
+// dropped products and the last piece's rounding are below 2^-26 of each
+// product, under FP32's own rounding of the result.  The bank is read in its
+// FP32 form, one row of each expanded pair, and the other row is derived in
+// registers ((u, v) -> (-v, u) per complex element, exact on the pieces).
+//
 // In the 16-bit expanding contraction the phase-encode output Z^T is carried
 // as a hi + lo pair of 16-bit values (hi = rn(z), lo = rn(z - hi)): its rows
 // hold both parts one after the other and meet the same bank row twice, so
@@ -65,6 +77,33 @@ struct Mma<Store::F32> {
   static constexpr int LW = 4;
   static constexpr int NE = 4;
 };
+template <>
+struct Mma<Store::BF16X6> {  // staged form only; the data are FP32
+  using E = float;
+  static constexpr int KB = 32;
+  static constexpr int LW = 8;
+  static constexpr int NE = 1;
+};
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int kPieces = 3;  // BF16 pieces per FP32 operand in BF16X6
+
+// The kPieces BF16 pieces of four FP32 values, four per 8-byte word: piece q
+// is the nearest-even BF16 of what pieces 0..q-1 leave of each value.
+__device__ inline void split_pieces(const floatx4& v, uint2 (&p)[kPieces]) {
+  floatx4 r = v;
+#pragma unroll
+  for (int q = 0; q < kPieces; ++q) {
+    const bf16x4 h = __builtin_convertvector(r, bf16x4);
+    p[q] = __builtin_bit_cast(uint2, h);
+    if (q + 1 < kPieces) r -= __builtin_convertvector(h, floatx4);
+  }
+}
+// Pieces of the partner row of an expanded pair: (u, v) -> (-v, u) for each
+// complex element held as two BF16 halves of a word.
+__device__ inline uint2 partner_pieces(uint2 p) {
+  return make_uint2(__builtin_rotateleft32(p.x, 16) ^ 0x8000u, __builtin_rotateleft32(p.y, 16) ^ 0x8000u);
+}
 
 // One MFMA step: 16-byte lane operands a, b (bit containers), step e of the block.
 template <Store ST>
@@ -400,6 +439,32 @@ struct Geo<Store::F32> {
   }
 };
 
+template <>
+struct Geo<Store::BF16X6> {
+  static constexpr int T = 16, KB = 32, LW = 8, NE = 1, NR = 4;
+  using Acc = floatx4;
+  __device__ static int row_of(int r, int h) { return 4 * h + r; }
+};
+
+// One k-tile of the BF16X6 product: piece fragments fa[m][q], fb[c][q] (eight
+// BF16 of one row each); every accumulator takes the six products of pieces
+// whose orders sum to at most kPieces - 1, larger orders first.
+template <int MT, int NT>
+__device__ inline void split_mma(const floatx4 (&fa)[MT][kPieces], const floatx4 (&fb)[NT][kPieces],
+                                 floatx4 (&acc)[MT][NT]) {
+#pragma unroll
+  for (int s = kPieces - 1; s >= 0; --s)
+#pragma unroll
+    for (int q = 0; q <= s; ++q)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+          acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, fa[m][q]),
+                                                               __builtin_bit_cast(bf16x8, fb[c][s - q]), acc[m][c],
+                                                               0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------
 // Compressing contraction staged through LDS.  The operand layout of an MFMA
 // spans 16 or 32 rows per load instruction, so register-direct loads touch
@@ -454,20 +519,25 @@ __device__ inline void block_mma(const floatx4 (&fa)[MT], const floatx4 (&fb)[NT
 
 template <int WM, int WN, int MT, int NT, int PF, Store ST, bool ODD>
 __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
-  static_assert(!ODD || ST == Store::F32, "odd patch lengths are built for FP32 only");
+  constexpr bool SPL = ST == Store::BF16X6;
+  static_assert(!ODD || ST == Store::F32 || SPL, "odd patch lengths are built for FP32 data only");
   using G = Geo<ST>;
   using E = typename Mma<ST>::E;
   constexpr int T = G::T, NR = G::NR;
   constexpr int ES = (int)sizeof(E);
-  constexpr int KT = 128 / ES, LS = 36;  // k-tile elements per row; LDS row stride in floats
+  // k-tile elements per row; LDS row stride in floats (BF16X6: the pieces of
+  // a row's k-tile one after the other, 16 floats each)
+  constexpr int KT = 128 / ES, LS = SPL ? 16 * kPieces + 4 : 36;
   // FP32 takes the three-multiplication form: a.M counts complex rows k, and
   // row k is bank row 2k, conj(A_g[k]) interleaved.
   constexpr bool C3 = ST == Store::F32;
   constexpr int RS = C3 ? 2 : 1, NA = C3 ? 3 : 1;  // bank rows per kernel row; accumulators per tile
-  constexpr int JB = 128 / (G::KB * ES), JF = G::KB * ES / 4;  // MFMA blocks per k-tile, floats per block
+  constexpr int JB = SPL ? 1 : 128 / (G::KB * ES), JF = G::KB * ES / 4;  // MFMA blocks per k-tile, floats per block
   constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
-  constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;  // 16-byte chunks per thread per k-tile
-  static_assert(AR * NTHR == TM * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
+  // bank rows loaded per k-tile (BF16X6: the first row of each expanded pair)
+  constexpr int TA = SPL ? TM / 2 : TM;
+  constexpr int AR = TA * 8 / NTHR, BR = TN * 8 / NTHR;  // 16-byte chunks per thread per k-tile
+  static_assert(AR * NTHR == TA * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
   __shared__ floatx4 smem[(TM + TN) * LS / 4];
   float* As = reinterpret_cast<float*>(smem);
   float* Bs = As + TM * LS;
@@ -517,7 +587,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
   uint32_t va[AR], vb[BR];
 #pragma unroll
   for (int r = 0; r < AR; ++r) {
-    const int row = tm * TM + (tid >> 3) + r * (NTHR / 8);
+    const int lr = (tid >> 3) + r * (NTHR / 8);
+    const int row = tm * TM + (SPL ? 2 * lr : lr);
     va[r] = row < a.M ? (uint32_t)(((size_t)row * RS * a.KD + kk) * ES) : kOOB;
   }
 #pragma unroll
@@ -574,24 +645,61 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
       const int st = st0 + f;
       if (st >= nst) break;
       __syncthreads();  // the previous k-tile has been read
+      if constexpr (SPL) {
 #pragma unroll
-      for (int r = 0; r < AR; ++r)
-        *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[f][r];
+        for (int r = 0; r < AR; ++r) {
+          uint2 pc[kPieces];
+          split_pieces(pa[f][r], pc);
+          float* row = As + 2 * ((tid >> 3) + r * (NTHR / 8)) * LS + 2 * c16;
 #pragma unroll
-      for (int r = 0; r < BR; ++r)
-        *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[f][r];
+          for (int q = 0; q < kPieces; ++q) {
+            *reinterpret_cast<uint2*>(row + 16 * q) = pc[q];
+            *reinterpret_cast<uint2*>(row + LS + 16 * q) = partner_pieces(pc[q]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+          uint2 pc[kPieces];
+          split_pieces(pb[f][r], pc);
+          float* row = Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 2 * c16;
+#pragma unroll
+          for (int q = 0; q < kPieces; ++q) *reinterpret_cast<uint2*>(row + 16 * q) = pc[q];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < AR; ++r)
+          *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[f][r];
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+          *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[f][r];
+      }
       __syncthreads();
       if (st + PF < nst) fetch(pa[f], pb[f]);
+      if constexpr (SPL) {
+        floatx4 fa[MT][kPieces], fb[NT][kPieces];
 #pragma unroll
-      for (int j = 0; j < JB; ++j) {
-      floatx4 fa[MT], fb[NT];
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int m = 0; m < MT; ++m)
-        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + JF * j + 4 * lh);
+          for (int q = 0; q < kPieces; ++q)
+            fa[m][q] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + 16 * q + 4 * lh);
 #pragma unroll
-      for (int c = 0; c < NT; ++c)
-        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
-        block_mma<ST, true>(fa, fb, acc);
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+          for (int q = 0; q < kPieces; ++q)
+            fb[c][q] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 16 * q + 4 * lh);
+        split_mma<MT, NT>(fa, fb, acc[0]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+          floatx4 fa[MT], fb[NT];
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+            fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + JF * j + 4 * lh);
+#pragma unroll
+          for (int c = 0; c < NT; ++c)
+            fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
+          block_mma<ST, true>(fa, fb, acc);
+        }
       }
     }
   }
@@ -626,19 +734,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_compress_lds(CompressArgs a) {
 // is staged through the same LDS to write whole W row segments.
 template <int WM, int WN, int MT, int NT, int PF, Store ST>
 __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
+  constexpr bool SPL = ST == Store::BF16X6;
   using G = Geo<ST>;
   using E = typename Mma<ST>::E;
   constexpr int T = G::T, NR = G::NR;
   constexpr int ES = (int)sizeof(E);
-  constexpr int KT = 128 / ES, LS = 36;
+  constexpr int KT = 128 / ES, LS = SPL ? 16 * kPieces + 4 : 36;
   // FP32 takes the three-multiplication form: a.N counts complex columns
   // (n, j), and column i is bank row 2i, A_g[:, i] interleaved.
   constexpr bool C3 = ST == Store::F32;
   constexpr int RS = C3 ? 2 : 1, NA = C3 ? 3 : 1, CF = C3 ? 2 : 1;  // CF: output floats per column
-  constexpr int JB = 128 / (G::KB * ES), JF = G::KB * ES / 4;
+  constexpr int JB = SPL ? 1 : 128 / (G::KB * ES), JF = G::KB * ES / 4;
   constexpr int TM = WM * MT * T, TN = WN * NT * T, NTHR = 64 * WM * WN;
-  constexpr int AR = TM * 8 / NTHR, BR = TN * 8 / NTHR;
-  static_assert(AR * NTHR == TM * 8 && BR * NTHR == TN * 8, "tile rows must split evenly over the threads");
+  constexpr int TB = SPL ? TN / 2 : TN;  // bank rows loaded per k-tile (BF16X6: first row of each pair)
+  constexpr int AR = TM * 8 / NTHR, BR = TB * 8 / NTHR;
+  static_assert(AR * NTHR == TM * 8 && BR * NTHR == TB * 8, "tile rows must split evenly over the threads");
   constexpr int LDT = CF * TN + 4;
   constexpr int SM = ((TM + TN) * LS > TM * LDT ? (TM + TN) * LS : TM * LDT);
   __shared__ floatx4 smem[SM / 4];
@@ -672,7 +782,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
   }
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
-    const int cc = tn * TN + (tid >> 3) + r * (NTHR / 8);
+    const int lr = (tid >> 3) + r * (NTHR / 8);
+    const int cc = tn * TN + (SPL ? 2 * lr : lr);
     const int kb0 = (a.kwrap && kc >= a.kwrap) ? kc - a.kwrap : kc;  // a chunk may start in the lo part
     vb[r] = cc < a.N ? (uint32_t)(((size_t)cc * RS * a.KDB + kb0) * ES) : kOOB;
   }
@@ -708,24 +819,61 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
       const int st = st0 + f;
       if (st >= nst) break;
       __syncthreads();
+      if constexpr (SPL) {
 #pragma unroll
-      for (int r = 0; r < AR; ++r)
-        *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[f][r];
+        for (int r = 0; r < AR; ++r) {
+          uint2 pc[kPieces];
+          split_pieces(pa[f][r], pc);
+          float* row = As + ((tid >> 3) + r * (NTHR / 8)) * LS + 2 * c16;
 #pragma unroll
-      for (int r = 0; r < BR; ++r)
-        *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[f][r];
+          for (int q = 0; q < kPieces; ++q) *reinterpret_cast<uint2*>(row + 16 * q) = pc[q];
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+          uint2 pc[kPieces];
+          split_pieces(pb[f][r], pc);
+          float* row = Bs + 2 * ((tid >> 3) + r * (NTHR / 8)) * LS + 2 * c16;
+#pragma unroll
+          for (int q = 0; q < kPieces; ++q) {
+            *reinterpret_cast<uint2*>(row + 16 * q) = pc[q];
+            *reinterpret_cast<uint2*>(row + LS + 16 * q) = partner_pieces(pc[q]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < AR; ++r)
+          *reinterpret_cast<floatx4*>(As + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pa[f][r];
+#pragma unroll
+        for (int r = 0; r < BR; ++r)
+          *reinterpret_cast<floatx4*>(Bs + ((tid >> 3) + r * (NTHR / 8)) * LS + 4 * c16) = pb[f][r];
+      }
       __syncthreads();
       if (st + PF < nst) fetch(pa[f], pb[f]);
+      if constexpr (SPL) {
+        floatx4 fa[MT][kPieces], fb[NT][kPieces];
 #pragma unroll
-      for (int j = 0; j < JB; ++j) {
-      floatx4 fa[MT], fb[NT];
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int m = 0; m < MT; ++m)
-        fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + JF * j + 4 * lh);
+          for (int q = 0; q < kPieces; ++q)
+            fa[m][q] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + 16 * q + 4 * lh);
 #pragma unroll
-      for (int c = 0; c < NT; ++c)
-        fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
-        block_mma<ST, false>(fa, fb, acc);
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+          for (int q = 0; q < kPieces; ++q)
+            fb[c][q] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + 16 * q + 4 * lh);
+        split_mma<MT, NT>(fa, fb, acc[0]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+          floatx4 fa[MT], fb[NT];
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+            fa[m] = *reinterpret_cast<const floatx4*>(As + (wm * MT * T + T * m + li) * LS + JF * j + 4 * lh);
+#pragma unroll
+          for (int c = 0; c < NT; ++c)
+            fb[c] = *reinterpret_cast<const floatx4*>(Bs + (wn * NT * T + T * c + li) * LS + JF * j + 4 * lh);
+          block_mma<ST, false>(fa, fb, acc);
+        }
       }
     }
   }
@@ -752,7 +900,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_expand_lds(ExpandArgs a) {
     const int rl = e / (TF / 4), cl = (e - rl * (TF / 4)) * 4;
     const int y = rbase + rl, col = cbase + cl;
     if (y >= a.M || col >= ncolf) continue;
-    store_w_quad<ST>(a.W, tile + rl * LDT + cl, b, y, col, ncolf, a.M, a.nc, a.nt, a.P, p);
+    store_w_quad<storage_of(ST)>(a.W, tile + rl * LDT + cl, b, y, col, ncolf, a.M, a.nc, a.nt, a.P, p);
   }
 }
 
@@ -813,12 +961,22 @@ constexpr Shape kCompressLds16[kNumShapes] = {{4, 1, 2, 4, 1}, {2, 2, 4, 2, 1}, 
                                               {2, 1, 4, 4, 1}, {4, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 2, 2, 2, 1}};
 constexpr Shape kExpandLds16[kNumShapes] = {{2, 2, 2, 2, 1}, {1, 2, 2, 2, 1}, {1, 4, 2, 2, 1}, {2, 4, 2, 2, 1},
                                             {1, 4, 2, 4, 1}, {1, 2, 2, 4, 1}, {1, 4, 2, 2, 2}, {2, 2, 2, 4, 1}};
+// BF16X6 (16 x 16 tiles of expanded rows / columns; the bank operand loads
+// half the rows of its tile, so TM / 2 (compressing) or TN / 2 (expanding)
+// rows must split evenly over the threads).
+// A k-tile here is short work for the MFMA (one 16 x 16 x 32 block per
+// piece product), so the loads run several k-tiles ahead.
+constexpr Shape kCompressSplit[kNumShapes] = {{4, 1, 2, 4, 3}, {4, 1, 2, 4, 2}, {4, 1, 2, 4, 4}, {2, 2, 2, 2, 3},
+                                              {4, 2, 2, 2, 3}, {4, 1, 2, 2, 3}, {1, 2, 2, 2, 3}, {2, 2, 2, 2, 4}};
+constexpr Shape kExpandSplit[kNumShapes] = {{2, 2, 2, 2, 3}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 4}, {1, 4, 2, 2, 3},
+                                            {2, 4, 2, 2, 3}, {2, 2, 2, 4, 3}, {2, 2, 4, 2, 3}, {1, 2, 2, 2, 3}};
 constexpr Shape kCompressGeneral = {4, 1, 2, 2, 3};
 constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
 
 // Whether the LDS-staged and buffer-addressed forms apply.  The staged forms
 // take k-tiles of one 128-byte line per row.
-int staged_ktile(Store st) { return st == Store::F32 ? 32 : 64; }
+int staged_ktile(Store st) { return storage_of(st) == Store::F32 ? 32 : 64; }
+size_t elem_bytes(Store st) { return storage_of(st) == Store::F32 ? 4 : 2; }
 // Coils that the widest k-chunk of a split touches (the staged compressing
 // form addresses the data operand from the first of them).
 int chunk_coil_span(int KD, int kchunk, int ksplit, int twoP) {
@@ -831,16 +989,16 @@ int chunk_coil_span(int KD, int kchunk, int ksplit, int twoP) {
 }
 bool compress_span_fits(size_t coil_elems, int span, size_t esz) { return (size_t)span * coil_elems * esz < kOOB; }
 bool compress_staged(const CompressArgs& a, Store st) {
-  const size_t esz = st == Store::F32 ? 4 : 2;
+  const size_t esz = elem_bytes(st);
   const int span = chunk_coil_span(a.KD, a.kchunk, a.ksplit, 2 * a.P);
-  // FP32 takes any P (odd P through the two-half data loads), 16-bit types 2P a multiple of 8
-  return (st == Store::F32 || (2 * a.P) % (int)(16 / esz) == 0) && a.kchunk % staged_ktile(st) == 0 &&
+  // FP32 data take any P (odd P through the two-half data loads), 16-bit types 2P a multiple of 8
+  return (esz == 4 || (2 * a.P) % (int)(16 / esz) == 0) && a.kchunk % staged_ktile(st) == 0 &&
          compress_span_fits((size_t)a.N * a.nt * 2, span, esz) && (size_t)a.M * a.KD * esz < kOOB;
 }
 // 2 kp is a multiple of 32, so KD (2 kp FP32, 4 kp 16-bit) is always a whole
 // number of k-tiles; the staged form needs 32-bit buffer offsets.
 bool expand_staged(const ExpandArgs& a, Store st) {
-  const size_t esz = st == Store::F32 ? 4 : 2;
+  const size_t esz = elem_bytes(st);
   return a.KD % staged_ktile(st) == 0 && (size_t)a.M * a.KD * esz < kOOB && (size_t)a.N * a.KDB * esz < kOOB;
 }
 
@@ -850,12 +1008,12 @@ template <int V, Store ST>
 void launch_compress_v(StageScope& sc, hipStream_t s, const CompressArgs& a) {
   const int rest = a.B * a.np * a.ksplit;
   if (compress_staged(a, ST)) {
-    constexpr Shape S = ST == Store::F32 ? kCompressLds[V] : kCompressLds16[V];
+    constexpr Shape S = ST == Store::F32 ? kCompressLds[V] : ST == Store::BF16X6 ? kCompressSplit[V] : kCompressLds16[V];
     constexpr int T = Geo<ST>::T;
     CompressArgs c = a;
     if (ST == Store::F32) c.M = a.K;  // complex rows of the three-multiplication form
     const dim3 grid(tiles(c.N, S.wn * S.nt * T) * tiles(c.M, S.wm * S.mt * T) * rest);
-    if constexpr (ST == Store::F32) {
+    if constexpr (storage_of(ST) == Store::F32) {
       if (a.P & 1) {
         sc.launch(k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, true>, grid, dim3(64 * S.wm * S.wn),
                            0, s, c);
@@ -865,16 +1023,17 @@ void launch_compress_v(StageScope& sc, hipStream_t s, const CompressArgs& a) {
     sc.launch(k_compress_lds<S.wm, S.wn, S.mt, S.nt, S.depth, ST, false>, grid, dim3(64 * S.wm * S.wn), 0,
                        s, c);
   } else {
+    // operands of 2 GiB or more: BF16X6 takes the FP32 general form
     constexpr Shape S = kCompressGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
-    sc.launch(k_compress<S.wm, S.wn, S.mt, S.nt, ST>, grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    sc.launch(k_compress<S.wm, S.wn, S.mt, S.nt, storage_of(ST)>, grid, dim3(64 * S.wm * S.wn), 0, s, a);
   }
 }
 template <int V, Store ST>
 void launch_expand_v(StageScope& sc, hipStream_t s, const ExpandArgs& a) {
   const int rest = a.B * a.np;
   if (expand_staged(a, ST)) {
-    constexpr Shape S = ST == Store::F32 ? kExpandLds[V] : kExpandLds16[V];
+    constexpr Shape S = ST == Store::F32 ? kExpandLds[V] : ST == Store::BF16X6 ? kExpandSplit[V] : kExpandLds16[V];
     constexpr int T = Geo<ST>::T;
     ExpandArgs e = a;
     if (ST == Store::F32) e.N = a.N / 2;  // complex columns of the three-multiplication form
@@ -883,7 +1042,7 @@ void launch_expand_v(StageScope& sc, hipStream_t s, const ExpandArgs& a) {
   } else {
     constexpr Shape S = kExpandGeneral;
     const dim3 grid(tiles(a.N, S.wn * S.nt * 16) * tiles(a.M, S.wm * S.mt * 16) * rest);
-    sc.launch(k_expand<S.wm, S.wn, S.mt, S.nt, ST>, grid, dim3(64 * S.wm * S.wn), 0, s, a);
+    sc.launch(k_expand<S.wm, S.wn, S.mt, S.nt, storage_of(ST)>, grid, dim3(64 * S.wm * S.wn), 0, s, a);
   }
 }
 
@@ -933,7 +1092,7 @@ int kblock(Store st) { return st == Store::F32 ? Geo<Store::F32>::KB : Geo<Store
 int gemm_compress(const Plan& pl, StageScope& sc, Store st, const void* in, int ncol, float2* out, int ksplit,
                   int cvar) {
   CompressArgs a;
-  if (st == Store::F32) {
+  if (storage_of(st) == Store::F32) {
     a.A = pl.Aexp;
   } else {
     const int i = bank16_index(pl, st);
@@ -958,6 +1117,7 @@ int gemm_compress(const Plan& pl, StageScope& sc, Store st, const void* in, int 
   a.split_stride = (size_t)pl.B * pl.np * pl.K * ncol;
   switch (st) {
     case Store::F32: compress_variant<Store::F32>(cvar, sc, pl.stream, a); break;
+    case Store::BF16X6: compress_variant<Store::BF16X6>(cvar, sc, pl.stream, a); break;
     case Store::BF16: compress_variant<Store::BF16>(cvar, sc, pl.stream, a); break;
     default: compress_variant<Store::F16>(cvar, sc, pl.stream, a); break;
   }
@@ -972,11 +1132,15 @@ int gemm_expand_variants() { return kNumShapes; }
 
 // Defaults: for the compressing contraction the work-group shape with the
 // tallest row tile that pads at most 1/8 of its rows (FP32: 64 or 32 of the K
-// complex rows; 16-bit: 128, 64 or 32 of the 2K real rows), else the shortest;
-// for the expanding one shape 0; and a split giving about 504 work-groups.
-int compress_shape_for_rows(int rows, bool f32) {
+// complex rows; 16-bit and BF16X6: 128, 64 or 32 of the 2K real rows), else
+// the shortest; for the expanding one shape 0; and a split giving about 504
+// work-groups.
+int compress_shape_for_rows(int rows, Store st) {
+  const bool f32 = st == Store::F32;
   const int n = f32 ? 2 : 3;
-  const int order[3] = {0, 7, 6}, tile[3] = {f32 ? 64 : 128, f32 ? 32 : 64, 32};
+  const int order16[3] = {0, 7, 6}, orderx6[3] = {0, 3, 6};
+  const int* order = st == Store::BF16X6 ? orderx6 : order16;
+  const int tile[3] = {f32 ? 64 : 128, f32 ? 32 : 64, 32};
   for (int i = 0; i < n; ++i) {
     const int padded = (rows + tile[i] - 1) / tile[i] * tile[i];
     if (8 * (padded - rows) <= padded) return order[i];
@@ -984,14 +1148,14 @@ int compress_shape_for_rows(int rows, bool f32) {
   return order[n - 1];
 }
 void default_gemm_config(Plan& pl) {
-  for (int c = 0; c < 2; ++c) {
-    const Store st = c == 0 ? Store::F32 : Store::BF16;
+  for (const Store st : {Store::F32, Store::BF16, Store::BF16X6}) {
     Plan::GemmCfg& g = pl.cfg(st);
-    const int rows = c == 0 ? pl.K : 2 * pl.K;  // complex rows in FP32, real rows in 16-bit
-    g.cvar = compress_shape_for_rows(rows, c == 0);
+    const int rows = st == Store::F32 ? pl.K : 2 * pl.K;  // complex rows in FP32, real rows otherwise
+    g.cvar = compress_shape_for_rows(rows, st);
     g.evar = 0;
-    const Shape S = c == 0 ? kCompressLds[g.cvar] : kCompressLds16[g.cvar];  // the staged forms take every even P
-    const int T = c == 0 ? 32 : 16;
+    const Shape S = st == Store::F32 ? kCompressLds[g.cvar] : st == Store::BF16X6 ? kCompressSplit[g.cvar]
+                                                                                  : kCompressLds16[g.cvar];
+    const int T = st == Store::F32 ? 32 : 16;
     const long t = (long)tiles(pl.ny, S.wn * S.nt * T) * tiles(rows, S.wm * S.mt * T) * pl.B * pl.np;
     // work-groups: measured best for E'^H E' on the 224 x 224, 32-coil slice
     // (the phase-encode stage reads one partial of Z per split)
@@ -999,10 +1163,10 @@ void default_gemm_config(Plan& pl) {
     int ks = (int)std::max<long>(1, (target + t - 1) / t);
     ks = std::min(std::min(ks, std::max(1, 2 * pl.ns / 128)), kMaxKsplit);
     // a split whose k-chunks the staged form can address (large volumes)
-    const size_t esz = c == 0 ? 4 : 2;
     while (ks < kMaxKsplit &&
            !compress_span_fits((size_t)pl.ny * pl.nt * 2,
-                               chunk_coil_span(2 * pl.ns, compress_kchunk(2 * pl.ns, ks, st), ks, 2 * pl.P), esz))
+                               chunk_coil_span(2 * pl.ns, compress_kchunk(2 * pl.ns, ks, st), ks, 2 * pl.P),
+                               elem_bytes(st)))
       ++ks;
     g.ksplit = ks;
   }
@@ -1021,7 +1185,7 @@ int launch_compress_data(const Plan& pl, const float2* ksp, float2* out) {
 int launch_group_expand(const Plan& pl, Store st) {
   StageScope sc(pl, GPJC_STAGE_GROUP_EXPAND, true);
   ExpandArgs a;
-  if (st == Store::F32) {
+  if (storage_of(st) == Store::F32) {
     a.Zt = pl.Zt;
     a.AH = pl.AH;
   } else {
@@ -1036,8 +1200,8 @@ int launch_group_expand(const Plan& pl, Store st) {
   a.M = pl.ny;
   a.N = 2 * pl.ns;
   a.KDB = 2 * pl.Kp;
-  a.KD = st == Store::F32 ? 2 * pl.Kp : 4 * pl.Kp;
-  a.kwrap = st == Store::F32 ? 0 : 2 * pl.Kp;
+  a.KD = storage_of(st) == Store::F32 ? 2 * pl.Kp : 4 * pl.Kp;
+  a.kwrap = storage_of(st) == Store::F32 ? 0 : 2 * pl.Kp;
   a.nc = pl.nc;
   a.nt = pl.nt;
   a.P = pl.P;
@@ -1045,6 +1209,7 @@ int launch_group_expand(const Plan& pl, Store st) {
   a.B = pl.B;
   switch (st) {
     case Store::F32: expand_variant<Store::F32>(pl.cfg(st).evar, sc, pl.stream, a); break;
+    case Store::BF16X6: expand_variant<Store::BF16X6>(pl.cfg(st).evar, sc, pl.stream, a); break;
     case Store::BF16: expand_variant<Store::BF16>(pl.cfg(st).evar, sc, pl.stream, a); break;
     default: expand_variant<Store::F16>(pl.cfg(st).evar, sc, pl.stream, a); break;
   }

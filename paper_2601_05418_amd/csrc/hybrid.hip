@@ -186,22 +186,23 @@ __global__ void k_flag_clear(int* __restrict__ flag) {
 }
 
 template <Store ST>
-int lsqr_u(const Plan& pl, bool start, int ms, int R) {
+int lsqr_u(const Plan& pl, bool start, int ms, int R, int ksplit) {
   StageScope scope(pl, GPJC_STAGE_SOLVER);
   const int nsets = pl.B * ms;
   const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
   void* zt = ST == Store::F32 ? static_cast<void*>(pl.Zt) : static_cast<void*>(pl.Zt16);
   hipLaunchKernelGGL((k_lsqr_u<ST>), dim3(nsets), dim3(256), 0, pl.stream, start ? 1 : 0, pl.Zt, pl.Zp,
-                     pl.cfg(ST).ksplit, zs, pl.vd, zt, pl.red, nsets, pl.np, pl.K, pl.Kp, pl.ny, ms, R);
+                     ksplit, zs, pl.vd, zt, pl.red, nsets, pl.np, pl.K, pl.Kp, pl.ny, ms, R);
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
 }
 
 int lsqr_u_st(const Plan& pl, Store st, bool start, int ms, int R) {
-  switch (st) {
-    case Store::F32: return lsqr_u<Store::F32>(pl, start, ms, R);
-    case Store::BF16: return lsqr_u<Store::BF16>(pl, start, ms, R);
-    default: return lsqr_u<Store::F16>(pl, start, ms, R);
+  const int ks = pl.cfg(st).ksplit;  // partials of Z the compressing contraction of st wrote
+  switch (storage_of(st)) {
+    case Store::F32: return lsqr_u<Store::F32>(pl, start, ms, R, ks);
+    case Store::BF16: return lsqr_u<Store::BF16>(pl, start, ms, R, ks);
+    default: return lsqr_u<Store::F16>(pl, start, ms, R, ks);
   }
 }
 

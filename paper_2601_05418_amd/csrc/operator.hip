@@ -986,14 +986,14 @@ template <Store ST>
 struct PeNormal {
   template <int NY>
   struct L {
-    static int run(const Plan& pl) {
+    static int run(const Plan& pl, int ksplit) {
       StageScope sc(pl, GPJC_STAGE_PE_NORMAL, true);
       const int nlines = pl.B * pl.np * pl.K;
       if constexpr (Split<NY>::ok) {
         constexpr int lines = PeNormal2Geo<NY>::L;
         const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
         sc.launch(k_pe_normal2<NY, ST>, dim3((nlines + lines - 1) / lines), dim3(256), 0, pl.stream,
-                  (const float2*)pl.Zp, pl.cfg(ST).ksplit, zs, zt_for(pl, ST), (const float*)pl.maskf, nlines, pl.K,
+                  (const float2*)pl.Zp, ksplit, zs, zt_for(pl, ST), (const float*)pl.maskf, nlines, pl.K,
                   pl.Kp, (const float2*)pl.tw_y);
         GPJC_HIP(hipGetLastError());
         return GPJC_OK;
@@ -1001,7 +1001,7 @@ struct PeNormal {
       const size_t lds = (size_t)(NY + 2 * pl.f3_lpb * fline(NY)) * sizeof(float2);
       const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
       sc.launch(k_pe_normal<NY, ST>, dim3((nlines + pl.f3_lpb - 1) / pl.f3_lpb), dim3(256), lds, pl.stream,
-                (const float2*)pl.Zp, pl.cfg(ST).ksplit, zs, zt_for(pl, ST), (const float*)pl.maskf, nlines,
+                (const float2*)pl.Zp, ksplit, zs, zt_for(pl, ST), (const float*)pl.maskf, nlines,
                 pl.f3_lpb, pl.K, pl.Kp, (const float2*)pl.tw_y);
       GPJC_HIP(hipGetLastError());
       return GPJC_OK;
@@ -1036,7 +1036,7 @@ struct PeCols {
 };
 
 int launch_readout_fwd(const Plan& pl, const float2* img, Store st) {
-  switch (st) {
+  switch (storage_of(st)) {
     case Store::F32: return dispatch_n<ReadoutFwd<Store::F32>::L>(pl.nx, pl, img);
     case Store::BF16: return dispatch_n<ReadoutFwd<Store::BF16>::L>(pl.nx, pl, img);
     default: return dispatch_n<ReadoutFwd<Store::F16>::L>(pl.nx, pl, img);
@@ -1044,7 +1044,7 @@ int launch_readout_fwd(const Plan& pl, const float2* img, Store st) {
 }
 
 int launch_readout_adj(const Plan& pl, Store st) {
-  switch (st) {
+  switch (storage_of(st)) {
     case Store::F32: return dispatch_n<ReadoutAdj<Store::F32>::L>(pl.nx, pl);
     case Store::BF16: return dispatch_n<ReadoutAdj<Store::BF16>::L>(pl.nx, pl);
     default: return dispatch_n<ReadoutAdj<Store::F16>::L>(pl.nx, pl);
@@ -1060,13 +1060,15 @@ int launch_combine(const Plan& pl, float2* out) {
   return GPJC_OK;
 }
 
+// The split st's compressing contraction used is the number of partials of Z
+// the phase-encode stage sums.
 int launch_pe_fwd(const Plan& pl, float2* out, Store st) {
-  if (pl.nz > 1) return launch_pe3_fwd(pl, out);
+  if (pl.nz > 1) return launch_pe3_fwd(pl, out, st);
   return dispatch_n<PeFwd>(pl.ny, pl, out, pl.cfg(st).ksplit);
 }
 int launch_pe_adj(const Plan& pl, const float2* in, Store st) {
   if (pl.nz > 1) return launch_pe3_adj(pl, in, st);
-  switch (st) {
+  switch (storage_of(st)) {
     case Store::F32: return dispatch_n<PeAdj<Store::F32>::L>(pl.ny, pl, in);
     case Store::BF16: return dispatch_n<PeAdj<Store::BF16>::L>(pl.ny, pl, in);
     default: return dispatch_n<PeAdj<Store::F16>::L>(pl.ny, pl, in);
@@ -1074,10 +1076,11 @@ int launch_pe_adj(const Plan& pl, const float2* in, Store st) {
 }
 int launch_pe_normal(const Plan& pl, Store st) {
   if (pl.nz > 1) return launch_pe3_normal(pl, st);
-  switch (st) {
-    case Store::F32: return dispatch_n<PeNormal<Store::F32>::L>(pl.ny, pl);
-    case Store::BF16: return dispatch_n<PeNormal<Store::BF16>::L>(pl.ny, pl);
-    default: return dispatch_n<PeNormal<Store::F16>::L>(pl.ny, pl);
+  const int ks = pl.cfg(st).ksplit;
+  switch (storage_of(st)) {
+    case Store::F32: return dispatch_n<PeNormal<Store::F32>::L>(pl.ny, pl, ks);
+    case Store::BF16: return dispatch_n<PeNormal<Store::BF16>::L>(pl.ny, pl, ks);
+    default: return dispatch_n<PeNormal<Store::F16>::L>(pl.ny, pl, ks);
   }
 }
 

@@ -168,11 +168,11 @@ __global__ __launch_bounds__(256) void k3_scatter(const float2* __restrict__ in,
 
 template <int N>
 struct YFwd {
-  static int run(const Plan& pl, size_t zstride) {
+  static int run(const Plan& pl, int ksplit, size_t zstride) {
     constexpr int L = lines3<N>();
     const int nlines = pl.B * pl.np * pl.K * pl.nz;
-    hipLaunchKernelGGL(k3_y_fwd<N>, dim3((nlines + L - 1) / L), dim3(256), 0, pl.stream, pl.Zp, pl.cfg(Store::F32).ksplit,
-                       zstride, pl.T3, nlines, pl.tw_y3);
+    hipLaunchKernelGGL(k3_y_fwd<N>, dim3((nlines + L - 1) / L), dim3(256), 0, pl.stream, pl.Zp, ksplit, zstride,
+                       pl.T3, nlines, pl.tw_y3);
     return GPJC_OK;
   }
 };
@@ -212,7 +212,7 @@ int dispatch3(int n, Args&&... args) {
 }
 
 int y_inv(const Plan& pl, Store st) {
-  switch (st) {
+  switch (storage_of(st)) {
     case Store::F32: return dispatch3<YInv<Store::F32>::L>(pl.ny2, pl);
     case Store::BF16: return dispatch3<YInv<Store::BF16>::L>(pl.ny2, pl);
     default: return dispatch3<YInv<Store::F16>::L>(pl.ny2, pl);
@@ -221,10 +221,10 @@ int y_inv(const Plan& pl, Store st) {
 
 }  // namespace
 
-int launch_pe3_fwd(const Plan& pl, float2* out) {
+int launch_pe3_fwd(const Plan& pl, float2* out, Store st) {
   StageScope sc(pl, GPJC_STAGE_PE_FWD);
   const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
-  GPJC_TRY(dispatch3<YFwd>(pl.ny2, pl, zs));
+  GPJC_TRY(dispatch3<YFwd>(pl.ny2, pl, pl.cfg(st).ksplit, zs));
   GPJC_TRY(dispatch3<ZPass>(pl.nz, pl, 0));
   const size_t nplanes = (size_t)pl.B * pl.np * pl.K;
   hipLaunchKernelGGL(k3_gather, dim3(2048), dim3(256), 0, pl.stream, pl.T3, pl.pts3, pl.ms, pl.ny, nplanes, out);
@@ -245,7 +245,7 @@ int launch_pe3_adj(const Plan& pl, const float2* in, Store st) {
 int launch_pe3_normal(const Plan& pl, Store st) {
   StageScope sc(pl, GPJC_STAGE_PE_NORMAL);
   const size_t zs = (size_t)pl.B * pl.np * pl.K * pl.ny;
-  GPJC_TRY(dispatch3<YFwd>(pl.ny2, pl, zs));
+  GPJC_TRY(dispatch3<YFwd>(pl.ny2, pl, pl.cfg(st).ksplit, zs));
   GPJC_TRY(dispatch3<ZPass>(pl.nz, pl, 1));
   GPJC_TRY(y_inv(pl, st));
   GPJC_HIP(hipGetLastError());

@@ -29,8 +29,14 @@ int fail(int code, const std::string& msg);
     if (s_ != GPJC_OK) return s_; \
   } while (0)
 
-// Reduced-precision storage types.
-enum class Store { F32 = 0, BF16 = 1, F16 = 2 };
+// Arithmetic of a precision: FP32, the 16-bit storage types, and BF16X6 (FP32
+// storage everywhere; the group contractions run on the BF16 MFMA with every
+// FP32 operand split into three BF16 pieces).
+enum class Store { F32 = 0, BF16 = 1, F16 = 2, BF16X6 = 3 };
+// The type hybrid data, Z and the phase-encode stage are stored in.
+constexpr Store storage_of(Store st) { return st == Store::BF16X6 ? Store::F32 : st; }
+// Whether a precision stores 16-bit values (and so takes FP32 refinement in CG).
+constexpr bool is_16bit(Store st) { return st == Store::BF16 || st == Store::F16; }
 
 // HIP-event timing of stage launches (enabled on request).
 struct Timing {
@@ -61,14 +67,16 @@ struct Plan {
   int f1h_cpc = 1;          // coils per chunk
   int f3_lpb = 1;           // phase-encode lines per workgroup
   int f3_tb = 1;            // readout columns per uncompressed phase-encode workgroup
-  // group-contraction configuration per precision class ([0] FP32, [1] BF16 / FP16):
-  // tile shape of the compressing and expanding contractions, split of the compressing one
+  // group-contraction configuration per precision class ([0] FP32, [1] BF16 / FP16,
+  // [2] BF16X6): tile shape of the compressing and expanding contractions, split of
+  // the compressing one (the phase-encode stage sums that many partials of Z)
   struct GemmCfg {
     int cvar = 0, evar = 0, ksplit = 1;
   };
-  GemmCfg gemm[2];
-  const GemmCfg& cfg(Store st) const { return gemm[st == Store::F32 ? 0 : 1]; }
-  GemmCfg& cfg(Store st) { return gemm[st == Store::F32 ? 0 : 1]; }
+  GemmCfg gemm[3];
+  static int cfg_index(Store st) { return st == Store::F32 ? 0 : st == Store::BF16X6 ? 2 : 1; }
+  const GemmCfg& cfg(Store st) const { return gemm[cfg_index(st)]; }
+  GemmCfg& cfg(Store st) { return gemm[cfg_index(st)]; }
   long config_gen = 0;      // bumped whenever the launch configuration changes
 
   // 3D volumes (gpjc_plan_create_3d): rows are (z, y) pairs, ny = nz * ny2;
@@ -273,7 +281,7 @@ int run_gd_step_backward(const Plan& pl, Store st, const float2* g, const float*
 int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
 
 // ---- phase-encode stage of 3D volumes (pe3d.hip) ----
-int launch_pe3_fwd(const Plan& pl, float2* out);
+int launch_pe3_fwd(const Plan& pl, float2* out, Store st);
 int launch_pe3_adj(const Plan& pl, const float2* in, Store st);
 int launch_pe3_normal(const Plan& pl, Store st);
 int setup_pe3(Plan& pl, const uint8_t* mask2);

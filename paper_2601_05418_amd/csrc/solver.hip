@@ -330,11 +330,11 @@ int cg_finish(const Plan& pl, float2* x, int iters, double* h_resid, int* h_flag
 }
 
 bool cg_refresh_at(int it, int iters, int refine_every, Store st) {
-  return refine_every > 0 && st != Store::F32 && (it + 1) % refine_every == 0 && it + 1 < iters;
+  return refine_every > 0 && is_16bit(st) && (it + 1) % refine_every == 0 && it + 1 < iters;
 }
 
 int run_cg(Plan& pl, Store st, const float2* y, float2* x, int iters, int refine_every, double* h_resid) {
-  const bool refine = refine_every > 0 && st != Store::F32;
+  const bool refine = refine_every > 0 && is_16bit(st);
   GPJC_TRY(cg_setup(pl, st, refine, y, x));
   for (int it = 0; it < iters; ++it) GPJC_TRY(cg_iteration(pl, st, cg_refresh_at(it, iters, refine_every, st)));
   int flag = 0;

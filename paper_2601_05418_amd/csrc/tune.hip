@@ -33,7 +33,9 @@ std::mutex g_mu;
 std::map<std::string, Choice> g_cache;
 std::set<std::string> g_loaded;
 
-const char* prec_name(Store st) { return st == Store::F32 ? "fp32" : st == Store::BF16 ? "bf16" : "fp16"; }
+const char* prec_name(Store st) {
+  return st == Store::F32 ? "fp32" : st == Store::BF16 ? "bf16" : st == Store::F16 ? "fp16" : "bf16x6";
+}
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 int pow2_up(int v) {

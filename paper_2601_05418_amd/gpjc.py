@@ -22,8 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpjc.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "gpjc.h")
 
-FP32, BF16, FP16 = 0, 1, 2
-PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
+FP32, BF16, FP16, BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "bf16x6": BF16X6}
 
 STAGES = ("readout_fwd", "group_compress", "pe_normal", "pe_fwd", "pe_adj", "group_expand", "readout_adj",
           "pe_cols", "combine", "solver", "explicit_fwd", "explicit_adj")

@@ -109,6 +109,26 @@ def test_volume_reduced_precision(gpu_lib, prec, bound):
     assert max(ef, ea, en) <= bound
 
 
+def test_volume_phase_encode_sums_its_precisions_split(gpu_lib):
+    """The 2D phase-encode stage sums as many partials of Z as the
+    compressing contraction of the call's precision wrote: BF16 with a split
+    other than FP32's, then FP32 again, each within its bound."""
+    v = CASES["small"]()
+    g = v.geom
+    a, _ = ov.calibrate(v.coils, v.psf, g.os, g.patch_len, g.patch_group, g.n_groups, g.k)
+    plan = plan_with(v, a)
+    fwd, adj, nrm = ops_for(v, a)
+    f32 = plan.gemm_config("fp32")["ksplit"]
+    c16 = plan.gemm_config("bf16")
+    plan.set_gemm_config(c16["compress"], c16["expand"], 3 if f32 != 3 else 2, prec="bf16")
+    x = H.round64(v.image)
+    e16 = H.rel_l2(host(plan.normal(dev(x[None]), prec="bf16"))[0], nrm(x))
+    ef16 = H.rel_l2(host(plan.forward(dev(x[None]), prec="bf16"))[0], fwd(x))
+    print(f"bf16 normal {e16:.2e}, forward {ef16:.2e}", flush=True)
+    assert max(e16, ef16) <= 2e-3
+    check(host(plan.normal(dev(x[None])))[0], nrm(x))
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_volume_calibration(gpu_lib, case):
     v = CASES[case]()
