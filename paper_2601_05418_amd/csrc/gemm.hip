@@ -963,12 +963,13 @@ constexpr Shape kExpandLds16[kNumShapes] = {{2, 2, 2, 2, 1}, {1, 2, 2, 2, 1}, {1
                                             {1, 4, 2, 4, 1}, {1, 2, 2, 4, 1}, {1, 4, 2, 2, 2}, {2, 2, 2, 4, 1}};
 // BF16X6 (16 x 16 tiles of expanded rows / columns; the bank operand loads
 // half the rows of its tile, so TM / 2 (compressing) or TN / 2 (expanding)
-// rows must split evenly over the threads).
-// A k-tile here is short work for the MFMA (one 16 x 16 x 32 block per
-// piece product), so the loads run several k-tiles ahead.
-constexpr Shape kCompressSplit[kNumShapes] = {{4, 1, 2, 4, 3}, {4, 1, 2, 4, 2}, {4, 1, 2, 4, 4}, {2, 2, 2, 2, 3},
+// rows must split evenly over the threads).  A k-tile is short work for the
+// MFMA here (six 16 x 16 x 32 products per tile pair), so the loads run two
+// to four k-tiles ahead.  Index 0 of each: measured best on the 224 x 224,
+// 32-coil slice (with a split of 3 for the compressing one).
+constexpr Shape kCompressSplit[kNumShapes] = {{4, 1, 2, 4, 2}, {4, 1, 2, 4, 3}, {4, 1, 2, 4, 4}, {2, 2, 2, 2, 3},
                                               {4, 2, 2, 2, 3}, {4, 1, 2, 2, 3}, {1, 2, 2, 2, 3}, {2, 2, 2, 2, 4}};
-constexpr Shape kExpandSplit[kNumShapes] = {{2, 2, 2, 2, 3}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 4}, {1, 4, 2, 2, 3},
+constexpr Shape kExpandSplit[kNumShapes] = {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 3}, {2, 2, 2, 2, 4}, {1, 4, 2, 2, 3},
                                             {2, 4, 2, 2, 3}, {2, 2, 2, 4, 3}, {2, 2, 4, 2, 3}, {1, 2, 2, 2, 3}};
 constexpr Shape kCompressGeneral = {4, 1, 2, 2, 3};
 constexpr Shape kExpandGeneral = {1, 4, 2, 2, 3};
