@@ -310,8 +310,8 @@ int gpjc_stage_timing_select(gpjc_plan* plan, unsigned stage_mask);
 int gpjc_stage_times(gpjc_plan* plan, double* h_ms, int* h_launches);
 
 /* Work-group tile shape of the two group contractions and the contraction
- * split of the compressing one (1..8), for one precision class: FP32, or the
- * two 16-bit types together (BF16 and FP16 share one setting).  Variant
+ * split of the compressing one (1..8), for one precision class: FP32, the
+ * two 16-bit types together (BF16 and FP16 share one setting), or BF16X6.  Variant
  * numbers index per-class tables of built shapes.  The defaults come from
  * the plan's sizes; gpjc_autotune times the variants and installs the
  * fastest.  Changes only speed, never results beyond FP32 summation order. */
