@@ -224,3 +224,35 @@ def test_autotune(gpu_lib, tmp_path):
     ops = H.oracle_ops(sl, a)
     x = H.round64(H.crandn(np.random.default_rng(36), (1, sl.geom.ny, sl.geom.nx)))
     check(host(plan.normal(dev(x), prec=X6))[0], ops["nrm"](x[0]))
+
+
+def test_plans_without_contractions_run_their_fp32_path(gpu_lib):
+    """The uncompressed operator and the explicit model of a modulation map
+    have no group contraction: BF16X6 runs their FP32 kernels, bit for bit."""
+    from tests.test_gpu_explicit import CASES as MAP_CASES
+    from tests.test_gpu_explicit import plan_with as map_plan
+    sl = H.rounded_slice(H.CASES["rect"]())
+    unc = gpjc.Plan.from_slice(sl, compressed=False)
+    msl = MAP_CASES["small"]()
+    mp = map_plan(msl, H.random_bank(msl.geom, seed=2))
+    for plan, g in ((unc, sl.geom), (mp, msl.geom)):
+        x = dev(H.round64(H.crandn(np.random.default_rng(37), (1, g.ny, g.nx))))
+        assert np.array_equal(host(plan.normal(x, prec=X6)), host(plan.normal(x)))
+        assert np.array_equal(host(plan.forward(x, prec=X6)), host(plan.forward(x)))
+
+
+def test_lsqr_sums_its_own_split(gpu_lib):
+    """Algorithm #1 with BF16X6 column stages, the split set apart from
+    FP32's: same-schedule LSQR against the oracle."""
+    from oracle import hybrid as oh
+    from tests.test_gpu_hybrid import wave_case
+    sl, g, a, e_c, s, plan = wave_case("rect", 4)
+    c = plan.gemm_config(X6)
+    ks = 3 if plan.gemm_config("fp32")["ksplit"] != 3 else 2
+    plan.set_gemm_config(c["compress"], c["expand"], ks, prec=X6)
+    xg, hg = plan.recon_lsqr(dev(s[None]), 15, prec=X6, want_resid=True)
+    xo, ho = oh.recon(s, e_c, g.mask, 4, 15)
+    e = osv.nrmse(host(xg)[0], xo)
+    print(f"LSQR-15 BF16X6 (split {ks}): NRMSE vs oracle {e:.2e}", flush=True)
+    assert e <= H.NRMSE_RECON
+    assert np.allclose(hg, ho, rtol=1e-4)
