@@ -256,3 +256,27 @@ def test_lsqr_sums_its_own_split(gpu_lib):
     print(f"LSQR-15 BF16X6 (split {ks}): NRMSE vs oracle {e:.2e}", flush=True)
     assert e <= H.NRMSE_RECON
     assert np.allclose(hg, ho, rtol=1e-4)
+
+
+def test_unrolled_network_matches_fp32(gpu_lib):
+    """The unrolled network (10 checkpointed GD steps, 2 images) with BF16X6
+    contractions: loss and gradients agree with the FP32 network to the FP32
+    bars (the two differ only by rounding inside the contractions)."""
+    from paper_2601_05418_amd import autograd as ga
+    from tests.test_gpu_autograd import setup
+    sl, plan, ops, y, x0, t, lip = setup(seed=6)
+    res = {}
+    for prec in ("fp32", X6):
+        torch.manual_seed(0)
+        net = ga.UnrolledGD(plan, steps=10, alpha0=0.8 / lip, checkpoint_every=2, prec=prec)
+        x = dev(x0).requires_grad_(True)
+        loss = 0.5 * (net(dev(y), x) - dev(t)).abs().pow(2).sum()
+        loss.backward()
+        res[prec] = (float(loss.detach()), x.grad.detach().cpu().numpy().astype(np.complex128),
+                     net.alpha.grad.detach().cpu().numpy().astype(np.float64))
+    (l0, gx0, ga0), (l1, gx1, ga1) = res["fp32"], res[X6]
+    print(f"loss {l0:.6e} / {l1:.6e}; x-grad rel {H.rel_l2(gx1, gx0):.2e}; "
+          f"alpha-grad rel {np.linalg.norm(ga1 - ga0) / np.linalg.norm(ga0):.2e}", flush=True)
+    assert abs(l1 - l0) <= 1e-5 * abs(l0)
+    assert H.rel_l2(gx1, gx0) <= 1e-5
+    assert np.linalg.norm(ga1 - ga0) <= 1e-5 * np.linalg.norm(ga0)
