@@ -120,6 +120,60 @@ __global__ __launch_bounds__(256) void k_explicit_fwd(const float2* __restrict__
   }
 }
 
+// Forward for several images at once: G lanes per row, so a wave takes 64 / G
+// rows per step; lane g reads the 16-byte pairs g, g + G, ... of its row (G
+// consecutive pairs per load instruction and row), and the BC image rows of
+// column y sit in LDS, where the row groups of a wave read the same pairs.
+// Each row's sums are reduced over its G lanes in a fixed butterfly order: the
+// cross-lane work per row is log2(G) steps instead of the six of a whole-wave
+// reduction, for 2 BC values each.
+template <int BC, int G>
+__global__ __launch_bounds__(256) void k_explicit_fwd_g(const float2* __restrict__ Ec, const float2* __restrict__ img,
+                                                        int b0, int B, int nx, int ny, int rows, int rpw,
+                                                        float2* __restrict__ Z) {
+  extern __shared__ floatx4 xs[];  // [BC][nx / 2] pairs of image values
+  constexpr int RW = 64 / G;       // rows per wave and step
+  const int y = blockIdx.y, r_beg = blockIdx.x * rpw, r_end = min(rows, r_beg + rpw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane % G, rl = lane / G;
+  const int npair = nx / 2;
+  for (int i = tid; i < BC * npair; i += 256) {
+    const int b = i / npair, q = i - b * npair;
+    xs[i] = b0 + b < B ? reinterpret_cast<const floatx4*>(img + ((size_t)(b0 + b) * ny + y) * nx)[q]
+                       : floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  __syncthreads();
+  for (int r0 = r_beg + wave * RW; r0 < r_end; r0 += 4 * RW) {
+    const int r = r0 + rl;
+    // rows past the end read the last row and are not written
+    const floatx4* er = reinterpret_cast<const floatx4*>(Ec + ((size_t)y * rows + min(r, r_end - 1)) * nx);
+    float ar[BC], ai[BC];
+#pragma unroll
+    for (int b = 0; b < BC; ++b) ar[b] = ai[b] = 0.f;
+#pragma unroll 4
+    for (int q = g; q < npair; q += G) {
+      const floatx4 m = er[q];
+#pragma unroll
+      for (int b = 0; b < BC; ++b) {
+        const floatx4 v = xs[b * npair + q];
+        ar[b] += m[0] * v[0] - m[1] * v[1] + m[2] * v[2] - m[3] * v[3];
+        ai[b] += m[0] * v[1] + m[1] * v[0] + m[2] * v[3] + m[3] * v[2];
+      }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int b = 0; b < BC; ++b) {
+        ar[b] += __shfl_xor(ar[b], off, 64);
+        ai[b] += __shfl_xor(ai[b], off, 64);
+      }
+    if (g == 0 && r < r_end)
+#pragma unroll
+      for (int b = 0; b < BC; ++b)
+        if (b0 + b < B) Z[((size_t)(b0 + b) * rows + r) * ny + y] = make_float2(ar[b], ai[b]);
+  }
+}
+
 constexpr int kAdjRows = 512;  // rows per chunk of the adjoint (LDS staging of Z)
 
 // Adjoint: work-group (chunk c of the rows, column y).  A thread owns one x
@@ -191,6 +245,90 @@ __global__ __launch_bounds__(256) void k_explicit_adj(const float2* __restrict__
   }
 }
 
+// Adjoint for several images at once: as k_explicit_adj, but a thread owns a
+// pair of neighbouring x (16-byte loads of E') and the chunk's Z values sit in
+// LDS row-major, [row][image], so one 16-byte LDS read gives two images of a
+// row: per row and thread, one load, BC / 2 LDS reads and 8 BC multiply-adds.
+template <int BC>
+__global__ __launch_bounds__(256) void k_explicit_adj_p(const float2* __restrict__ Ec, const float2* __restrict__ Zt,
+                                                        int b0, int B, int nx, int ny, int np, int K, int kp, int rc,
+                                                        float2* __restrict__ part) {
+  static_assert(BC % 2 == 0, "images in pairs");
+  const int c = blockIdx.x, y = blockIdx.y;
+  const int rows = np * K;
+  const int r_beg = c * rc, nr = max(0, min(rows, r_beg + rc) - r_beg);
+  __shared__ floatx4 zs[kAdjRows * BC / 2];  // [row][image pair]
+  __shared__ floatx4 red[256 * BC / 2];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < BC * nr; i += 256) {
+    const int rr = i / BC, b = i - rr * BC;
+    const int r = r_beg + rr, p = r / K, k = r - p * K;
+    const float2 z = b0 + b < B ? Zt[(((size_t)(b0 + b) * np + p) * ny + y) * kp + k] : make_float2(0.f, 0.f);
+    reinterpret_cast<float2*>(zs)[rr * BC + b] = z;
+  }
+  __syncthreads();
+  const int npair = nx / 2;
+  const int nsub = npair < 256 ? 256 / npair : 1;
+  const int sub = tid / (npair < 256 ? npair : 256);
+  const size_t nimg = (size_t)ny * nx;
+  for (int q0 = 0; q0 < npair; q0 += 256) {
+    const int q = q0 + (npair < 256 ? tid % npair : tid);
+    const bool act = sub < nsub && q < npair;
+    floatx4 acc[BC];  // per image: (x0 re, x0 im, x1 re, x1 im)
+#pragma unroll
+    for (int b = 0; b < BC; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (act) {
+      const floatx4* col = reinterpret_cast<const floatx4*>(Ec + ((size_t)y * rows + r_beg) * nx) + q;
+      for (int r0 = sub; r0 < nr; r0 += 8 * nsub) {
+        floatx4 e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = col[(size_t)min(r0 + u * nsub, nr - 1) * npair];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int rr = r0 + u * nsub;
+          if (rr < nr) {
+#pragma unroll
+            for (int h = 0; h < BC / 2; ++h) {
+              const floatx4 z = zs[rr * (BC / 2) + h];  // images 2h and 2h + 1
+#pragma unroll
+              for (int w = 0; w < 2; ++w) {
+                const float zr = z[2 * w], zi = z[2 * w + 1];
+                floatx4& a = acc[2 * h + w];
+                a[0] += e[u][0] * zr + e[u][1] * zi;  // conj(e) z, first x
+                a[1] += e[u][0] * zi - e[u][1] * zr;
+                a[2] += e[u][2] * zr + e[u][3] * zi;  // second x
+                a[3] += e[u][2] * zi - e[u][3] * zr;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (nsub > 1) {
+      for (int h = 0; h < BC / 2; ++h) {
+        __syncthreads();
+        red[tid * 2] = acc[2 * h];
+        red[tid * 2 + 1] = acc[2 * h + 1];
+        __syncthreads();
+        if (sub == 0 && act)
+          for (int s2 = 1; s2 < nsub; ++s2) {
+            const floatx4 u0 = red[(s2 * npair + tid) * 2], u1 = red[(s2 * npair + tid) * 2 + 1];
+#pragma unroll
+            for (int e2 = 0; e2 < 4; ++e2) {
+              acc[2 * h][e2] += u0[e2];
+              acc[2 * h + 1][e2] += u1[e2];
+            }
+          }
+      }
+    }
+    if (sub == 0 && act)
+#pragma unroll
+      for (int b = 0; b < BC; ++b)
+        if (b0 + b < B)
+          reinterpret_cast<floatx4*>(part + ((size_t)c * B + b0 + b) * nimg + (size_t)y * nx)[q] = acc[b];
+  }
+}
+
 template <int BC>
 void launch_fwd_bc(const Plan& pl, const float2* img, int b0, int xb, dim3 grid, int rpw) {
   const int rows = pl.np * pl.K;
@@ -203,8 +341,12 @@ void launch_fwd_bc(const Plan& pl, const float2* img, int b0, int xb, dim3 grid,
 
 }  // namespace
 
-// Rows of the forward per work-group (16 per wave).
+// Rows of the forward per work-group: 16 per wave for one or two images; 64
+// per wave for more (k_explicit_fwd_g, which stages the image rows once per
+// work-group).
 constexpr int kFwdRowsPerWg = 64;
+constexpr int kFwdRowsPerWgMulti = 256;
+constexpr int kFwdLanesPerRow = 8;
 
 int explicit_chunks(int rows, int ny, int B) {
   const int bp = (B + 7) / 8;
@@ -229,12 +371,20 @@ int launch_explicit_fwd(const Plan& pl, const float2* img) {
   const int xb = (pl.nx / 2 + 63) / 64;  // 16-byte pairs per lane
   if (xb > 4) return fail(GPJC_E_UNSUPPORTED, "explicit model: nx above 512");
   const dim3 grid((rows + kFwdRowsPerWg - 1) / kFwdRowsPerWg, pl.ny);
+  const dim3 grid_m((rows + kFwdRowsPerWgMulti - 1) / kFwdRowsPerWgMulti, pl.ny);
   for (int b0 = 0; b0 < pl.B; b0 += 8) {
     const int left = pl.B - b0;
-    if (left == 1) launch_fwd_bc<1>(pl, img, b0, xb, grid, kFwdRowsPerWg);
-    else if (left == 2) launch_fwd_bc<2>(pl, img, b0, xb, grid, kFwdRowsPerWg);
-    else if (left <= 4) launch_fwd_bc<4>(pl, img, b0, xb, grid, kFwdRowsPerWg);
-    else launch_fwd_bc<8>(pl, img, b0, xb, grid, kFwdRowsPerWg);
+    if (left == 1) {
+      launch_fwd_bc<1>(pl, img, b0, xb, grid, kFwdRowsPerWg);
+    } else if (left == 2) {
+      launch_fwd_bc<2>(pl, img, b0, xb, grid, kFwdRowsPerWg);
+    } else if (left <= 4) {
+      hipLaunchKernelGGL((k_explicit_fwd_g<4, kFwdLanesPerRow>), grid_m, dim3(256), 4 * (pl.nx / 2) * sizeof(floatx4),
+                         pl.stream, pl.Ec, img, b0, pl.B, pl.nx, pl.ny, rows, kFwdRowsPerWgMulti, pl.Zp);
+    } else {
+      hipLaunchKernelGGL((k_explicit_fwd_g<8, kFwdLanesPerRow>), grid_m, dim3(256), 8 * (pl.nx / 2) * sizeof(floatx4),
+                         pl.stream, pl.Ec, img, b0, pl.B, pl.nx, pl.ny, rows, kFwdRowsPerWgMulti, pl.Zp);
+    }
   }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
@@ -256,11 +406,11 @@ int launch_explicit_adj(const Plan& pl) {
       hipLaunchKernelGGL((k_explicit_adj<2>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny, pl.np,
                          pl.K, pl.Kp, rc, pl.part);
     else if (left <= 4)
-      hipLaunchKernelGGL((k_explicit_adj<4>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny, pl.np,
-                         pl.K, pl.Kp, rc, pl.part);
+      hipLaunchKernelGGL((k_explicit_adj_p<4>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny,
+                         pl.np, pl.K, pl.Kp, rc, pl.part);
     else
-      hipLaunchKernelGGL((k_explicit_adj<8>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny, pl.np,
-                         pl.K, pl.Kp, rc, pl.part);
+      hipLaunchKernelGGL((k_explicit_adj_p<8>), grid, dim3(256), 0, pl.stream, pl.Ec, pl.Zt, b0, pl.B, pl.nx, pl.ny,
+                         pl.np, pl.K, pl.Kp, rc, pl.part);
   }
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
