@@ -53,11 +53,36 @@ __global__ __launch_bounds__(256) void k3_y_fwd(const float2* __restrict__ Zp, i
   const int tid = threadIdx.x;
   for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
   const int l0 = blockIdx.x * L, nl = min(L, nlines - l0);
-  for (int i = tid; i < nl * NY; i += 256) {
-    const int li = i / NY, y = i - li * NY;
-    float2 v = make_float2(0.f, 0.f);
-    for (int s = 0; s < ksplit; ++s) v = cadd(v, Zp[(size_t)s * zstride + (size_t)l0 * NY + i]);
-    A[li * LS + fpad(y)] = (y & 1) ? make_float2(-v.x, -v.y) : v;
+  // The partials are summed in order, and the loads of kSum3 of them for
+  // kIt3 elements are issued before any is added.
+  constexpr int kIt3 = 4, kSum3 = 3;
+  const int nel = nl * NY;
+  for (int i0 = 0; i0 < nel; i0 += kIt3 * 256) {
+    float2 a[kIt3];
+#pragma unroll
+    for (int it = 0; it < kIt3; ++it) a[it] = make_float2(0.f, 0.f);
+    for (int s0 = 0; s0 < ksplit; s0 += kSum3) {
+      float2 v[kSum3][kIt3];
+#pragma unroll
+      for (int h = 0; h < kSum3; ++h)
+#pragma unroll
+        for (int it = 0; it < kIt3; ++it) {
+          const int i = min(i0 + tid + 256 * it, nel - 1);  // past the end: a valid element, not stored
+          v[h][it] = s0 + h < ksplit ? Zp[(size_t)(s0 + h) * zstride + (size_t)l0 * NY + i] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+      for (int h = 0; h < kSum3; ++h)
+#pragma unroll
+        for (int it = 0; it < kIt3; ++it) a[it] = cadd(a[it], v[h][it]);
+    }
+#pragma unroll
+    for (int it = 0; it < kIt3; ++it) {
+      const int i = i0 + tid + 256 * it;
+      if (i < nel) {
+        const int li = i / NY, y = i - li * NY;
+        A[li * LS + fpad(y)] = (y & 1) ? make_float2(-a[it].x, -a[it].y) : a[it];
+      }
+    }
   }
   __syncthreads();
   const float2* res = fft_lines<NY>(A, Bf, twl, nl, LS, tid, 256, sync3);
@@ -115,31 +140,34 @@ __global__ __launch_bounds__(256) void k3_z(float2* __restrict__ T, int ny, int 
   }
 }
 
-// y pass, inverse, lines (b, p, k, z) of T -> Z^T rows (z * ny + y), k fastest.
+// y pass, inverse, lines (b, p, k, z) of T -> Z^T rows (z * ny + y), k
+// fastest.  A work-group takes L consecutive k of one (b, p, z), so its
+// stores for each y are L consecutive elements of a Z^T row.
 template <int NY, Store ST>
-__global__ __launch_bounds__(256) void k3_y_inv(const float2* __restrict__ T, void* __restrict__ Zt, int nlines,
-                                                int nz, int K, int kp, const float2* __restrict__ tw) {
+__global__ __launch_bounds__(256) void k3_y_inv(const float2* __restrict__ T, void* __restrict__ Zt, int nz, int K,
+                                                int kp, const float2* __restrict__ tw) {
   constexpr int LS = fline(NY), L = lines3<NY>();
   __shared__ float2 twl[NY];
   __shared__ float2 A[L * LS], Bf[L * LS];
   const int tid = threadIdx.x;
   for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
-  const int l0 = blockIdx.x * L, nl = min(L, nlines - l0);
+  const int kblocks = (K + L - 1) / L;
+  const int z = blockIdx.x % nz, rest = blockIdx.x / nz;  // consecutive groups read neighbouring lines of T
+  const int kb = rest % kblocks, bp = rest / kblocks;
+  const int k0 = kb * L, nl = min(L, K - k0);
+  const float2* Tl = T + (((size_t)bp * K + k0) * nz + z) * NY;  // line li at Tl + li nz NY
   for (int i = tid; i < nl * NY; i += 256) {
     const int li = i / NY, y = i - li * NY;
-    const float2 v = cconj(T[(size_t)l0 * NY + i]);
+    const float2 v = cconj(Tl[(size_t)li * nz * NY + y]);
     A[li * LS + fpad(y)] = (y & 1) ? make_float2(-v.x, -v.y) : v;
   }
   __syncthreads();
   const float2* res = fft_lines<NY>(A, Bf, twl, nl, LS, tid, 256, sync3);
-  const int rows = nz * NY;
+  const size_t row0 = (size_t)bp * nz * NY + (size_t)z * NY;
   for (int i = tid; i < nl * NY; i += 256) {
     const int y = i / nl, li = i - y * nl;
-    const int l = l0 + li;  // line = (bpk, z)
-    const int z = l % nz, bpk = l / nz;
-    const int bp = bpk / K, k = bpk - bp * K;
     const float2 v = cconj(cscale(res[li * LS + fpad(y)], post3<NY>(y)));
-    store_zt<ST>(Zt, (size_t)bp * rows + (size_t)z * NY + y, kp, k, v);
+    store_zt<ST>(Zt, row0 + y, kp, k0 + li, v);
   }
 }
 
@@ -193,10 +221,10 @@ struct YInv {
   struct L {
     static int run(const Plan& pl) {
       constexpr int LL = lines3<N>();
-      const int nlines = pl.B * pl.np * pl.K * pl.nz;
+      const int groups = pl.B * pl.np * pl.nz * ((pl.K + LL - 1) / LL);  // (b, p, block of k, z)
       void* zt = ST == Store::F32 ? static_cast<void*>(pl.Zt) : static_cast<void*>(pl.Zt16);
-      hipLaunchKernelGGL((k3_y_inv<N, ST>), dim3((nlines + LL - 1) / LL), dim3(256), 0, pl.stream, pl.T3, zt, nlines,
-                         pl.nz, pl.K, pl.Kp, pl.tw_y3);
+      hipLaunchKernelGGL((k3_y_inv<N, ST>), dim3(groups), dim3(256), 0, pl.stream, pl.T3, zt, pl.nz, pl.K, pl.Kp,
+                         pl.tw_y3);
       return GPJC_OK;
     }
   };
