@@ -280,3 +280,13 @@ def test_unrolled_network_matches_fp32(gpu_lib):
     assert abs(l1 - l0) <= 1e-5 * abs(l0)
     assert H.rel_l2(gx1, gx0) <= 1e-5
     assert np.linalg.norm(ga1 - ga0) <= 1e-5 * np.linalg.norm(ga0)
+
+
+@pytest.mark.parametrize("case", ["n180", "n230", "n280"])
+def test_paper_matrix_sizes(gpu_lib, case):
+    """The matrix sizes of the paper's scans (180, 230 = 10 x 23, 280): forward,
+    adjoint and E'^H E' at the FP32 bars (random orthonormal bank)."""
+    from tests.test_gpu_operator import PAPER_SIZES
+    sl = H.rounded_slice(PAPER_SIZES[case]())
+    a, plan = make(sl, bank="random", seed=23)
+    all_three(plan, H.oracle_ops(sl, a), sl.geom, 38)

@@ -46,6 +46,9 @@ CASES = {
     # ragged: 48 x 48 x 32, 3 coils, os 2 (96), 6 patches of 16, K = 10, CAIPI 3 x 2 shift 1, 4 x 4 centre
     "rect": lambda: rounded(synth.volume(1, n=48, nz=32, nc=3, os_=2, patch_len=16, k=10, ry=3, rz=2, shift=1,
                                          acs=4, cycles=2)),
+    # K = 20: the inverse y pass takes its k in two blocks, the second partial
+    "k20": lambda: rounded(synth.volume(2, n=32, nz=16, nc=4, os_=4, patch_len=16, k=20, ry=2, rz=2, shift=1,
+                                        cycles=4)),
 }
 
 
