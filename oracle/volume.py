@@ -88,6 +88,23 @@ def forward_full(image, coils, psf, mask, os_):
     return f.reshape(nc, nz * ny, nt)[:, sampled_points(mask), :]
 
 
+def adjoint_full(s, coils, psf, mask, os_):
+    """Uncompressed E^H: S [Nc][Ms][Nt] -> image [Nz][Ny][Nx].  The acquired
+    points are zero-filled into every (coil, sample) plane, each plane goes
+    through the inverse centred 2D DFT, then the readout adjoint."""
+    nc, ms, nt = s.shape
+    nz, ny = mask.shape
+    full = np.zeros((nc, nz * ny, nt), dtype=np.complex128)
+    full[:, sampled_points(mask), :] = s
+    w = oe.cidft(oe.cidft(full.reshape(nc, nz, ny, nt), axis=2), axis=1)
+    return readout_encode_adj(w, coils, psf, os_)
+
+
+def normal_full(image, coils, psf, mask, os_):
+    """Uncompressed E^H E."""
+    return adjoint_full(forward_full(image, coils, psf, mask, os_), coils, psf, mask, os_)
+
+
 def calibrate(coils, psf, os_, patch_len, patch_group, n_groups, k, roi=None, noise_cov=None):
     """Section 2.4 over all voxels of the volume: the 2D calibration on the
     (z, y) rows."""

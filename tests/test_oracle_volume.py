@@ -1,5 +1,6 @@
 """Pins of the 3D oracle (oracle/volume.py): the dense signal equation with
-two phase encodes (Eqs. 1-4), reduction to the 2D operator at Nz = 1, the
+two phase encodes (Eqs. 1-4) and its conjugate transpose for the
+uncompressed adjoint and normal operators, reduction to the 2D operator at Nz = 1, the
 adjoint identity, Eq. 13 on acquired data, losslessness at full rank, and
 the R-fold point spread of a CAIPI mask."""
 import numpy as np
@@ -21,6 +22,20 @@ def test_dense_signal_equation_two_phase_encodes():
     assert np.allclose(s.reshape(-1), e @ v.image.reshape(-1), atol=1e-12)
 
 
+def test_uncompressed_adjoint_and_normal_are_the_dense_ones():
+    """E^H and E^H E of the uncompressed volume operator against the
+    conjugate transpose of the dense signal equation, entry by entry."""
+    v = tiny_volume()
+    args = (v.coils, v.psf, v.mask2, v.geom.os)
+    e = ov.dense_encoding(*args)
+    rng = np.random.default_rng(3)
+    s = ov.forward_full(v.image, *args)
+    y = rng.standard_normal(s.shape) + 1j * rng.standard_normal(s.shape)
+    assert np.allclose(ov.adjoint_full(y, *args).reshape(-1), e.conj().T @ y.reshape(-1), atol=1e-12)
+    x = rng.standard_normal(v.image.shape) + 1j * rng.standard_normal(v.image.shape)
+    assert np.allclose(ov.normal_full(x, *args).reshape(-1), e.conj().T @ (e @ x.reshape(-1)), atol=1e-11)
+
+
 def test_single_partition_is_the_2d_operator():
     sl = synth.tiny_slice(0, nx=8, ny=8, nc=2, os_=2, patch_len=4, k=3)
     g = sl.geom
@@ -31,6 +46,8 @@ def test_single_partition_is_the_2d_operator():
     assert np.allclose(s3, s2, atol=1e-12)
     f3 = ov.forward_full(sl.image[None], sl.coils[:, None], sl.psf[None], mask2, g.os)
     assert np.allclose(f3, oe.forward_full(sl.image, sl.coils, sl.psf, g.mask, g.os), atol=1e-12)
+    a3h = ov.adjoint_full(f3, sl.coils[:, None], sl.psf[None], mask2, g.os)
+    assert np.allclose(a3h[0], oe.adjoint_full(f3, sl.coils, sl.psf, g.mask, g.os), atol=1e-12)
     a3, _ = ov.calibrate(sl.coils[:, None], sl.psf[None], g.os, g.patch_len, g.patch_group, g.n_groups, g.k)
     assert np.allclose(oc.projectors(a3), oc.projectors(a), atol=1e-10)
 
