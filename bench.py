@@ -354,7 +354,9 @@ def volume_bench(steps=3):
     (180 x 180 x 80, 32 coils, os 8): 192 x 192 x 64, 32 coils, os 8 (1536
     samples), corkscrew PSF with 8 cycles and +-6 rad, 48 patches of 32 on the
     6 groups of one period, K = 56 (18x), CAIPI 4 x 3 shift 1 with a 16 x 16
-    centre.  Calibration, E'^H E' per volume (FP32, BF16), CG-20."""
+    centre.  Calibration, E'^H E' per volume (FP32, BF16), CG-20, and the
+    uncompressed FP32 E^H E of the same volume; a stage-timed application of
+    each operator."""
     import numpy as np
     import torch
 
@@ -391,9 +393,34 @@ def volume_bench(steps=3):
     plan.recon_cg(y, 20)
     torch.cuda.synchronize()
     res["cg20_s_per_volume"] = time.perf_counter() - t
+
+    def staged(p, prec):
+        p.stage_timing(True)
+        p.normal(x, prec=prec, out=o)
+        torch.cuda.synchronize()
+        st = p.stage_times()
+        p.stage_timing(False)
+        return {k: round(v[0], 4) for k, v in st.items() if v[1]}
+
+    res["stages_ms_fp32"] = staged(plan, "fp32")
     plan.close()
     log(f"3D volume: calibrate {t_cal:.2f} s, E'^H E' {res['normal_ms_fp32']:.2f} ms, "
         f"CG-20 {res['cg20_s_per_volume']:.3f} s")
+    full = gpjc.Plan.from_volume(v, compressed=False)
+    for _ in range(2):
+        full.normal(x, out=o)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        full.normal(x, out=o)
+    torch.cuda.synchronize()
+    res["uncompressed_fp32"] = {"normal_ms": (time.perf_counter() - t) / steps * 1e3,
+                                "stages_ms": staged(full, "fp32")}
+    full.close()
+    for prec in ("fp32", "bf16"):
+        res["uncompressed_fp32"][f"speedup_of_compressed_{prec}"] = \
+            res["uncompressed_fp32"]["normal_ms"] / res[f"normal_ms_{prec}"]
+    log(f"3D volume, uncompressed: E^H E {res['uncompressed_fp32']['normal_ms']:.2f} ms")
     return res
 
 

@@ -117,9 +117,12 @@ int gpjc_plan_create(const gpjc_geom* geom, const gpjc_c64* d_coils, const gpjc_
  * phase-encode stage is the centred unitary 2D DFT over (z, y), and data
  * (gpjc_forward's output, gpjc_compress's input lines) list the acquired
  * points in raster order (kz major, ky fastest): Ms = number of them.
- * Compressed plans only; nx, ny, nz built FFT lengths.  CG, FISTA with the
- * Haar term (2D Haar of every z partition), batching, autotuning and the
- * 16-bit precisions work as for slices; algorithm #1 and the TV term are
+ * geom->compressed = 0 gives the uncompressed E (data [B][nc][Ms][nt]), whose
+ * phase-encode stage takes the 2D DFT of every (coil, readout sample) plane
+ * of the readout-stage output in place; it needs batch * nc * nz <= 65535
+ * (GPJC_E_UNSUPPORTED otherwise).  nx, ny, nz built FFT lengths.  CG, FISTA
+ * with the Haar term (2D Haar of every z partition), batching, autotuning and
+ * the 16-bit precisions work as for slices; algorithm #1 and the TV term are
  * built for slices (GPJC_E_UNSUPPORTED).  Synchronises. */
 int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, const gpjc_c64* d_coils,
                         const gpjc_c64* d_psf, void* hip_stream, gpjc_plan** out);

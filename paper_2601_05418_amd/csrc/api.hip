@@ -371,8 +371,10 @@ int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, con
   if (!geom) return fail(GPJC_E_INVAL, "geom is NULL");
   if (nz < 2) return fail(GPJC_E_INVAL, "nz must be >= 2 (use gpjc_plan_create for a 2D slice)");
   if (!mask2) return fail(GPJC_E_INVAL, "mask2 is NULL");
-  if (!geom->compressed) return fail(GPJC_E_UNSUPPORTED, "3D plans are built for the compressed operator");
   if ((long)nz * geom->ny > (1L << 20)) return fail(GPJC_E_INVAL, "nz * ny out of range");
+  if (!geom->compressed && ((long)geom->batch * geom->nc * nz > 65535 ||
+                            (long)geom->batch * geom->nc * nz * geom->ny >= (1L << 31)))
+    return fail(GPJC_E_UNSUPPORTED, "batch * nc * nz too large for the uncompressed volume operator");
   if (!fft_size_supported(geom->nx) || !fft_size_supported(geom->ny) || !fft_size_supported(nz))
     return fail(GPJC_E_UNSUPPORTED, "nx, ny and nz must be built FFT lengths");
   // the 2D machinery on (z, y) rows
@@ -392,7 +394,7 @@ int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, con
     Plan& p = *pl;
     p.nz = nz;
     p.ny2 = geom->ny;
-    s = dalloc(&p.T3, (size_t)p.B * p.np * p.K * p.ny);
+    if (p.compressed) s = dalloc(&p.T3, (size_t)p.B * p.np * p.K * p.ny);
     if (s == GPJC_OK) s = dalloc(&p.pts3, (size_t)p.ms);
     if (s == GPJC_OK) s = dalloc(&p.sel3, (size_t)p.ny);
     if (s == GPJC_OK) s = dalloc(&p.maskf3, (size_t)p.ny);

@@ -759,38 +759,56 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
 }
 
 // ---------------------------------------------------------------------------
-// F_yᴴ M F_y on uncompressed columns, in place, two-pass register form (as
-// k_pe_normal2).  Work-group: one (b, n) and L consecutive t; lane ln = tid %
-// L owns column t0 + ln, so every global access is an L-sample row segment.
-// The first pass reads its stride-N2 inputs straight from W and the last pass
-// writes straight back; only the two exchanges go through LDS, laid out with
-// the column index fastest.
+// Centred DFTs along the columns of uncompressed planes, in place, two-pass
+// register form (as k_pe_normal2).  Element e of column c of plane q sits at
+// W[q pstride + e estride + c], c < ncols: for a slice, planes (b, n) with
+// columns t (estride = ncols = Nt); for a volume's y pass, planes (b, n, z)
+// likewise; for its z pass, planes (b, n) with columns y Nt + t (estride =
+// ncols = Ny Nt).  Work-group: L consecutive columns of one plane; lane ln =
+// tid % L owns column c0 + ln, so every global access is an L-sample row
+// segment.  The first pass reads its stride-N2 inputs straight from W and the
+// last pass writes straight back; only the exchanges go through LDS, laid out
+// with the column index fastest.  N = N1 N2 with L max(N1, N2) = 256.
 // ---------------------------------------------------------------------------
-template <int NY>
-struct PeCols2Geo {
-  static constexpr int N1 = Split<NY>::N1, N2 = Split<NY>::N2;
+template <int N, int N1_>
+struct Cols2Geo {
+  static constexpr int N1 = N1_, N2 = N / N1_;
   static constexpr int L = 256 / (N1 > N2 ? N1 : N2);  // columns per work-group
 };
 
-template <int NY>
-__global__ __launch_bounds__(256) void k_pe_cols_normal2(float2* __restrict__ W, const float* __restrict__ maskf,
-                                                         int nt, const float2* __restrict__ tw) {
-  using Gm = PeCols2Geo<NY>;
+// N1 <= sqrt(N) as large as possible with 256 divisible by N / N1 (so every
+// thread has an item in the first pass); the slice's factors otherwise.
+constexpr int cols_n1(int n) {
+  int best = 1;
+  for (int d = 2; d * d <= n; ++d)
+    if (n % d == 0 && n / d <= 32 && 256 % (n / d) == 0 && reg_dft_ok(d) && reg_dft_ok(n / d)) best = d;
+  return best > 1 ? best : split_n1(n);
+}
+
+// F^H M F per column: mask maskf[k mstride + c / cdiv] at frequency k of
+// column c (a slice: mstride 1, cdiv = ncols; a volume's z pass: mstride Ny,
+// cdiv Nt, the mask row of the column's ky).
+template <int NY, int N1_>
+__global__ __launch_bounds__(256) void k_pe_cols_normal2(float2* __restrict__ W, size_t pstride, size_t estride,
+                                                         int ncols, const float* __restrict__ maskf, int mstride,
+                                                         int cdiv, const float2* __restrict__ tw) {
+  using Gm = Cols2Geo<NY, N1_>;
   constexpr int N1 = Gm::N1, N2 = Gm::N2, L = Gm::L;
   __shared__ float2 twl[NY];
   __shared__ float2 E[N1 * N2 * L];  // element (i2, k1) of column ln at (i2 N1 + k1) L + ln
   const int tid = threadIdx.x;
   for (int i = tid; i < NY; i += 256) twl[i] = tw[i];
-  const int t0 = blockIdx.x * L;
+  const int c0 = blockIdx.x * L;
   const int ln = tid % L, it = tid / L;
-  const bool colok = t0 + ln < nt;
-  float2* col = W + (size_t)blockIdx.y * NY * nt + t0 + ln;  // sample y of this column at col[y nt]
+  const bool colok = c0 + ln < ncols;
+  const int moff = colok ? (c0 + ln) / cdiv : 0;
+  float2* col = W + (size_t)blockIdx.y * pstride + c0 + ln;  // element y of this column at col[y estride]
   float2 v[N1];
   if (it < N2) {  // forward, first pass: item (ln, i2 = it)
 #pragma unroll
     for (int i1 = 0; i1 < N1; ++i1) {
       const int y = it + N2 * i1;
-      const float2 a = colok ? col[(size_t)y * nt] : make_float2(0.f, 0.f);
+      const float2 a = colok ? col[(size_t)y * estride] : make_float2(0.f, 0.f);
       v[i1] = (y & 1) ? make_float2(-a.x, -a.y) : a;
     }
   }
@@ -816,7 +834,8 @@ __global__ __launch_bounds__(256) void k_pe_cols_normal2(float2* __restrict__ W,
     rdft<N2>(w);  // w[k2] = F[k1 + N1 k2]
     const float inv = 1.0f / (float)NY;
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) w[k2] = cconj(cscale(w[k2], maskf[it + N1 * k2] * inv));
+    for (int k2 = 0; k2 < N2; ++k2)
+      w[k2] = cconj(cscale(w[k2], maskf[(size_t)(it + N1 * k2) * mstride + moff] * inv));
     rdft<N2>(w);
   }
   __syncthreads();
@@ -839,7 +858,65 @@ __global__ __launch_bounds__(256) void k_pe_cols_normal2(float2* __restrict__ W,
       const int y = it + N2 * n1;
       float2 r = cconj(v[n1]);
       if (y & 1) r = make_float2(-r.x, -r.y);
-      col[(size_t)y * nt] = r;
+      col[(size_t)y * estride] = r;
+    }
+  }
+}
+
+// The centred DFT (inverse = 0) or its inverse (1) of every column.  Forward:
+// x[e] (-1)^e in, X[k] pe_post(k) out; inverse: conj(X[k]) pe_post(k) in,
+// conj(.) (-1)^e out.
+template <int N, int N1_>
+__global__ __launch_bounds__(256) void k_cols2(float2* __restrict__ W, size_t pstride, size_t estride, int ncols,
+                                               int inverse, const float2* __restrict__ tw) {
+  using Gm = Cols2Geo<N, N1_>;
+  constexpr int N1 = Gm::N1, N2 = Gm::N2, L = Gm::L;
+  __shared__ float2 twl[N];
+  __shared__ float2 E[N1 * N2 * L];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += 256) twl[i] = tw[i];
+  const int c0 = blockIdx.x * L;
+  const int ln = tid % L, it = tid / L;
+  const bool colok = c0 + ln < ncols;
+  float2* col = W + (size_t)blockIdx.y * pstride + c0 + ln;
+  float2 v[N1];
+  if (it < N2) {  // first pass: item (ln, i2 = it)
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1) {
+      const int e = it + N2 * i1;
+      const float2 a = colok ? col[(size_t)e * estride] : make_float2(0.f, 0.f);
+      v[i1] = inverse ? cscale(cconj(a), pe_post<N>(e)) : ((e & 1) ? make_float2(-a.x, -a.y) : a);
+    }
+  }
+  __syncthreads();  // twiddle table
+  if (it < N2) {
+    rdft<N1>(v);
+    E[(it * N1) * L + ln] = v[0];
+    int m = it;
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      E[(it * N1 + k1) * L + ln] = cmul(v[k1], twl[m]);
+      m += it;
+      m = m >= N ? m - N : m;
+    }
+  }
+  __syncthreads();
+  if (it < N1 && colok) {  // second pass: item (ln, k1 = it), outputs k1 + N1 k2
+    float2 w[N2];
+#pragma unroll
+    for (int i2 = 0; i2 < N2; ++i2) w[i2] = E[(i2 * N1 + it) * L + ln];
+    rdft<N2>(w);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int e = it + N1 * k2;
+      float2 r;
+      if (inverse) {
+        r = cconj(w[k2]);
+        if (e & 1) r = make_float2(-r.x, -r.y);
+      } else {
+        r = cscale(w[k2], pe_post<N>(e));
+      }
+      col[(size_t)e * estride] = r;
     }
   }
 }
@@ -1017,9 +1094,10 @@ struct PeCols {
       StageScope sc(pl, GPJC_STAGE_PE_COLS);
       if constexpr (ST == Store::F32 && Split<NY>::ok) {
         if (mode == 2) {
-          constexpr int L = PeCols2Geo<NY>::L;
-          hipLaunchKernelGGL((k_pe_cols_normal2<NY>), dim3((pl.nt + L - 1) / L, pl.B * pl.nc), dim3(256), 0,
-                             pl.stream, pl.W, pl.maskf, pl.nt, pl.tw_y);
+          constexpr int N1 = Split<NY>::N1, L = Cols2Geo<NY, N1>::L;
+          hipLaunchKernelGGL((k_pe_cols_normal2<NY, N1>), dim3((pl.nt + L - 1) / L, pl.B * pl.nc), dim3(256), 0,
+                             pl.stream, pl.W, (size_t)NY * pl.nt, (size_t)pl.nt, pl.nt, (const float*)pl.maskf, 1,
+                             pl.nt, (const float2*)pl.tw_y);
           GPJC_HIP(hipGetLastError());
           return GPJC_OK;
         }
@@ -1034,6 +1112,34 @@ struct PeCols {
     }
   };
 };
+
+// The passes of a volume's uncompressed phase-encode stage over W, in place
+// (pe3d.hip orders them): 0 y forward, 1 y inverse, over lines of Ny at
+// stride Nt in every (b, n, z) row block; 2 z forward, 3 z inverse, 4 z
+// forward, 2D mask, inverse, over the columns (y, t) of every (b, n) plane
+// at stride Ny Nt.  N is Ny for the y passes, Nz for the z passes.
+template <int N>
+struct Cols3 {
+  static int run(const Plan& pl, int pass) {
+    constexpr int N1 = cols_n1(N), L = Cols2Geo<N, N1>::L;
+    const bool ypass = pass < 2;
+    const size_t ncols = ypass ? (size_t)pl.nt : (size_t)pl.ny2 * pl.nt;  // also the element stride
+    const size_t pstride = ypass ? (size_t)pl.ny2 * pl.nt : (size_t)pl.ny * pl.nt;
+    const int planes = ypass ? pl.B * pl.nc * pl.nz : pl.B * pl.nc;
+    const float2* tw = ypass ? pl.tw_y3 : pl.tw_z3;
+    const dim3 grid((unsigned)((ncols + L - 1) / L), planes);
+    if (pass == 4)
+      hipLaunchKernelGGL((k_pe_cols_normal2<N, N1>), grid, dim3(256), 0, pl.stream, pl.W, pstride, ncols, (int)ncols,
+                         (const float*)pl.maskf3, pl.ny2, pl.nt, tw);
+    else
+      hipLaunchKernelGGL((k_cols2<N, N1>), grid, dim3(256), 0, pl.stream, pl.W, pstride, ncols, (int)ncols, pass & 1,
+                         tw);
+    GPJC_HIP(hipGetLastError());
+    return GPJC_OK;
+  }
+};
+
+int launch_pe3_cols_pass(const Plan& pl, int pass) { return dispatch_n<Cols3>(pass < 2 ? pl.ny2 : pl.nz, pl, pass); }
 
 int launch_readout_fwd(const Plan& pl, const float2* img, Store st) {
   switch (storage_of(st)) {
@@ -1104,7 +1210,7 @@ int op_forward(const Plan& pl, Store st, const float2* img, float2* out) {
   }
   if (!pl.compressed) {
     GPJC_TRY(launch_readout_fwd(pl, img, Store::F32));
-    return launch_pe_cols_fwd(pl, out);
+    return pl.nz > 1 ? launch_pe3_cols_fwd(pl, out) : launch_pe_cols_fwd(pl, out);
   }
   GPJC_TRY(launch_readout_fwd(pl, img, st));
   GPJC_TRY(launch_group_compress(pl, st));
@@ -1117,7 +1223,7 @@ int op_adjoint_part(const Plan& pl, Store st, const float2* in) {
     return launch_explicit_adj(pl);
   }
   if (!pl.compressed) {
-    GPJC_TRY(launch_pe_cols_adj(pl, in));
+    GPJC_TRY(pl.nz > 1 ? launch_pe3_cols_adj(pl, in) : launch_pe_cols_adj(pl, in));
     return launch_readout_adj(pl, Store::F32);
   }
   GPJC_TRY(launch_pe_adj(pl, in, st));
@@ -1145,7 +1251,7 @@ int op_normal_part(const Plan& pl, Store st, const float2* img) {
   }
   if (!pl.compressed) {
     GPJC_TRY(launch_readout_fwd(pl, img, Store::F32));
-    GPJC_TRY(launch_pe_cols_normal(pl));
+    GPJC_TRY(pl.nz > 1 ? launch_pe3_cols_normal(pl) : launch_pe_cols_normal(pl));
     return launch_readout_adj(pl, Store::F32);
   }
   GPJC_TRY(launch_readout_fwd(pl, img, st));

@@ -11,6 +11,13 @@
 //   normal   Zp -> y-DFT -> T -> z-DFT, mask, inverse z-DFT -> T -> inverse y-DFT -> Z^T
 //   adjoint  S' -> scatter (zero fill) -> T -> inverse z-DFT -> T -> inverse y-DFT -> Z^T
 //
+// The uncompressed operator takes the same 2D DFT of every (coil, sample)
+// plane of the readout-stage output W [b][n][z Ny + y][t], in place, with
+// the two-pass column kernels of operator.hip: a y pass over lines of Ny at
+// stride Nt, a z pass over the (y, t) columns of each (b, n) plane at stride
+// Ny Nt; whole rows of Nt samples are gathered to, or scattered from,
+// S [b][n][Ms][Nt].
+//
 // Centred DFT of length N from an unnormalised FFT: x[i] (-1)^i in, then
 // X[k] (-1)^(N/2 + k) / sqrt(N) out; the inverse is conj(F(conj(.))).
 #include <hip/hip_runtime.h>
@@ -194,6 +201,33 @@ __global__ __launch_bounds__(256) void k3_scatter(const float2* __restrict__ in,
   }
 }
 
+// out[q][m][t] = W[q][pts[m]][t] over the planes q = (b, n): the acquired rows
+__global__ __launch_bounds__(256) void k3_gather_rows(const float2* __restrict__ W, const int* __restrict__ pts, int ms,
+                                                      int rows, int nt, int nout, float2* __restrict__ out) {
+  for (int o = blockIdx.x; o < nout; o += gridDim.x) {
+    const int q = o / ms, m = o - q * ms;
+    const float2* src = W + ((size_t)q * rows + pts[m]) * nt;
+    float2* dst = out + (size_t)o * nt;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) dst[t] = src[t];
+  }
+}
+
+// W[q][r][t] = S[q][sel[r]][t] where row r is acquired, 0 elsewhere
+__global__ __launch_bounds__(256) void k3_scatter_rows(const float2* __restrict__ in, const int* __restrict__ sel,
+                                                       int ms, int rows, int nt, int nw, float2* __restrict__ W) {
+  for (int o = blockIdx.x; o < nw; o += gridDim.x) {
+    const int q = o / rows, r = o - q * rows;
+    const int m = sel[r];
+    float2* dst = W + (size_t)o * nt;
+    if (m >= 0) {
+      const float2* src = in + ((size_t)q * ms + m) * nt;
+      for (int t = threadIdx.x; t < nt; t += blockDim.x) dst[t] = src[t];
+    } else {
+      for (int t = threadIdx.x; t < nt; t += blockDim.x) dst[t] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
 template <int N>
 struct YFwd {
   static int run(const Plan& pl, int ksplit, size_t zstride) {
@@ -276,6 +310,37 @@ int launch_pe3_normal(const Plan& pl, Store st) {
   GPJC_TRY(dispatch3<YFwd>(pl.ny2, pl, pl.cfg(st).ksplit, zs));
   GPJC_TRY(dispatch3<ZPass>(pl.nz, pl, 1));
   GPJC_TRY(y_inv(pl, st));
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int launch_pe3_cols_fwd(const Plan& pl, float2* out) {
+  StageScope sc(pl, GPJC_STAGE_PE_COLS);
+  GPJC_TRY(launch_pe3_cols_pass(pl, 0));
+  GPJC_TRY(launch_pe3_cols_pass(pl, 2));
+  const int nout = pl.B * pl.nc * pl.ms;
+  hipLaunchKernelGGL(k3_gather_rows, dim3(std::min(nout, 8192)), dim3(256), 0, pl.stream, pl.W, pl.pts3, pl.ms, pl.ny,
+                     pl.nt, nout, out);
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int launch_pe3_cols_adj(const Plan& pl, const float2* in) {
+  StageScope sc(pl, GPJC_STAGE_PE_COLS);
+  const int nw = pl.B * pl.nc * pl.ny;
+  hipLaunchKernelGGL(k3_scatter_rows, dim3(std::min(nw, 8192)), dim3(256), 0, pl.stream, in, pl.sel3, pl.ms, pl.ny,
+                     pl.nt, nw, pl.W);
+  GPJC_TRY(launch_pe3_cols_pass(pl, 3));
+  GPJC_TRY(launch_pe3_cols_pass(pl, 1));
+  GPJC_HIP(hipGetLastError());
+  return GPJC_OK;
+}
+
+int launch_pe3_cols_normal(const Plan& pl) {
+  StageScope sc(pl, GPJC_STAGE_PE_COLS);
+  GPJC_TRY(launch_pe3_cols_pass(pl, 0));
+  GPJC_TRY(launch_pe3_cols_pass(pl, 4));
+  GPJC_TRY(launch_pe3_cols_pass(pl, 1));
   GPJC_HIP(hipGetLastError());
   return GPJC_OK;
 }

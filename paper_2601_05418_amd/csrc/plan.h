@@ -82,7 +82,7 @@ struct Plan {
   // 3D volumes (gpjc_plan_create_3d): rows are (z, y) pairs, ny = nz * ny2;
   // the phase-encode stage is the 2D DFT over (z, y) with a 2D mask
   int nz = 1, ny2 = 0;
-  float2* T3 = nullptr;     // [B][np][K][nz][ny2] planes between the 2D-DFT passes
+  float2* T3 = nullptr;     // [B][np][K][nz][ny2] planes between the 2D-DFT passes (compressed plans)
   int* pts3 = nullptr;      // [ms] row (kz * ny2 + ky) of each acquired point
   int* sel3 = nullptr;      // [ny] acquired-point index of every row, or -1
   float* maskf3 = nullptr;  // [ny] 0 / 1
@@ -197,6 +197,8 @@ int launch_pe_normal(const Plan& pl, Store st);
 int launch_pe_cols_fwd(const Plan& pl, float2* out);
 int launch_pe_cols_adj(const Plan& pl, const float2* in);
 int launch_pe_cols_normal(const Plan& pl);
+// volumes: one pass over W in place; 0 / 1 y forward / inverse, 2 / 3 z forward / inverse, 4 z normal
+int launch_pe3_cols_pass(const Plan& pl, int pass);
 int launch_expand_bank(Plan& pl);
 // Tile shapes built per precision class, and the default configuration of a plan.
 int gemm_compress_variants();
@@ -284,6 +286,10 @@ int run_wavelet_absmax(Plan& pl, const float2* img, int levels, double* h_out);
 int launch_pe3_fwd(const Plan& pl, float2* out, Store st);
 int launch_pe3_adj(const Plan& pl, const float2* in, Store st);
 int launch_pe3_normal(const Plan& pl, Store st);
+// the same stage on the uncompressed W [B][nc][nz ny2][nt], in place
+int launch_pe3_cols_fwd(const Plan& pl, float2* out);
+int launch_pe3_cols_adj(const Plan& pl, const float2* in);
+int launch_pe3_cols_normal(const Plan& pl);
 int setup_pe3(Plan& pl, const uint8_t* mask2);
 
 // ---- explicit readout model for general modulation maps (explicit.hip) ----

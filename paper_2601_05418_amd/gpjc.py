@@ -206,11 +206,11 @@ class Plan:
                    g.k, batch=batch, compressed=compressed, **kw)
 
     @classmethod
-    def from_volume(cls, v, batch=1, **kw):
+    def from_volume(cls, v, batch=1, compressed=True, **kw):
         """A plan for a 3D volume (synth.Volume)."""
         g = v.geom
         return cls(g.nx, g.ny, g.nc, g.os, v.coils, v.psf, v.mask2, g.patch_len, g.patch_group, g.n_groups, g.k,
-                   batch=batch, compressed=True, nz=v.nz, **kw)
+                   batch=batch, compressed=compressed, nz=v.nz, **kw)
 
     @classmethod
     def from_map_slice(cls, sl, batch=1, **kw):
