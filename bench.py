@@ -513,6 +513,8 @@ def main():
                     help="only run 5 plain device copies of MIB MiB (reference for byte counters)")
     ap.add_argument("--op-only", type=int, default=0, metavar="N",
                     help="only calibrate and run N applications of E'^H E' (for profiler runs)")
+    ap.add_argument("--volume-only", action="store_true",
+                    help="only run the 3D volume measurement and print its record (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single "
@@ -533,6 +535,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": n * 4, "copies": 5}), flush=True)
+        return
+    if args.volume_only:
+        print(json.dumps({"volume_3d": volume_bench()}), flush=True)
         return
     sl = synth.highfield_slice(0, periodic=args.periodic)
     g = sl.geom
