@@ -354,7 +354,7 @@ def volume_bench(steps=3):
     (180 x 180 x 80, 32 coils, os 8): 192 x 192 x 64, 32 coils, os 8 (1536
     samples), corkscrew PSF with 8 cycles and +-6 rad, 48 patches of 32 on the
     6 groups of one period, K = 56 (18x), CAIPI 4 x 3 shift 1 with a 16 x 16
-    centre.  Calibration, E'^H E' per volume (FP32, BF16), CG-20, and the
+    centre.  Calibration, tile autotuning, E'^H E' per volume (FP32, BF16), CG-20, and the
     uncompressed FP32 E^H E of the same volume; a stage-timed application of
     each operator."""
     import numpy as np
@@ -371,6 +371,8 @@ def volume_bench(steps=3):
     plan.calibrate()
     torch.cuda.synchronize()
     t_cal = time.perf_counter() - t
+    for prec in ("fp32", "bf16"):
+        plan.autotune(prec)  # contraction tiles for the volume's shapes (under a second each)
     x = torch.as_tensor(np.ascontiguousarray(v.image[None], np.complex64)).to(dev)
     o = torch.empty_like(x)
     res = {"workload": f"3D Wave-CAIPI {g.nx}x{g.ny}x{v.nz}, {g.nc} coils, os {g.os} ({g.nt} samples), "
