@@ -63,6 +63,28 @@ def test_invalid_geometry(over, code):
     assert lib.gpjc_last_error()
 
 
+def test_volume_plan_refusals():
+    """gpjc_plan_create_3d checks its sizes before it touches a device: nz,
+    the mask, an unbuilt Nz, and for the uncompressed operator the
+    batch * nc * nz planes of its y pass."""
+    lib = gpjc.load()
+    mask2 = np.ones(16 * 16, np.uint8)
+    out = ctypes.c_void_p()
+    m = mask2.ctypes.data_as(ctypes.c_void_p)
+    g, keep = _geom(nx=16, ny=16, nc=4, os=2, patch_len=4, n_groups=8, k=4)
+    assert lib.gpjc_plan_create_3d(ctypes.byref(g), 1, m, FAKE, FAKE, None, ctypes.byref(out)) == gpjc.GPJC_E_INVAL
+    assert lib.gpjc_plan_create_3d(ctypes.byref(g), 16, None, FAKE, FAKE, None, ctypes.byref(out)) == \
+        gpjc.GPJC_E_INVAL
+    g, keep = _geom(nx=16, ny=16, nc=4, os=2, patch_len=4, n_groups=8, k=4)
+    assert lib.gpjc_plan_create_3d(ctypes.byref(g), 22, np.ones(22 * 16, np.uint8).ctypes.data_as(ctypes.c_void_p),
+                                   FAKE, FAKE, None, ctypes.byref(out)) == gpjc.GPJC_E_UNSUPPORTED
+    g, keep = _geom(nx=16, ny=16, nc=4096, os=2, compressed=0)
+    assert lib.gpjc_plan_create_3d(ctypes.byref(g), 16, m, FAKE, FAKE, None, ctypes.byref(out)) == \
+        gpjc.GPJC_E_UNSUPPORTED
+    assert b"nz" in lib.gpjc_last_error()
+    assert out.value is None
+
+
 def test_group_value_out_of_range():
     lib = gpjc.load()
     pg = np.arange(16, dtype=np.int32)
