@@ -371,7 +371,7 @@ int gpjc_plan_create_3d(const gpjc_geom* geom, int nz, const uint8_t* mask2, con
   if (!geom) return fail(GPJC_E_INVAL, "geom is NULL");
   if (nz < 2) return fail(GPJC_E_INVAL, "nz must be >= 2 (use gpjc_plan_create for a 2D slice)");
   if (!mask2) return fail(GPJC_E_INVAL, "mask2 is NULL");
-  if ((long)nz * geom->ny > (1L << 20)) return fail(GPJC_E_INVAL, "nz * ny out of range");
+  if ((long)nz * geom->ny > 65535L * 16) return fail(GPJC_E_INVAL, "nz * ny out of range");
   if (!geom->compressed && ((long)geom->batch * geom->nc * nz > 65535 ||
                             (long)geom->batch * geom->nc * nz * geom->ny >= (1L << 31)))
     return fail(GPJC_E_UNSUPPORTED, "batch * nc * nz too large for the uncompressed volume operator");
