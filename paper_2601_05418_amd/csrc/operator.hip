@@ -318,12 +318,12 @@ __global__ __launch_bounds__(256) void k_readout_fwd2(const float2* __restrict__
 // taken as conj(FFT(conj(.))) with the two passes of the forward form; the
 // sum over sub-transforms of the pre-twiddled results and the coil
 // combination follow.  Pre-twiddles are read from the (L1-resident) table.
-// Grid (kAdjRows x chunks, row blocks, B): the chunks of kAdjRows
+// Grid (kAdjRowBlock x chunks, row blocks, B): the chunks of kAdjRowBlock
 // consecutive rows are consecutive work-groups, so they find each row's PSF
 // in L2 (sweeping all rows of one chunk after another took a volume's PSF,
 // Nz Ny Nt samples, from HBM once per chunk), while the W rows read at one
-// time stay kAdjRows consecutive rows of each coil.
-constexpr int kAdjRows = 16;
+// time stay kAdjRowBlock consecutive rows of each coil.
+constexpr int kAdjRowBlock = 16;
 template <int NX, Store ST>
 __global__ __launch_bounds__(256) void k_readout_adj2(const void* __restrict__ W, const float2* __restrict__ coils,
                                                       const float2* __restrict__ psfp, const float2* __restrict__ twin,
@@ -335,7 +335,8 @@ __global__ __launch_bounds__(256) void k_readout_adj2(const void* __restrict__ W
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nt = os * NX;
   const int nxp = NX + ((os - NX % 32) % 32 + 32) % 32;
-  const int y = blockIdx.y * kAdjRows + blockIdx.x % kAdjRows, chunk = blockIdx.x / kAdjRows, b = blockIdx.z;
+  const int y = blockIdx.y * kAdjRowBlock + blockIdx.x % kAdjRowBlock;
+  const int chunk = blockIdx.x / kAdjRowBlock, b = blockIdx.z;
   if (y >= ny) return;  // the last row block's spare work-groups
   const int n0 = chunk * cb, ncb = min(cb, nc - n0);
   float2* twl = sm;       // [NX]
@@ -775,7 +776,7 @@ __global__ __launch_bounds__(256) void k_pe_cols(const void* __restrict__ Win, v
 // tid % L owns column c0 + ln, so every global access is an L-sample row
 // segment.  The first pass reads its stride-N2 inputs straight from W and the
 // last pass writes straight back; only the exchanges go through LDS, laid out
-// with the column index fastest.  N = N1 N2 with L max(N1, N2) = 256.
+// with the column index fastest.  N = N1 N2, L max(N1, N2) <= 256.
 // ---------------------------------------------------------------------------
 template <int N, int N1_>
 struct Cols2Geo {
@@ -1014,7 +1015,7 @@ struct ReadoutAdj {
       if constexpr (Split<NX>::ok) {
         if (pl.f2_adj) {
           const size_t lds = two_pass_lds_adj(NX, pl.os, pl.f2_cb) * sizeof(float2);
-          const dim3 grid(kAdjRows * pl.f1h_nchunk, (pl.ny + kAdjRows - 1) / kAdjRows, pl.B);
+          const dim3 grid(kAdjRowBlock * pl.f1h_nchunk, (pl.ny + kAdjRowBlock - 1) / kAdjRowBlock, pl.B);
           sc.launch(k_readout_adj2<NX, ST>, grid, dim3(pl.f2_threads), lds, pl.stream, (const void*)pl.W, pl.coils,
                     pl.psfp, pl.twin, pl.tw_x, pl.part, pl.ny, pl.nc, pl.os, pl.f2_cb, pl.B);
           GPJC_HIP(hipGetLastError());
