@@ -237,11 +237,23 @@ def test_volume_uncompressed_batch_and_cg(gpu_lib):
     one = gpjc.Plan.from_volume(v, compressed=False)
     y = H.round64(fwd(v.image))
     xg, hist = one.recon_cg(dev(y[None]), 12, want_resid=True)
-    xo, ho = osv.cg(nrm, adj(y), 12)
+    b = adj(y)
+    xo, ho = osv.cg(nrm, b, 12)
     e = osv.nrmse(host(xg)[0], xo)
     print(f"uncompressed CG-12 NRMSE {e:.2e}", flush=True)
     assert e <= H.NRMSE_RECON
     assert np.allclose(hist, ho, rtol=1e-3)
+    # FISTA with the Haar term of every z partition on the same schedule
+    shp = v.image.shape
+    flat = (shp[0] * shp[1], shp[2])
+    nrm2 = lambda u: nrm(u.reshape(shp)).reshape(flat)
+    lip = osv.power_iteration(nrm2, flat, iters=40, seed=0) * 1.01
+    lam = 1e-3 * np.abs(osv.haar_fwd(b.reshape(flat), 2)).max()
+    xf = host(one.recon_fista(dev(y[None]), 15, lam, lip, levels=2))[0]
+    xfo, _ = osv.fista(nrm2, b.reshape(flat), 15, lam, lip, 2)
+    e = osv.nrmse(xf, xfo.reshape(shp))
+    print(f"uncompressed FISTA-15 NRMSE {e:.2e}", flush=True)
+    assert e <= H.NRMSE_RECON
 
 
 def test_volume_uncompressed_moderate_size(gpu_lib):
