@@ -1164,13 +1164,15 @@ void default_gemm_config(Plan& pl) {
     int ks = (int)std::max<long>(1, (target + t - 1) / t);
     ks = std::min(std::min(ks, std::max(1, 2 * pl.ns / 128)), kMaxKsplit);
     // a split whose k-chunks the staged form can address (large volumes)
-    while (ks < kMaxKsplit &&
-           !compress_span_fits((size_t)pl.ny * pl.nt * 2,
-                               chunk_coil_span(2 * pl.ns, compress_kchunk(2 * pl.ns, ks, st), ks, 2 * pl.P),
-                               elem_bytes(st)))
-      ++ks;
+    while (ks < kMaxKsplit && !compress_split_staged(pl, st, ks)) ++ks;
     g.ksplit = ks;
   }
+}
+
+bool compress_split_staged(const Plan& pl, Store st, int ksplit) {
+  return compress_span_fits((size_t)pl.ny * pl.nt * 2,
+                            chunk_coil_span(2 * pl.ns, compress_kchunk(2 * pl.ns, ksplit, st), ksplit, 2 * pl.P),
+                            elem_bytes(st));
 }
 
 int launch_group_compress(const Plan& pl, Store st) {

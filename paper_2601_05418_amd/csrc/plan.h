@@ -200,6 +200,9 @@ int launch_pe_cols_normal(const Plan& pl);
 // volumes: one pass over W in place; 0 / 1 y forward / inverse, 2 / 3 z forward / inverse, 4 z normal
 int launch_pe3_cols_pass(const Plan& pl, int pass);
 int launch_expand_bank(Plan& pl);
+// Whether the staged compressing forms can address the readout-stage output
+// of a plan with this split (else it runs on the general form).
+bool compress_split_staged(const Plan& pl, Store st, int ksplit);
 // Tile shapes built per precision class, and the default configuration of a plan.
 int gemm_compress_variants();
 int gemm_expand_variants();

@@ -118,9 +118,14 @@ int measure(Plan& pl, Store st, Choice* out, float* us_c, float* us_e) {
   // The split is timed together with the phase-encode stage, which reads
   // back one partial of Z per split.
   const int splits[] = {1, 2, 3, 4, 6, 8};
+  // splits that leave the staged forms (an operand of several GiB) are not
+  // timed when another split keeps them
+  bool any_staged = false;
+  for (int ks : splits) any_staged = any_staged || (ks <= kMaxKsplit && compress_split_staged(pl, st, ks));
   for (int v = 0; status == GPJC_OK && v < gemm_compress_variants(); ++v)
     for (int ks : splits) {
       if (status != GPJC_OK || ks > kMaxKsplit || (ks > 1 && kd / ks < 64)) continue;
+      if (any_staged && !compress_split_staged(pl, st, ks)) continue;
       cfg.cvar = v;
       cfg.ksplit = ks;
       float us = 0.f;
