@@ -290,5 +290,10 @@ def test_volume_full_size_properties(gpu_lib):
         rel = abs(lhs - rhs) / (np.linalg.norm(s) * np.linalg.norm(y))
         print(f"adjoint identity {rel:.2e}", flush=True)
         assert rel <= 1e-6
+    # the autotuned tiles: the 4.8 GB operand needs a split the staged forms can address
+    choice = comp.autotune("fp32")
+    print(f"autotuned {choice}", flush=True)
+    assert choice["ksplit"] >= 3
+    check(host(comp.forward(xd)), s_c)
     comp.close()
     full.close()
