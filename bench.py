@@ -422,6 +422,27 @@ def volume_bench(steps=3):
     for prec in ("fp32", "bf16"):
         res["uncompressed_fp32"][f"speedup_of_compressed_{prec}"] = \
             res["uncompressed_fp32"]["normal_ms"] / res[f"normal_ms_{prec}"]
+    # Against the roofline, from the stage-timed applications: the volume's
+    # rows (z, y) take the place of a slice's rows y in the work model.
+    import dataclasses
+    gv = dataclasses.replace(g, ny=g.ny * v.nz)
+    roof = {}
+    for stage in ("readout_fwd", "group_compress", "group_expand", "readout_adj"):
+        ms = res["stages_ms_fp32"].get(stage)
+        bound, work, unit = stage_work(gv, stage, "fp32")
+        if ms:
+            rate = work / (ms * 1e-3) / (1e12 if unit == "flop" else 1e9)
+            peak = PEAKS["fp32"] / 1e12 if bound == "mfma" else PEAKS["hbm"] / 1e9
+            roof[stage] = {"bound": bound, "achieved": rate, "peak": peak,
+                           "unit": "TFLOP/s" if unit == "flop" else "GB/s", "frac": rate / peak}
+    w_bytes = 8.0 * g.nc * g.ny * v.nz * g.nt
+    ms = res["uncompressed_fp32"]["stages_ms"].get("pe_cols")
+    if ms:
+        roof["uncompressed_pe_cols"] = {
+            "bound": "hbm", "passes": 3, "moved_GB": 3 * 2 * w_bytes / 1e9, "algorithmic_GB": 2 * w_bytes / 1e9,
+            "achieved_moved": 3 * 2 * w_bytes / (ms * 1e-3) / 1e9, "achieved": 2 * w_bytes / (ms * 1e-3) / 1e9,
+            "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s", "frac": 2 * w_bytes / (ms * 1e-3) / PEAKS["hbm"]}
+    res["roofline"] = roof
     log(f"3D volume, uncompressed: E^H E {res['uncompressed_fp32']['normal_ms']:.2f} ms")
     return res
 
