@@ -126,13 +126,14 @@ __global__ __launch_bounds__(256) void k_explicit_fwd(const float2* __restrict__
 // column y sit in LDS, where the row groups of a wave read the same pairs.
 // Each row's sums are reduced over its G lanes in a fixed butterfly order: the
 // cross-lane work per row is log2(G) steps instead of the six of a whole-wave
-// reduction, for 2 BC values each.
-template <int BC, int G>
+// reduction, for 2 BC values each.  A lane takes RPL rows RW apart at once, so
+// each image value it reads from LDS serves RPL rows.
+template <int BC, int G, int RPL>
 __global__ __launch_bounds__(256) void k_explicit_fwd_g(const float2* __restrict__ Ec, const float2* __restrict__ img,
                                                         int b0, int B, int nx, int ny, int rows, int rpw,
                                                         float2* __restrict__ Z) {
   extern __shared__ floatx4 xs[];  // [BC][nx / 2] pairs of image values
-  constexpr int RW = 64 / G;       // rows per wave and step
+  constexpr int RW = 64 / G;       // rows per wave and step for each of a lane's RPL rows
   const int y = blockIdx.y, r_beg = blockIdx.x * rpw, r_end = min(rows, r_beg + rpw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane % G, rl = lane / G;
@@ -143,34 +144,50 @@ __global__ __launch_bounds__(256) void k_explicit_fwd_g(const float2* __restrict
                        : floatx4{0.f, 0.f, 0.f, 0.f};
   }
   __syncthreads();
-  for (int r0 = r_beg + wave * RW; r0 < r_end; r0 += 4 * RW) {
-    const int r = r0 + rl;
-    // rows past the end read the last row and are not written
-    const floatx4* er = reinterpret_cast<const floatx4*>(Ec + ((size_t)y * rows + min(r, r_end - 1)) * nx);
-    float ar[BC], ai[BC];
+  for (int r0 = r_beg + wave * RW * RPL; r0 < r_end; r0 += 4 * RW * RPL) {
+    // a lane's rows r0 + rl + j RW share every image value it reads from LDS
+    const floatx4* er[RPL];
 #pragma unroll
-    for (int b = 0; b < BC; ++b) ar[b] = ai[b] = 0.f;
-#pragma unroll 4
+    for (int j = 0; j < RPL; ++j)  // rows past the end read the last row and are not written
+      er[j] = reinterpret_cast<const floatx4*>(Ec + ((size_t)y * rows + min(r0 + rl + j * RW, r_end - 1)) * nx);
+    float ar[RPL][BC], ai[RPL][BC];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+#pragma unroll
+      for (int b = 0; b < BC; ++b) ar[j][b] = ai[j][b] = 0.f;
+#pragma unroll 2
     for (int q = g; q < npair; q += G) {
-      const floatx4 m = er[q];
+      floatx4 m[RPL];
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) m[j] = er[j][q];
 #pragma unroll
       for (int b = 0; b < BC; ++b) {
         const floatx4 v = xs[b * npair + q];
-        ar[b] += m[0] * v[0] - m[1] * v[1] + m[2] * v[2] - m[3] * v[3];
-        ai[b] += m[0] * v[1] + m[1] * v[0] + m[2] * v[3] + m[3] * v[2];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+          ar[j][b] += m[j][0] * v[0] - m[j][1] * v[1] + m[j][2] * v[2] - m[j][3] * v[3];
+          ai[j][b] += m[j][0] * v[1] + m[j][1] * v[0] + m[j][2] * v[3] + m[j][3] * v[2];
+        }
       }
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1)
 #pragma unroll
-      for (int b = 0; b < BC; ++b) {
-        ar[b] += __shfl_xor(ar[b], off, 64);
-        ai[b] += __shfl_xor(ai[b], off, 64);
-      }
-    if (g == 0 && r < r_end)
+      for (int j = 0; j < RPL; ++j)
 #pragma unroll
-      for (int b = 0; b < BC; ++b)
-        if (b0 + b < B) Z[((size_t)(b0 + b) * rows + r) * ny + y] = make_float2(ar[b], ai[b]);
+        for (int b = 0; b < BC; ++b) {
+          ar[j][b] += __shfl_xor(ar[j][b], off, 64);
+          ai[j][b] += __shfl_xor(ai[j][b], off, 64);
+        }
+    if (g == 0)
+#pragma unroll
+      for (int j = 0; j < RPL; ++j) {
+        const int r = r0 + rl + j * RW;
+        if (r < r_end)
+#pragma unroll
+          for (int b = 0; b < BC; ++b)
+            if (b0 + b < B) Z[((size_t)(b0 + b) * rows + r) * ny + y] = make_float2(ar[j][b], ai[j][b]);
+      }
   }
 }
 
@@ -347,6 +364,7 @@ void launch_fwd_bc(const Plan& pl, const float2* img, int b0, int xb, dim3 grid,
 constexpr int kFwdRowsPerWg = 64;
 constexpr int kFwdRowsPerWgMulti = 256;
 constexpr int kFwdLanesPerRow = 8;
+constexpr int kFwdRowsPerLane = 2;  // rows a lane of the grouped forward takes together
 
 int explicit_chunks(int rows, int ny, int B) {
   const int bp = (B + 7) / 8;
@@ -379,11 +397,13 @@ int launch_explicit_fwd(const Plan& pl, const float2* img) {
     } else if (left == 2) {
       launch_fwd_bc<2>(pl, img, b0, xb, grid, kFwdRowsPerWg);
     } else if (left <= 4) {
-      hipLaunchKernelGGL((k_explicit_fwd_g<4, kFwdLanesPerRow>), grid_m, dim3(256), 4 * (pl.nx / 2) * sizeof(floatx4),
-                         pl.stream, pl.Ec, img, b0, pl.B, pl.nx, pl.ny, rows, kFwdRowsPerWgMulti, pl.Zp);
+      hipLaunchKernelGGL((k_explicit_fwd_g<4, kFwdLanesPerRow, kFwdRowsPerLane>), grid_m, dim3(256),
+                         4 * (pl.nx / 2) * sizeof(floatx4), pl.stream, pl.Ec, img, b0, pl.B, pl.nx, pl.ny, rows,
+                         kFwdRowsPerWgMulti, pl.Zp);
     } else {
-      hipLaunchKernelGGL((k_explicit_fwd_g<8, kFwdLanesPerRow>), grid_m, dim3(256), 8 * (pl.nx / 2) * sizeof(floatx4),
-                         pl.stream, pl.Ec, img, b0, pl.B, pl.nx, pl.ny, rows, kFwdRowsPerWgMulti, pl.Zp);
+      hipLaunchKernelGGL((k_explicit_fwd_g<8, kFwdLanesPerRow, kFwdRowsPerLane>), grid_m, dim3(256),
+                         8 * (pl.nx / 2) * sizeof(floatx4), pl.stream, pl.Ec, img, b0, pl.B, pl.nx, pl.ny, rows,
+                         kFwdRowsPerWgMulti, pl.Zp);
     }
   }
   GPJC_HIP(hipGetLastError());
